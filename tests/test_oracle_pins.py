@@ -1,0 +1,351 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the mathematics.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a transposed factor, a wrong level) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from workloads import (Domain, Workload, config_c1, config_table1, config_tiny, grid_levels,
+                       lattice_coords)
+from oracle.brute import Brute
+from oracle.ct import CTPreconditioner
+from oracle.fe import assemble
+from oracle.krylov import fgmres
+from oracle.mesh import Lattice, embedding
+from oracle.operator import Problem
+from oracle import strip
+from oracle.timedg import time_matrices
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.strip() and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+# --- T1: Table 1 dof column ---------------------------------------------------------
+
+def test_table1_dof_column_counts():
+    """dim V_L = sum over upper n_x n_v - sum over lower n_x n_v reproduces all 31 entries."""
+    for d, r, Lp, dof in _read("table1_dof.txt"):
+        d, r, Lp, dof = int(d), int(r), int(Lp), int(dof)
+        # periodic, 4 cells at paper level 1; order-r elements have r*cells nodes per axis
+        n = lambda lp: (r * 4 * 2 ** (lp - 1)) ** d
+        up = sum(n(l1) * n(Lp + 1 - l1) for l1 in range(1, Lp + 1))
+        lo = sum(n(l1) * n(Lp - l1) for l1 in range(1, Lp))
+        assert up - lo == dof, (d, r, Lp)
+
+
+@pytest.mark.parametrize("d,Lp", [(1, 1), (1, 2), (1, 3), (1, 4), (2, 1), (2, 2)])
+def test_table1_dof_equals_rank_of_spanning_set(d, Lp):
+    """The rank of the sparse-grid mass matrix (Gram matrix of the spanning set) is dim V_L."""
+    x = Domain(d, (0.0,) * d, (1.0,) * d, periodic=True)
+    w = Workload(name="t", x=x, v=x, lmin=2, L=Lp + 1, r=0, dt=1.0, delta=0.0, nstrips=1,
+                 beta=[None] * (2 * d), sigma=[], xfields={}, vfields={})
+    P = Problem(w)
+    M = P.assembled(P.mass_terms()).toarray()
+    rank = np.linalg.matrix_rank(M, tol=1e-10 * np.abs(M).max())
+    expect = {int(a[2]): int(a[3]) for a in _read("table1_dof.txt") if int(a[0]) == d and int(a[1]) == 1}
+    assert rank == expect[Lp]
+
+
+# --- T2/T3: factor matrices ---------------------------------------------------------
+
+def test_1d_closed_forms():
+    lat = Lattice(1, (0.0,), (2.0,), 4)
+    h = 2.0 / 16
+    xs = lattice_coords(Domain(1, (0.0,), (2.0,)), 4)[:, 0]
+    M = assemble(lat, "mass", []).toarray()
+    D = assemble(lat, "deriv", [], a=0).toarray()
+    S = assemble(lat, "stiff", [], a=0, b=0).toarray()
+    Mv = assemble(lat, "mass", [xs]).toarray()
+    k = 7
+    assert np.allclose(M[k, k - 1:k + 2], h * np.array([1 / 6, 2 / 3, 1 / 6]), atol=1e-15)
+    assert np.allclose(D[k, k - 1:k + 2], [-0.5, 0.0, 0.5], atol=1e-15)
+    assert np.allclose(S[k, k - 1:k + 2], np.array([-1.0, 2.0, -1.0]) / h, atol=1e-12)
+    assert math.isclose(Mv[k, k], 2 * h * xs[k] / 3, rel_tol=1e-13)
+    assert math.isclose(Mv[k, k + 1], h * (xs[k] + xs[k + 1]) / 12, rel_tol=1e-13)
+    # boundary rows: half mass, one-sided derivative
+    assert np.allclose(M[0, :2], h * np.array([1 / 3, 1 / 6]))
+    assert np.allclose(D[0, :2], [-0.5, 0.5])
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_factor_identities(d):
+    lo, hi = (-1.0,) * d, (1.0,) * d
+    fine = Lattice(d, lo, hi, 2)
+    coarse = Lattice(d, lo, hi, 1)
+    one = np.ones(fine.n)
+    M = assemble(fine, "mass", [])
+    assert math.isclose(one @ M @ one, 2.0 ** d, rel_tol=1e-13)
+    for a in range(d):
+        assert np.abs(assemble(fine, "deriv", [], a=a) @ one).max() < 1e-13
+        for b in range(d):
+            S = assemble(fine, "stiff", [], a=a, b=b)
+            assert np.abs(S @ one).max() < 1e-12
+            assert np.abs((S.T - assemble(fine, "stiff", [], a=b, b=a))).max() < 1e-13
+    E = embedding(coarse, fine)
+    assert np.allclose(E @ np.ones(coarse.n), 1.0)
+    # Galerkin identity E^T X_fine E = X_coarse for polynomial weights (Sect. 4.2)
+    Xf = lattice_coords(Domain(d, lo, hi), 2)
+    Xc = lattice_coords(Domain(d, lo, hi), 1)
+    for kind, kw in (("mass", {}), ("deriv", {"a": d - 1}), ("stiff", {"a": 0, "b": d - 1})):
+        wf = [Xf[:, 0], Xf[:, d - 1]]
+        wc = [Xc[:, 0], Xc[:, d - 1]]
+        lhs = (E.T @ assemble(fine, kind, wf, **kw) @ E).toarray()
+        rhs = assemble(coarse, kind, wc, **kw).toarray()
+        assert np.abs(lhs - rhs).max() < 1e-13
+    if d > 1:
+        F = assemble(fine, "face", [], face=(0, 1))
+        assert math.isclose(one @ F @ one, 2.0 ** (d - 1), rel_tol=1e-13)
+
+
+def test_prolongation_reproduces_linear_functions():
+    dom = Domain(2, (0.0, -1.0), (1.0, 3.0))
+    for l in range(0, 3):
+        c = Lattice(2, dom.lo, dom.hi, l)
+        f = Lattice(2, dom.lo, dom.hi, l + 1)
+        Xc, Xf = c.node_coords(), f.node_coords()
+        lin = lambda X: 0.3 + 2 * X[:, 0] - 0.7 * X[:, 1]
+        assert np.allclose(embedding(c, f) @ lin(Xc), lin(Xf), atol=1e-13)
+
+
+# --- time-DG blocks ------------------------------------------------------------------
+
+def test_time_matrices_closed_forms():
+    dt = 0.3
+    Mt, Tt, Ct, Gt = time_matrices(0, dt)
+    assert np.allclose(Mt, [[dt]]) and np.allclose(Tt, 0) and np.allclose(Ct, 0) and np.allclose(Gt, 1)
+    Mt, Tt, Ct, Gt = time_matrices(1, dt)
+    assert np.allclose(Mt, np.diag([dt, dt / 3]))
+    assert np.allclose(Tt, [[0, 2], [0, 0]])
+    assert np.allclose(Ct, [[0, 0], [0, 4 / dt]])
+    assert np.allclose(Gt, [[1, -1], [-1, 1]])
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_pade_reaction_step(r):
+    """beta=0, delta=0, sigma=c: each strip maps U to R(c dt) U with the (r, r+1) Pade
+    approximant of exp(-z) -- the classical DG(r) time-stepping property."""
+    sig, dt = 0.7, 0.25
+    x = Domain(1, (0.0,), (1.0,))
+    v = Domain(1, (-1.0,), (1.0,))
+    w = Workload(name="pade", x=x, v=v, lmin=1, L=3, r=r, dt=dt, delta=0.0, nstrips=2,
+                 beta=[None, None], sigma=[(sig, (), ())], xfields={}, vfields={},
+                 u0=lambda X, V: np.cos(3 * X[..., 0]) + V[..., 0] ** 2)
+    P = Problem(w)
+    sols, st = strip.march(P, tol=1e-13)
+    z = sig * dt
+    Rz = 1 / (1 + z) if r == 0 else (1 - z / 3) / (1 + 2 * z / 3 + z * z / 6)
+    prev = strip.initial_coefficients(P)
+    for u in sols:
+        tr = strip.trace_right(P, u, P.R)
+        e = tr - Rz * prev
+        # squared L2 norm of the difference function (the coefficients are not unique)
+        assert abs(e @ P.apply_mass(e)) < 1e-14 * (tr @ P.apply_mass(tr))
+        prev = tr
+
+
+# --- T4: brute force (weak form by quadrature) vs Kronecker form ---------------------
+
+@pytest.mark.parametrize("kind", ["d1", "d1p", "d2"])
+def test_brute_force_equals_kronecker(kind):
+    w = config_tiny(kind)
+    A2 = Problem(w).assembled().toarray()
+    A1 = Brute(w).matrix()
+    assert np.abs(A1 - A2).max() <= 1e-12 * np.abs(A1).max()
+
+
+@pytest.mark.slow
+def test_brute_force_equals_kronecker_d3():
+    w = config_tiny("d3")
+    A2 = Problem(w).assembled().toarray()
+    A1 = Brute(w, nq_x=3, nq_v=4).matrix()
+    assert np.abs(A1 - A2).max() <= 1e-12 * np.abs(A1).max()
+
+
+def test_blockwise_order_equals_assembled():
+    for kind in ("d1", "d2"):
+        P = Problem(config_tiny(kind))
+        u = np.random.default_rng(1).standard_normal(P.ndof)
+        assert np.abs(P.apply(u) - P.assembled() @ u).max() < 1e-13
+
+
+# --- T6/T7/T8: properties of the full operator ----------------------------------------
+
+@pytest.mark.parametrize("kind", ["d1", "d2"])
+def test_kernel_vectors(kind):
+    """+E c on one upper grid and -E' c on its neighbour represent the zero function."""
+    P = Problem(config_tiny(kind))
+    rng = np.random.default_rng(2)
+    for i in range(len(P.upper) - 1):
+        (lx, lv), (lx2, lv2) = P.upper[i], P.upper[i + 1]
+        low = (lx, lv - 1)
+        c = rng.standard_normal((P.R, P.nx(low[0]), P.nv(low[1])))
+        z = [np.zeros((P.R, P.nx(a), P.nv(b))) for a, b in P.upper]
+        Ev = P.E("v", lv, lv - 1)
+        Ex = P.E("x", lx2, lx)
+        z[i] = np.stack([(Ev @ cs.T).T for cs in c])
+        z[i + 1] = -np.stack([Ex @ cs for cs in c])
+        z = np.concatenate([a.ravel() for a in z])
+        Az = P.apply(z)
+        assert np.abs(Az).max() < 1e-13 * max(1.0, np.abs(P.apply(np.abs(z))).max())
+
+
+def test_constants_consistency():
+    for kind in ("d1", "d2"):
+        P = Problem(config_tiny(kind))
+        u = np.random.default_rng(3).standard_normal(P.ndof)
+        blocks = P.split(P.apply(u))
+        sums = np.array([b.reshape(P.R, -1).sum(axis=1) for b in blocks])
+        assert np.abs(sums - sums[0]).max() < 1e-12 * np.abs(sums).max()
+
+
+@pytest.mark.parametrize("w", [config_table1(2), config_tiny("d1"), config_tiny("d1p")],
+                         ids=["table1", "tiny_d1", "tiny_d1p"])
+def test_symmetric_part_psd(w):
+    """Lemma 1: A(v,v) >= 1/2 |||v|||^2 >= 0, so (A + A^T)/2 is positive semi-definite."""
+    A = Problem(w).assembled().toarray()
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert ev.min() > -1e-12 * np.abs(ev).max()
+
+
+# --- T9: mass balance -------------------------------------------------------------------
+
+def test_mass_conservation_periodic_x():
+    """sigma=0, f=0, x periodic and beta_v=0: (U_j^-, 1) is conserved strip by strip."""
+    x = Domain(1, (0.0,), (1.0,), periodic=True)
+    v = Domain(1, (-1.0,), (1.0,))
+    w = Workload(name="mass", x=x, v=v, lmin=1, L=4, r=1, dt=0.05, delta=0.03, nstrips=3,
+                 beta=[(1.0, (), ("v0",)), None], sigma=[], xfields={},
+                 vfields={"v0": lambda P: P[:, 0].copy()},
+                 u0=lambda X, V: (1 + np.sin(2 * np.pi * X[..., 0])) * np.exp(-3 * V[..., 0] ** 2))
+    P = Problem(w)
+    sols, _ = strip.march(P, tol=1e-13)
+    n0 = P.nx(P.upper[0][0]) * P.nv(P.upper[0][1])
+
+    def mass(u1):
+        return P.apply_mass(u1)[:n0].sum()
+
+    m0 = mass(strip.initial_coefficients(P))
+    for u in sols:
+        assert abs(mass(strip.trace_right(P, u, P.R)) - m0) < 1e-11 * abs(m0)
+
+
+def test_mass_decay_with_reaction():
+    """sigma const, beta=(v, 0) periodic in x: d/dt (U,1) = -sigma (U,1) holds weakly:
+    (U_j^-,1) - (U_{j-1}^-,1) = -sigma int_{I_j} (U,1) dt."""
+    sig = 0.4
+    x = Domain(1, (0.0,), (1.0,), periodic=True)
+    v = Domain(1, (-1.0,), (1.0,))
+    w = Workload(name="mass2", x=x, v=v, lmin=1, L=4, r=1, dt=0.1, delta=0.02, nstrips=2,
+                 beta=[(1.0, (), ("v0",)), None], sigma=[(sig, (), ())], xfields={},
+                 vfields={"v0": lambda P: P[:, 0].copy()},
+                 u0=lambda X, V: (1 + np.cos(2 * np.pi * X[..., 0])) * (1 - V[..., 0] ** 2))
+    P = Problem(w)
+    sols, _ = strip.march(P, tol=1e-13)
+    n0 = P.nx(P.upper[0][0]) * P.nv(P.upper[0][1])
+    mass = lambda u1: P.apply_mass(u1)[:n0].sum()
+    prev = mass(strip.initial_coefficients(P))
+    for u in sols:
+        blk = P.split(u)
+        # int_{I_j} (U,1) dt = dt * (U_0 coefficient, 1) since int eta_1 = 0
+        u0part = np.concatenate([b[0].ravel() for b in blk])
+        integral = w.dt * mass(u0part)
+        now = mass(strip.trace_right(P, u, P.R))
+        assert abs((now - prev) + sig * integral) < 1e-11
+        prev = now
+
+
+# --- T12 and Krylov -------------------------------------------------------------------------
+
+def test_ct_single_grid_is_exact_inverse():
+    w = config_tiny("d1")
+    w.L = w.lmin                      # one upper grid, no lower grid
+    P = Problem(w)
+    b = np.random.default_rng(4).standard_normal(P.ndof)
+    x, st = fgmres(P.apply, b, CTPreconditioner(P), tol=1e-12)
+    assert st["iters"] == 1 and st["rel"] < 1e-12
+
+
+def test_ct_linear_and_interpolation_exact():
+    P = Problem(config_tiny("d2"))
+    ct = CTPreconditioner(P)
+    rng = np.random.default_rng(5)
+    r1, r2 = rng.standard_normal(P.ndof), rng.standard_normal(P.ndof)
+    assert np.abs(ct(2 * r1 - 3 * r2) - (2 * ct(r1) - 3 * ct(r2))).max() < 1e-10
+    # the combination formula reproduces any function of V_L: take a hat product on grid (1,1)
+    g = P.upper[1]
+    Xc = lattice_coords(P.w.x, g[0])
+    Vc = lattice_coords(P.w.v, g[1])
+    kx, kv = 4, 3
+    latx = Lattice(2, P.w.x.lo, P.w.x.hi, g[0])
+    latv = Lattice(2, P.w.v.lo, P.w.v.hi, g[1])
+
+    def hat(X, V):
+        sh = X.shape[:-1]
+        Xf = np.broadcast_to(X, np.broadcast_shapes(X.shape, V.shape[:-1] + (2,))).reshape(-1, 2)
+        Vf = np.broadcast_to(V, np.broadcast_shapes(V.shape, X.shape[:-1] + (2,))).reshape(-1, 2)
+        a = latx.eval(Xf)[0][:, kx].toarray().ravel()
+        b = latv.eval(Vf)[0][:, kv].toarray().ravel()
+        return (a * b).reshape(np.broadcast_shapes(X.shape[:-1], V.shape[:-1]))
+
+    ui = strip.interpolate(P, hat)
+    ref = np.zeros(P.ndof // P.R)
+    off = sum(P.nx(a) * P.nv(b) for a, b in P.upper[:1])
+    ref[off + kx * P.nv(g[1]) + kv] = 1.0
+    e = ui - ref
+    assert e @ P.apply_mass(e) < 1e-26
+
+
+def test_fgmres_solves_nonsingular_system():
+    rng = np.random.default_rng(6)
+    A = np.eye(40) * 3 + rng.standard_normal((40, 40)) * 0.3
+    b = rng.standard_normal(40)
+    x, st = fgmres(lambda v: A @ v, b, tol=1e-13, restart=10)
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-10)
+
+
+# --- T10/T11: exact solutions and the paper's convergence table ----------------------------
+
+def test_c1_exact_solution_error_small():
+    w = config_c1()
+    w.noise = 0.0
+    P = Problem(w)
+    sols, st = strip.march(P, tol=1e-10)
+    assert all(s["rel"] <= 1e-10 for s in st)
+    T = w.nstrips * w.dt
+    e = strip.trace_right(P, sols[-1], P.R) - strip.interpolate(P, lambda X, V: w.exact(T, X, V))
+    ex = strip.interpolate(P, lambda X, V: w.exact(T, X, V))
+    assert np.sqrt(e @ P.apply_mass(e)) < 0.02 * np.sqrt(ex @ P.apply_mass(ex))
+
+
+def test_table1_d1_r1_convergence():
+    """Table 1, d=1, r=1: SD-norm errors and orders of the periodic advection test.
+
+    The paper compares with an order-(r+1) interpolant of u in V_{L+1}; the oracle
+    compares with u itself, so values are pinned to 12% and orders to 0.05 (for the
+    asymptotic levels L >= 3).  Exact digits: parity unpinned.
+    """
+    from oracle.norms import sd_error_periodic
+    table = {int(r[0]): (float(r[2]), float(r[3])) for r in _read("table1_d1_r1_errors.txt")}
+    errs = {}
+    for Lp in range(1, 6):
+        w = config_table1(Lp)
+        P = Problem(w)
+        sols, st = strip.march(P, tol=1e-12)
+        assert all(s["rel"] <= 1e-12 for s in st)
+        errs[Lp] = sd_error_periodic(P, None, sols, w.exact)
+        assert abs(errs[Lp] / table[Lp][0] - 1) < 0.12, (Lp, errs[Lp])
+    for Lp in range(3, 6):
+        order = np.log2(errs[Lp - 1] / errs[Lp])
+        assert abs(order - table[Lp][1]) < 0.05, (Lp, order)
