@@ -1,0 +1,247 @@
+/*
+ * sgdg.h -- C ABI of libsgdg: the sparse-grid time-discontinuous Galerkin
+ * streamline-diffusion method for phase-space transport, on AMD MI355X (gfx950).
+ *
+ * Problem (Sect. 1, (eq:transport)/(eq:inflow)):
+ *     d_t u + beta(x,v) . grad_(x,v) u + sigma(x,v) u = f   in (0,T) x Omega_x x Omega_v,
+ *     u(0) = u0,   u = g on the inflow boundary {beta . n < 0}.
+ * Discretisation (Sect. 2): nested P1 spaces V_l on each box (2^l cells per
+ * axis, Kuhn simplices), the sparse space V_L = sum over |l|_1 = L + lmin of
+ * V^x_{lx} (x) V^v_{lv}, discontinuous polynomials of degree r in time, and the
+ * streamline-diffusion weak form (eq:weak_form_j) on each time strip.
+ *
+ * Data layout (every vector argument, host or device):
+ *   a sparse-grid function of one strip is stored by its spanning-set
+ *   coefficients (eq:spanningset): one block per upper-diagonal component
+ *   grid (lx, lv), lx + lv = level_max + level_min, blocks in increasing lx;
+ *   each block is a row-major [R][n_x][n_v] array, R = r + 1 time slices
+ *   (Legendre basis on the strip), v index fastest.  Inside a domain, nodes
+ *   are numbered in C order over the axis indices (last axis fastest).
+ *   A batch of B vectors is [B][n_dof], contiguous.
+ *   "Nodal" arrays (data sampled at grid nodes) use the same per-grid
+ *   [n_x][n_v] blocks, upper-diagonal grids first, then the lower-diagonal
+ *   grids (lx + lv = level_max + level_min - 1, increasing lx).
+ *
+ * Ownership: sgdg_grid and sgdg_ops are created by the library and released
+ * with the matching *_destroy.  Host arrays passed in are copied during the
+ * call.  Device buffers (suffix _dev) are owned by the caller, must hold the
+ * stated number of elements of the stated type and stay valid until the
+ * stream has executed the call; the library never frees them.  Internal
+ * workspace (Krylov bases, scan arrays) belongs to the sgdg_ops handle.
+ *
+ * Errors: every entry point returns an sgdg_status; no exception crosses the
+ * ABI.  Arguments are validated before any device work is queued
+ * (SGDG_E_ARG).  sgdg_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.
+ *
+ * Streams: apply / combine / precondition / rhs are queued on the given
+ * stream and return without synchronising.  solve_strip synchronises the
+ * stream before it returns its statistics.  An sgdg_ops handle must not be
+ * used from two threads at once, nor on two streams concurrently.
+ */
+#ifndef SGDG_H
+#define SGDG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGDG_OK = 0,
+  SGDG_E_ARG = -1,        /* invalid argument or shape */
+  SGDG_E_ALLOC = -2,      /* device or host allocation failed */
+  SGDG_E_HIP = -3,        /* a HIP runtime call failed */
+  SGDG_E_NOCONV = -4,     /* iteration limit reached before the tolerance */
+  SGDG_E_BREAKDOWN = -5,  /* Krylov breakdown before the tolerance */
+  SGDG_E_NAN = -6,        /* NaN/Inf in a residual norm */
+  SGDG_E_STATE = -7       /* handle not in a usable state */
+} sgdg_status;
+
+typedef enum { SGDG_F64 = 0, SGDG_F32 = 1 } sgdg_dtype;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* sgdg_last_error(void);
+
+/* ---------------------------------------------------------------- layout -- */
+
+/* One box domain, Omega^(1) (x) or Omega^(2) (v), Sect. 2.  dim in 1..3;
+ * all axes share the periodic flag. */
+typedef struct {
+  int dim;
+  double lo[3], hi[3];
+  int periodic;
+} sgdg_domain;
+
+typedef struct sgdg_grid_s* sgdg_grid;
+
+/* Builds the component-grid layout of V_L, (eq:sg_space) with level numbering
+ * level_min..level_max on both domains (paper level 1 <-> level_min).
+ * time_degree r in 0..2.  Fails with SGDG_E_ARG on dims that differ, dim
+ * outside 1..3, level_min > level_max, level_max > 12, lo >= hi. */
+sgdg_status sgdg_build_sparse_grid(const sgdg_domain* x, const sgdg_domain* v, int level_min,
+                                   int level_max, int time_degree, sgdg_grid* out);
+
+/* Component grids of one diagonal: which = 0 upper (the spanning set), 1 lower
+ * (combination technique).  Every output pointer may be NULL; arrays must hold
+ * n_comp entries (query n_comp first with the others NULL).  offset[i] is the
+ * start of grid i in a one-slice nodal array of that diagonal; n_dof is
+ * R * sum(nx*nv) for the upper diagonal and sum(nx*nv) for the lower one. */
+sgdg_status sgdg_grid_info(sgdg_grid g, int which, int* n_comp, int64_t* n_dof, int* lx, int* lv,
+                           int64_t* nx, int64_t* nv, int64_t* offset);
+void sgdg_grid_destroy(sgdg_grid g);
+
+/* ----------------------------------------------------------- coefficients -- */
+
+/* scale * prod_i xf[i](x) * prod_j vf[j](v), each factor a P1 field given by
+ * its values at the nodes of the finest level of its domain (host arrays,
+ * copied).  This is the separable form of Sect. 4.2. */
+typedef struct {
+  double scale;
+  int n_xf;
+  const double* const* xf;
+  int n_vf;
+  const double* const* vf;
+} sgdg_separable;
+
+/* beta[c], c = 0..2*dim-1 (x components, then v components), NULL for a zero
+ * component; sigma = sum of n_sigma separable terms.  dt is the strip length,
+ * delta the streamline-diffusion parameter (delta > 0, delta < 1/sigma). */
+typedef struct {
+  const sgdg_separable* beta[6];
+  int n_sigma;
+  const sgdg_separable* sigma;
+  double dt;
+  double delta;
+} sgdg_problem;
+
+typedef struct sgdg_ops_s* sgdg_ops;
+
+/* Assembles every factor matrix of the strip operator (eq:matrices) on the
+ * finest level of each domain by exact integration, restricts it to all
+ * coarser levels with the embedding matrices (Sect. 4.2,
+ * X_{l,l'} = E_{L,l}^T X_{L,L} E_{L,l'}), builds the Kronecker term lists and
+ * uploads everything to the current HIP device.  The inflow weight on a face
+ * with normal velocity s*a(x)*b(v) is split exactly into (s a)^+ b^- + (s a)^- b^+
+ * (each factor the P1 interpolant of the kinked nodal values); such a face
+ * needs beta's component to be one separable term (it is by construction).
+ * The grid must outlive the ops handle. */
+sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out);
+void sgdg_ops_destroy(sgdg_ops o);
+
+/* -------------------------------------------------------------- operators -- */
+
+typedef enum {
+  SGDG_OP_FULL = 0,      /* A^(delta) of (eq:Adelta), all blocks A_{l,l'}; R -> R slices */
+  SGDG_OP_BLOCKDIAG = 1, /* only the diagonal blocks A_{l,l} (the grid problems (eq:Adeltall)) */
+  SGDG_OP_MASS = 2,      /* (phi', phi) over the spanning set, one slice -> one slice */
+  SGDG_OP_DATA_F = 3,    /* f |-> int (f, w + delta(d_t w + d_beta w)), R -> R */
+  SGDG_OP_DATA_G = 4     /* g |-> int over the inflow boundary of |beta.n| g w, R -> R */
+} sgdg_opkind;
+
+/* y_dev = Op u_dev for a batch of vectors (Sect. 4.2, blockwise application
+ * [A u]_l = sum_l' A_{l,l'} u_l').  u_dev, y_dev: device arrays of batch *
+ * n_in / batch * n_out elements of type t (n_in = n_out = n_dof, or n_dof/R for
+ * SGDG_OP_MASS).  u_dev and y_dev must not overlap.  batch >= 1. */
+sgdg_status sgdg_apply_operator(sgdg_ops o, int kind, const void* u_dev, void* y_dev, sgdg_dtype t,
+                                int batch, hipStream_t s);
+
+/* Combination formula: spanning coefficients of sum_upper f_l - sum_lower f_l
+ * from nodal values on both diagonals (Algorithm 1's combination step; exact
+ * for interpolation, Sect. 4.3).  nodal_dev: device FP64 [nslices][all upper
+ * nodes + all lower nodes]; coef_dev: device FP64 [grid][nslices][n_x][n_v]. */
+sgdg_status sgdg_combine(sgdg_ops o, const double* nodal_dev, double* coef_dev, int nslices,
+                         hipStream_t s);
+
+/* ------------------------------------------------------- preconditioners -- */
+
+typedef struct {
+  int kind;             /* 0 = combination technique (Algorithm 1's body) */
+  double inner_rtol;    /* relative residual of each grid problem (eq:Adeltall) */
+  int inner_maxit;      /* iteration cap per grid problem */
+  int inner_restart;    /* GMRES restart length of the grid problems */
+  int mass_sweeps;      /* Chebyshev-Jacobi steps approximating each mass inverse (0 = Jacobi) */
+} sgdg_precond_opts;
+
+/* z_dev = P_CT r_dev (one vector, batch must be 1 in this version).
+ * Restricts the residual to the lower diagonal, solves every grid problem
+ * A_{l,l} dU_l = r_l by GMRES right-preconditioned with the inverse of
+ * (Tt + delta Ct + Gt) (x) M^x (x) M^v (Sect. 4.3), and combines.  t = F64 runs
+ * everything in FP64, t = F32 converts r to FP32 and runs the grid problems in
+ * FP32 (z returned in the dtype t).  Grid problems that reach inner_maxit are
+ * left at their best iterate (not an error). */
+sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_dev, sgdg_dtype t, int batch,
+                              const sgdg_precond_opts* po, hipStream_t s);
+
+/* --------------------------------------------------------- strip solves -- */
+
+/* Right-hand side b_j of (eq:weak_form_j) into b_dev (FP64, n_dof):
+ *   jump term (U_{j-1}^-, w_{j-1}^+) from u_prev_dev (FP64, prev_slices slices
+ *   per grid, the previous strip's solution, or prev_slices = 1 for U_0^-),
+ *   plus the data functionals of f and g given as nodal values at the r+2
+ *   Gauss-Legendre points of the strip: f_nodal_dev / g_nodal_dev are device
+ *   FP64 [r+2][all upper nodes + all lower nodes] or NULL (zero data).  The data
+ *   are projected onto P^r in time and interpolated on the sparse grid before
+ *   the functionals are applied, so b lies in the range of A^(delta). */
+sgdg_status sgdg_rhs(sgdg_ops o, const double* u_prev_dev, int prev_slices, const double* f_nodal_dev,
+                     const double* g_nodal_dev, double* b_dev, hipStream_t s);
+
+typedef struct {
+  double rtol;          /* stop when ||b - A u||_2 <= rtol ||b||_2 (FP64) */
+  int restart;          /* FGMRES restart length (<= 64) */
+  int maxit;            /* total FGMRES iterations */
+  int mixed_precision;  /* 1: FP64 refinement around an FP32 inner FGMRES (FP32 applies + FP32 CT) */
+  double inner_outer_rtol; /* mixed precision: tolerance of each FP32 correction solve */
+  sgdg_precond_opts pc;
+} sgdg_solve_opts;
+
+typedef struct {
+  int outer_iters;        /* FGMRES iterations (summed over refinement steps) */
+  int refinement_steps;   /* mixed precision only */
+  int inner_iters_total;  /* grid-problem GMRES iterations summed over all calls */
+  double rel_residual;    /* final ||b - A u|| / ||b|| in FP64 */
+  double seconds;         /* wall time of the call */
+} sgdg_solve_stats;
+
+/* Solves A^(delta) u = b for one strip by flexible GMRES right-preconditioned
+ * with the combination technique (FP64 Arnoldi; in mixed precision FP64
+ * iterative refinement around FP32 corrections).  b_dev: FP64 n_dof; u_dev:
+ * FP64 n_dof, used as the initial guess and overwritten.  Returns SGDG_E_NOCONV
+ * (with u_dev holding the last iterate and st filled) if maxit is reached,
+ * SGDG_E_NAN if a residual norm is not finite.  Synchronises s. */
+sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
+                             sgdg_solve_stats* st, hipStream_t s);
+
+/* ------------------------------------------------------------ diagnostics -- */
+
+/* Event timing of the operator kernels (for roofline reports).  mode 1 resets
+ * the counters and records a HIP event pair on the call's stream around every
+ * subsequent launch group of the operator kernels; mode 0 stops recording. */
+sgdg_status sgdg_profile(sgdg_ops o, int mode);
+/* Accumulated time (ms) and launch-group count of one kernel class since the
+ * last reset: slot 0 = Kronecker sweeps (k_sweeps), 1 = level scans (all
+ * steps of one application, k_scan), 2 = term accumulation (k_final).
+ * Waits for the recorded events. */
+sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launches);
+/* Shape of one operator: Kronecker terms, distinct v- and x-factors, stencil
+ * sizes of the two domains and the time slices in/out. */
+sgdg_status sgdg_op_info(sgdg_ops o, int kind, int* nterms, int* nvg, int* nxg, int* Sx, int* Sv, int* Rin,
+                         int* Rout);
+
+/* Host-only: dense block (row_grid, col_grid) of the operator `kind` (FULL,
+ * MASS, DATA_F or DATA_G; not BLOCKDIAG) assembled from the host factor
+ * tables, for small grids.  Grids are indices on the upper diagonal.  out:
+ * host array of (Rout*nx*nv) x (Rin*nx'*nv') doubles, row-major, rows in the
+ * [s][kx][kv] order of the row grid.  Touches no device.  Fails with
+ * SGDG_E_ARG on bad indices. */
+sgdg_status sgdg_debug_dense_block(const sgdg_domain* x, const sgdg_domain* v, int level_min, int level_max,
+                                   int time_degree, const sgdg_problem* p, int kind, int row_grid,
+                                   int col_grid, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGDG_H */

@@ -1,0 +1,173 @@
+// Internal declarations of libsgdg (host structures, device descriptors, kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sgdg.h"
+
+namespace sgdg {
+
+constexpr int kMaxS = 15;       // Kuhn stencil: 1 + 2 (2^d - 1) for d <= 3
+constexpr int kMaxR = 3;        // time slices (r <= 2)
+constexpr int kMaxGrids = 32;   // component grids in one launch
+constexpr int kMaxLevels = 13;  // levels 0..12
+
+// ------------------------------------------------------------------ errors --
+void set_error(const std::string& msg);
+struct Error {
+  sgdg_status code;
+  std::string msg;
+};
+#define SGDG_CHECK_HIP(call)                                                            \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::sgdg::Error{SGDG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ---------------------------------------------------------------- domains --
+struct Dom {
+  int d = 1;
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  bool periodic = false;
+  int axis_nodes(int l) const { return periodic ? (1 << l) : (1 << l) + 1; }
+  int64_t nodes(int l) const {
+    int64_t r = 1;
+    for (int a = 0; a < d; ++a) r *= axis_nodes(l);
+    return r;
+  }
+  double h(int l, int a) const { return (hi[a] - lo[a]) / double(1 << l); }
+};
+
+// Kuhn neighbourhood: offset 0 and +-b for every non-zero 0/1 vector b.
+struct Stencil {
+  int d = 0, S = 0;
+  int off[kMaxS][3] = {};
+  void init(int dim);
+  int slot(const int* o) const;  // -1 if o is not a stencil offset
+  int neg(int e) const;          // slot of -off[e]
+};
+
+// Index tables of one level of one domain (host copies).
+struct LevelTables {
+  int level = 0;
+  int m = 0;        // nodes per axis
+  int64_t n = 0;    // nodes
+  std::vector<int32_t> nbr;   // [n][S] neighbour node index (self if outside a non-periodic box)
+  std::vector<uint8_t> valid; // [n][S] 1 if the neighbour exists
+  std::vector<int32_t> par;   // [n][2] parents on level-1 (coarse node of the embedding E)
+  std::vector<double> parw;   // [n][2] weights (1,0) or (1/2,1/2)
+  std::vector<int32_t> chi;   // [n][S] children on level+1
+  std::vector<double> chiw;   // [n][S] weights (1 centre, 1/2 edge midpoints, 0 outside)
+};
+
+// A weight: scale * prod fields, optionally kinked (1: max(.,0), 2: max(-.,0)).
+struct Weight {
+  double scale = 1.0;
+  std::vector<int> fields;  // indices into the domain's field registry
+  int kink = 0;
+  bool operator<(const Weight& o) const;
+};
+
+enum FactorKind { kMass = 0, kDeriv = 1, kStiff = 2, kFace = 3 };
+
+struct FactorKey {
+  int kind = kMass;
+  int a = -1, b = -1;        // derivative directions
+  int axis = -1, side = -1;  // face
+  Weight w;
+  bool trans = false;
+  bool operator<(const FactorKey& o) const;
+};
+
+struct DomainData {
+  Dom dom;
+  Stencil st;
+  int lmin = 0, lmax = 0;
+  std::vector<LevelTables> lev;            // index level - lmin
+  std::vector<std::vector<double>> fields; // registry of nodal fields on the finest level
+  std::vector<const double*> field_src;    // caller pointers (identity for de-duplication)
+  std::vector<FactorKey> factors;          // registry of factors
+  std::vector<std::vector<std::vector<double>>> values;  // [factor][level-lmin][n*S]
+  int field_id(const double* src, int64_t n);
+  int factor_id(const FactorKey& k);
+  const LevelTables& L(int l) const { return lev[l - lmin]; }
+};
+
+// One Kronecker term  Tm (x) X (x) V  (Tm: Rout x Rin, row-major).
+struct Term {
+  double tm[kMaxR * kMaxR] = {};
+  int xf = -1, vf = -1;
+};
+
+struct TermList {
+  int Rin = 1, Rout = 1;
+  std::vector<Term> terms;
+};
+
+// Host-side construction (mesh.cpp, assembly.cpp, terms.cpp).
+void build_domain_tables(DomainData& D);
+void assemble_factor(DomainData& D, int fid);  // all levels of one factor
+struct ProblemIn {
+  const sgdg_problem* p;
+  int d, r;
+};
+// Builds the operator term lists: 0 FULL, 1 MASS, 2 DATA_F, 3 DATA_G. Registers factors.
+void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, TermList out[4]);
+void time_matrices(int r, double dt, double Mt[], double Tt[], double Ct[], double Gt[]);
+
+// ------------------------------------------------------ device descriptors --
+struct DevDomain {
+  int S = 0, lmin = 0, lmax = 0;
+  int64_t lev_off[kMaxLevels] = {};   // start of level l in the [n][S] tables (l - lmin)
+  int64_t par_off[kMaxLevels] = {};   // start of level l in the [n][2] parent tables
+  const int32_t* nbr = nullptr;
+  const int32_t* par = nullptr;
+  const double* parw = nullptr;
+  const int32_t* chi = nullptr;
+  const double* chiw = nullptr;
+  const double* vals = nullptr;       // [factor][level-major [n][S]] FP64
+  const float* vals32 = nullptr;      // same, FP32
+  int64_t fac_stride = 0;             // elements per factor
+  int mass_fac = -1;                  // plain mass factor (Jacobi / Chebyshev preconditioner)
+};
+
+struct DevGrids {
+  int n = 0, R = 1;
+  int lx[kMaxGrids] = {}, lv[kMaxGrids] = {};
+  int nx[kMaxGrids] = {}, nv[kMaxGrids] = {};
+  int64_t off[kMaxGrids + 1] = {};    // start of grid g's [R][nx][nv] block; off[n] = total
+};
+
+struct DevOp {
+  int Rin = 1, Rout = 1, nterms = 0, nvg = 0, nxg = 0;
+  const int* term_xf = nullptr;
+  const int* term_vf = nullptr;
+  const int* term_vg = nullptr;
+  const int* term_xg = nullptr;
+  const double* term_tm = nullptr;   // [nterms][Rout][Rin]
+  const float* term_tm32 = nullptr;
+  const int* vg_fac = nullptr;       // v factor of each V group
+  const int* xg_fac = nullptr;       // x factor of each X group
+};
+
+// Device buffer helper.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void alloc(size_t b);
+  void ensure(size_t b);  // grow-only
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace sgdg

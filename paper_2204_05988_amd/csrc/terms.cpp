@@ -1,0 +1,247 @@
+// Kronecker term lists of the strip operator (Sect. 4.2).
+//
+// For time-independent separable coefficients the block formula reads
+//   A = (Tt + delta Ct + Gt) (x) M  +  delta Tt (x) T^T  +  delta Tt^T (x) (T + K)
+//       + Mt (x) (T + delta C + K + delta K~ - G),
+// with the K~ term carrying delta (expanding (sigma v, delta d_beta w) from the
+// weak form (eq:weak_form_j)).  Spatial matrices (row = test phi, column =
+// trial phi'):
+//   M  = (phi', phi)                      -> M^x (x) M^v
+//   T  = (beta.grad phi', phi)            -> per component c: D_c[a] (x) M[b] or M[a] (x) D_c[b]
+//   C  = (beta.grad phi', beta.grad phi)  -> per pair (c, c'): stiffness / derivative products
+//   K  = (sigma phi', phi)                -> M[p] (x) M[q]
+//   K~ = (sigma phi', beta.grad phi)      -> transposed derivative factors
+//   -G = inflow integral of |beta.n| phi' phi; on a face with normal velocity
+//        s a(x) b(v):  (s a)^+ b^- + (s a)^- b^+ (each a P1 interpolant of kinked values).
+// Time blocks on a strip of length dt in the Legendre basis (closed forms):
+//   Mt = diag(dt/(2s+1)),  Tt[s][s'] = 2 if s' > s and s + s' odd,
+//   Ct[s][s'] = (2/dt) min(s,s')(min(s,s')+1) if s + s' even,  Gt[s][s'] = (-1)^(s+s').
+// The data functionals use  (f, w + delta(d_t w + d_beta w)) -> (Mt + delta Tt^T) (x) M + delta Mt (x) T^T
+// and  inflow |beta.n| g w -> Mt (x) (-G).
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+#include "sgdg_internal.h"
+
+namespace sgdg {
+
+void time_matrices(int r, double dt, double Mt[], double Tt[], double Ct[], double Gt[]) {
+  const int R = r + 1;
+  for (int s = 0; s < R; ++s)
+    for (int q = 0; q < R; ++q) {
+      const int i = s * R + q;
+      Mt[i] = s == q ? dt / (2 * s + 1) : 0.0;
+      Tt[i] = (q > s && ((s + q) & 1)) ? 2.0 : 0.0;
+      const int mn = std::min(s, q);
+      Ct[i] = ((s + q) & 1) ? 0.0 : (2.0 / dt) * mn * (mn + 1);
+      Gt[i] = ((s + q) & 1) ? -1.0 : 1.0;
+    }
+}
+
+namespace {
+
+struct KTerm {  // coef * X (x) V
+  double c;
+  FactorKey X, V;
+};
+
+Weight plain(DomainData& D, const sgdg_separable* sep, bool xside, int64_t n) {
+  Weight w;
+  w.scale = 1.0;
+  const int nf = xside ? sep->n_xf : sep->n_vf;
+  const double* const* f = xside ? sep->xf : sep->vf;
+  for (int i = 0; i < nf; ++i) w.fields.push_back(D.field_id(f[i], n));
+  std::sort(w.fields.begin(), w.fields.end());
+  return w;
+}
+
+Weight concat(const Weight& a, const Weight& b) {
+  Weight w;
+  w.scale = a.scale * b.scale;
+  w.fields = a.fields;
+  w.fields.insert(w.fields.end(), b.fields.begin(), b.fields.end());
+  std::sort(w.fields.begin(), w.fields.end());
+  return w;
+}
+
+FactorKey key(int kind, const Weight& w, int a = -1, int b = -1, int axis = -1, int side = -1) {
+  FactorKey k;
+  k.kind = kind;
+  k.w = w;
+  k.a = a;
+  k.b = b;
+  k.axis = axis;
+  k.side = side;
+  return k;
+}
+
+FactorKey tr(FactorKey k) {
+  // a transposed symmetric factor is the factor itself
+  if (k.kind == kMass || k.kind == kFace) return k;
+  if (k.kind == kStiff) {
+    std::swap(k.a, k.b);
+    return k;
+  }
+  k.trans = !k.trans;
+  return k;
+}
+
+bool weight_zero(const DomainData& D, const Weight& w) {
+  if (w.kink == 0) return w.scale == 0.0;
+  const int64_t n = D.L(D.lmax).n;
+  for (int64_t p = 0; p < n; ++p) {
+    double v = w.scale;
+    for (int f : w.fields) v *= D.fields[f][p];
+    if ((w.kink == 1 && v > 0) || (w.kink == 2 && v < 0)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, TermList out[4]) {
+  const int d = X.dom.d;
+  const int R = r + 1;
+  const int64_t nx = X.L(X.lmax).n, nv = V.L(V.lmax).n;
+  const double dl = p.delta;
+
+  std::vector<KTerm> M, T, C, K, Kt, Gm;
+  const Weight one;
+  M.push_back({1.0, key(kMass, one), key(kMass, one)});
+
+  std::vector<Weight> A(2 * d), B(2 * d);
+  std::vector<double> sc(2 * d, 0.0);
+  std::vector<bool> has(2 * d, false);
+  for (int c = 0; c < 2 * d; ++c) {
+    if (!p.beta[c]) continue;
+    has[c] = true;
+    sc[c] = p.beta[c]->scale;
+    A[c] = plain(X, p.beta[c], true, nx);
+    B[c] = plain(V, p.beta[c], false, nv);
+  }
+  for (int c = 0; c < 2 * d; ++c) {
+    if (!has[c]) continue;
+    if (c < d) T.push_back({sc[c], key(kDeriv, A[c], c), key(kMass, B[c])});
+    else T.push_back({sc[c], key(kMass, A[c]), key(kDeriv, B[c], c - d)});
+  }
+  for (int c = 0; c < 2 * d; ++c)
+    for (int c2 = 0; c2 < 2 * d; ++c2) {
+      if (!has[c] || !has[c2]) continue;
+      const Weight wa = concat(A[c], A[c2]), wb = concat(B[c], B[c2]);
+      // (beta_c d_c phi', beta_c2 d_c2 phi)
+      FactorKey fx, fv;
+      if (c < d && c2 < d) {
+        fx = key(kStiff, wa, c, c2);
+        fv = key(kMass, wb);
+      } else if (c < d) {
+        fx = key(kDeriv, wa, c);
+        fv = tr(key(kDeriv, wb, c2 - d));
+      } else if (c2 < d) {
+        fx = tr(key(kDeriv, wa, c2));
+        fv = key(kDeriv, wb, c - d);
+      } else {
+        fx = key(kMass, wa);
+        fv = key(kStiff, wb, c - d, c2 - d);
+      }
+      C.push_back({sc[c] * sc[c2], fx, fv});
+    }
+  for (int t = 0; t < p.n_sigma; ++t) {
+    const sgdg_separable* s = &p.sigma[t];
+    const Weight P = plain(X, s, true, nx), Q = plain(V, s, false, nv);
+    K.push_back({s->scale, key(kMass, P), key(kMass, Q)});
+    for (int c = 0; c < 2 * d; ++c) {
+      if (!has[c]) continue;
+      const Weight wa = concat(P, A[c]), wb = concat(Q, B[c]);
+      // (sigma phi', beta_c d_c phi)
+      if (c < d) Kt.push_back({s->scale * sc[c], tr(key(kDeriv, wa, c)), key(kMass, wb)});
+      else Kt.push_back({s->scale * sc[c], key(kMass, wa), tr(key(kDeriv, wb, c - d))});
+    }
+  }
+  for (int side_dom = 0; side_dom < 2; ++side_dom) {  // 0: faces of Omega_x, 1: faces of Omega_v
+    DomainData& D = side_dom == 0 ? X : V;
+    if (D.dom.periodic) continue;
+    for (int axis = 0; axis < d; ++axis) {
+      const int c = side_dom == 0 ? axis : d + axis;
+      if (!has[c]) continue;
+      for (int side = 0; side < 2; ++side) {
+        const double sgn = side == 0 ? -1.0 : 1.0;
+        for (int pass = 0; pass < 2; ++pass) {
+          Weight wa = A[c], wb = B[c];
+          wa.scale = sgn * sc[c];
+          wa.kink = pass == 0 ? 1 : 2;  // (s a)^+ with b^-, then (s a)^- with b^+
+          wb.scale = 1.0;
+          wb.kink = pass == 0 ? 2 : 1;
+          if (weight_zero(X, wa) || weight_zero(V, wb)) continue;
+          if (side_dom == 0) Gm.push_back({1.0, key(kFace, wa, -1, -1, axis, side), key(kMass, wb)});
+          else Gm.push_back({1.0, key(kMass, wa), key(kFace, wb, -1, -1, axis, side)});
+        }
+      }
+    }
+  }
+
+  double Mt[9], Tt[9], Ct[9], Gt[9], TtT[9];
+  time_matrices(r, p.dt, Mt, Tt, Ct, Gt);
+  for (int s = 0; s < R; ++s)
+    for (int q = 0; q < R; ++q) TtT[s * R + q] = Tt[q * R + s];
+
+  auto add = [&](TermList& L, const double* tm, double scale, const std::vector<KTerm>& ops, bool transpose) {
+    bool nz = false;
+    for (int i = 0; i < L.Rout * L.Rin; ++i) nz = nz || tm[i] != 0.0;
+    if (!nz || scale == 0.0) return;
+    for (const KTerm& k : ops) {
+      Term t;
+      const FactorKey fx = transpose ? tr(k.X) : k.X;
+      const FactorKey fv = transpose ? tr(k.V) : k.V;
+      t.xf = X.factor_id(fx);
+      t.vf = V.factor_id(fv);
+      for (int i = 0; i < L.Rout * L.Rin; ++i) t.tm[i] = scale * k.c * tm[i];
+      // merge with an existing (xf, vf) pair
+      bool merged = false;
+      for (Term& e : L.terms)
+        if (e.xf == t.xf && e.vf == t.vf) {
+          for (int i = 0; i < L.Rout * L.Rin; ++i) e.tm[i] += t.tm[i];
+          merged = true;
+          break;
+        }
+      if (!merged) L.terms.push_back(t);
+    }
+  };
+
+  // FULL
+  TermList& F = out[0];
+  F.Rin = F.Rout = R;
+  F.terms.clear();
+  double P0[9];
+  for (int i = 0; i < R * R; ++i) P0[i] = Tt[i] + dl * Ct[i] + Gt[i];
+  add(F, P0, 1.0, M, false);
+  add(F, Tt, dl, T, true);
+  add(F, TtT, dl, T, false);
+  add(F, TtT, dl, K, false);
+  add(F, Mt, 1.0, T, false);
+  add(F, Mt, dl, C, false);
+  add(F, Mt, 1.0, K, false);
+  add(F, Mt, dl, Kt, false);
+  add(F, Mt, 1.0, Gm, false);
+  // MASS
+  TermList& Ms = out[1];
+  Ms.Rin = Ms.Rout = 1;
+  Ms.terms.clear();
+  const double one1[1] = {1.0};
+  add(Ms, one1, 1.0, M, false);
+  // DATA_F
+  TermList& Df = out[2];
+  Df.Rin = Df.Rout = R;
+  Df.terms.clear();
+  double P1[9];
+  for (int i = 0; i < R * R; ++i) P1[i] = Mt[i] + dl * TtT[i];
+  add(Df, P1, 1.0, M, false);
+  add(Df, Mt, dl, T, true);
+  // DATA_G
+  TermList& Dg = out[3];
+  Dg.Rin = Dg.Rout = R;
+  Dg.terms.clear();
+  add(Dg, Mt, 1.0, Gm, false);
+}
+
+}  // namespace sgdg

@@ -1,0 +1,289 @@
+"""Python binding of libsgdg (ctypes).  Argument marshalling only: every step
+of the method runs in the HIP library; PyTorch provides device memory and the
+stream.  Raises if the library is not built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgdg.so")
+
+OP_FULL, OP_BLOCKDIAG, OP_MASS, OP_DATA_F, OP_DATA_G = 0, 1, 2, 3, 4
+F64, F32 = 0, 1
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_ALLOC", -3: "E_HIP", -4: "E_NOCONV", -5: "E_BREAKDOWN",
+          -6: "E_NAN", -7: "E_STATE"}
+
+EXPORTS = [
+    "sgdg_last_error", "sgdg_build_sparse_grid", "sgdg_grid_info", "sgdg_grid_destroy",
+    "sgdg_assemble_1d_factors", "sgdg_ops_destroy", "sgdg_apply_operator", "sgdg_combine",
+    "sgdg_precondition", "sgdg_rhs", "sgdg_solve_strip", "sgdg_debug_dense_block",
+    "sgdg_profile", "sgdg_profile_read", "sgdg_op_info",
+]
+
+
+class SgdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Domain(C.Structure):
+    _fields_ = [("dim", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int)]
+
+
+class Separable(C.Structure):
+    _fields_ = [("scale", C.c_double), ("n_xf", C.c_int), ("xf", C.POINTER(C.POINTER(C.c_double))),
+                ("n_vf", C.c_int), ("vf", C.POINTER(C.POINTER(C.c_double)))]
+
+
+class Problem(C.Structure):
+    _fields_ = [("beta", C.POINTER(Separable) * 6), ("n_sigma", C.c_int), ("sigma", C.POINTER(Separable)),
+                ("dt", C.c_double), ("delta", C.c_double)]
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("kind", C.c_int), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int),
+                ("inner_restart", C.c_int), ("mass_sweeps", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("mixed_precision", C.c_int),
+                ("inner_outer_rtol", C.c_double), ("pc", PrecondOpts)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("refinement_steps", C.c_int), ("inner_iters_total", C.c_int),
+                ("rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_05988_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64p, ip, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_double)
+    L.sgdg_last_error.restype = C.c_char_p
+    L.sgdg_build_sparse_grid.argtypes = [C.POINTER(Domain), C.POINTER(Domain), C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(vp)]
+    L.sgdg_grid_info.argtypes = [vp, C.c_int, ip, i64p, ip, ip, i64p, i64p, i64p]
+    L.sgdg_grid_destroy.argtypes = [vp]
+    L.sgdg_grid_destroy.restype = None
+    L.sgdg_assemble_1d_factors.argtypes = [vp, C.POINTER(Problem), C.POINTER(vp)]
+    L.sgdg_ops_destroy.argtypes = [vp]
+    L.sgdg_ops_destroy.restype = None
+    L.sgdg_apply_operator.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
+    L.sgdg_combine.argtypes = [vp, vp, vp, C.c_int, vp]
+    L.sgdg_precondition.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.POINTER(PrecondOpts), vp]
+    L.sgdg_rhs.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp]
+    L.sgdg_solve_strip.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+    L.sgdg_debug_dense_block.argtypes = [C.POINTER(Domain), C.POINTER(Domain), C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(Problem), C.c_int, C.c_int, C.c_int, dp]
+    L.sgdg_profile.argtypes = [vp, C.c_int]
+    L.sgdg_profile_read.argtypes = [vp, C.c_int, dp, i64p]
+    L.sgdg_op_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip, ip, ip]
+    for name in EXPORTS:
+        if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy"):
+            getattr(L, name).restype = C.c_int
+    _LIB = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise SgdgError(code, lib().sgdg_last_error().decode())
+
+
+def _domain(dom) -> Domain:
+    d = Domain()
+    d.dim = dom.d
+    for a in range(3):
+        d.lo[a] = dom.lo[a] if a < dom.d else 0.0
+        d.hi[a] = dom.hi[a] if a < dom.d else 1.0
+    d.periodic = int(dom.periodic)
+    return d
+
+
+class _ProblemHolder:
+    """Builds the C problem struct from a workload; keeps every array alive."""
+
+    def __init__(self, w, fx, fv):
+        self.keep = []
+        self.p = Problem()
+
+        def arr(a):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self.keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        def sep(scale, xn, vn):
+            s = Separable()
+            s.scale = float(scale)
+            xs = (C.POINTER(C.c_double) * max(1, len(xn)))(*[arr(fx[k]) for k in xn])
+            vs = (C.POINTER(C.c_double) * max(1, len(vn)))(*[arr(fv[k]) for k in vn])
+            self.keep += [xs, vs]
+            s.n_xf, s.xf = len(xn), C.cast(xs, C.POINTER(C.POINTER(C.c_double)))
+            s.n_vf, s.vf = len(vn), C.cast(vs, C.POINTER(C.POINTER(C.c_double)))
+            self.keep.append(s)
+            return s
+
+        for c in range(6):
+            b = w.beta[c] if c < len(w.beta) else None
+            self.p.beta[c] = C.pointer(sep(*b)) if b is not None else C.POINTER(Separable)()
+        sig = (Separable * max(1, len(w.sigma)))()
+        for i, (sc, P, Q) in enumerate(w.sigma):
+            sig[i] = sep(sc, P, Q)
+        self.keep.append(sig)
+        self.p.n_sigma = len(w.sigma)
+        self.p.sigma = C.cast(sig, C.POINTER(Separable))
+        self.p.dt = w.dt
+        self.p.delta = w.delta
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def default_precond_opts(inner_rtol=1e-8, inner_maxit=200, inner_restart=30, mass_sweeps=0) -> PrecondOpts:
+    return PrecondOpts(0, inner_rtol, inner_maxit, inner_restart, mass_sweeps)
+
+
+def default_solve_opts(rtol=1e-8, restart=50, maxit=400, mixed=False, inner_outer_rtol=1e-4, pc=None) -> SolveOpts:
+    return SolveOpts(rtol, restart, maxit, int(mixed), inner_outer_rtol, pc or default_precond_opts())
+
+
+class SparseGridOps:
+    """One strip operator of a workload on the current HIP device."""
+
+    def __init__(self, w, fields=None):
+        from workloads import nodal_fields
+        L = lib()
+        self.w = w
+        self.R = w.r + 1
+        fx, fv = fields if fields is not None else nodal_fields(w)
+        self._dx, self._dv = _domain(w.x), _domain(w.v)
+        g = C.c_void_p()
+        _check(L.sgdg_build_sparse_grid(C.byref(self._dx), C.byref(self._dv), w.lmin, w.L, w.r, C.byref(g)))
+        self.grid = g
+        self.prob = _ProblemHolder(w, fx, fv)
+        o = C.c_void_p()
+        _check(L.sgdg_assemble_1d_factors(g, C.byref(self.prob.p), C.byref(o)))
+        self.ops = o
+        self.upper = self.info(0)
+        self.lower = self.info(1)
+        self.ndof = int(self.R * sum(nx * nv for _, _, nx, nv in self.upper))
+        self.npts_up = int(sum(nx * nv for _, _, nx, nv in self.upper))
+        self.npts_low = int(sum(nx * nv for _, _, nx, nv in self.lower))
+
+    def info(self, which):
+        L = lib()
+        n = C.c_int()
+        _check(L.sgdg_grid_info(self.grid, which, C.byref(n), None, None, None, None, None, None))
+        k = n.value
+        lx, lv = (C.c_int * max(k, 1))(), (C.c_int * max(k, 1))()
+        nx, nv = (C.c_int64 * max(k, 1))(), (C.c_int64 * max(k, 1))()
+        _check(L.sgdg_grid_info(self.grid, which, None, None, lx, lv, nx, nv, None))
+        return [(lx[i], lv[i], nx[i], nv[i]) for i in range(k)]
+
+    def close(self):
+        if getattr(self, "ops", None):
+            lib().sgdg_ops_destroy(self.ops)
+            self.ops = None
+        if getattr(self, "grid", None):
+            lib().sgdg_grid_destroy(self.grid)
+            self.grid = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- calls -------------------------------------------------------------------
+    def apply(self, u, y, kind=OP_FULL, batch=1, stream=None):
+        import torch
+        dt = F64 if u.dtype == torch.float64 else F32
+        assert u.is_cuda and y.is_cuda and u.is_contiguous() and y.is_contiguous() and u.dtype == y.dtype
+        n = self.ndof // self.R if kind == OP_MASS else self.ndof
+        assert u.numel() == batch * n and y.numel() == batch * n, "shape mismatch"
+        _check(lib().sgdg_apply_operator(self.ops, kind, _ptr(u), _ptr(y), dt, batch, _stream(stream)))
+        return y
+
+    def combine(self, nodal, coef, nslices, stream=None):
+        assert nodal.numel() == nslices * (self.npts_up + self.npts_low) and coef.numel() == nslices * self.npts_up
+        _check(lib().sgdg_combine(self.ops, _ptr(nodal), _ptr(coef), nslices, _stream(stream)))
+        return coef
+
+    def precondition(self, r, z, opts: Optional[PrecondOpts] = None, stream=None):
+        import torch
+        dt = F64 if r.dtype == torch.float64 else F32
+        assert r.numel() == self.ndof and z.numel() == self.ndof and r.dtype == z.dtype
+        o = opts or default_precond_opts()
+        _check(lib().sgdg_precondition(self.ops, _ptr(r), _ptr(z), dt, 1, C.byref(o), _stream(stream)))
+        return z
+
+    def rhs(self, u_prev, prev_slices, f_nodal=None, g_nodal=None, b=None, stream=None):
+        import torch
+        if b is None:
+            b = torch.empty(self.ndof, dtype=torch.float64, device=u_prev.device)
+        assert u_prev.numel() == prev_slices * self.npts_up
+        nq = self.w.r + 2
+        for a in (f_nodal, g_nodal):
+            assert a is None or a.numel() == nq * (self.npts_up + self.npts_low)
+        _check(lib().sgdg_rhs(self.ops, _ptr(u_prev), prev_slices, _ptr(f_nodal) if f_nodal is not None else None,
+                              _ptr(g_nodal) if g_nodal is not None else None, _ptr(b), _stream(stream)))
+        return b
+
+    def profile(self, on: bool):
+        _check(lib().sgdg_profile(self.ops, 1 if on else 0))
+
+    def profile_read(self, slot):
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().sgdg_profile_read(self.ops, slot, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def op_info(self, kind=OP_FULL):
+        v = [C.c_int() for _ in range(7)]
+        _check(lib().sgdg_op_info(self.ops, kind, *[C.byref(x) for x in v]))
+        return dict(zip(["nterms", "nvg", "nxg", "Sx", "Sv", "Rin", "Rout"], [x.value for x in v]))
+
+    def solve_strip(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
+        o = opts or default_solve_opts()
+        st = SolveStats()
+        code = lib().sgdg_solve_strip(self.ops, _ptr(b), _ptr(u), C.byref(o), C.byref(st), _stream(stream))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        return u, st
+
+
+def debug_dense_block(w, kind, row_grid, col_grid, fields=None):
+    """Host-only dense operator block from the library's host assembly (diagnostics)."""
+    from workloads import grid_levels, lattice_shape, nodal_fields
+    fx, fv = fields if fields is not None else nodal_fields(w)
+    holder = _ProblemHolder(w, fx, fv)
+    up, _ = grid_levels(w)
+    R = w.r + 1
+    Rin = Rout = 1 if kind == OP_MASS else R
+    n = lambda dom, l: int(np.prod(lattice_shape(dom, l)))
+    (lx, lv), (lx2, lv2) = up[row_grid], up[col_grid]
+    rows, cols = Rout * n(w.x, lx) * n(w.v, lv), Rin * n(w.x, lx2) * n(w.v, lv2)
+    out = np.zeros((rows, cols))
+    dx, dv = _domain(w.x), _domain(w.v)
+    _check(lib().sgdg_debug_dense_block(C.byref(dx), C.byref(dv), w.lmin, w.L, w.r, C.byref(holder.p), kind,
+                                        row_grid, col_grid, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
