@@ -268,6 +268,71 @@ static void transpose_level(const DomainData& D, int l, const std::vector<double
       if (Lt.valid[p * S + e]) T[p * S + e] = X[int64_t(Lt.nbr[p * S + e]) * S + D.st.neg(e)];
 }
 
+void build_wide_tables(DomainData& D) {
+  const Dom& dom = D.dom;
+  const int d = dom.d, S = D.st.S;
+  D.woff.clear();
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < S; ++b) {
+      std::array<int, 3> o{0, 0, 0};
+      for (int x = 0; x < d; ++x) o[x] = D.st.off[a][x] + D.st.off[b][x];
+      if (std::find(D.woff.begin(), D.woff.end(), o) == D.woff.end()) D.woff.push_back(o);
+    }
+  std::sort(D.woff.begin(), D.woff.end());
+  const int W = int(D.woff.size());
+  D.wide_idx.assign(D.lmax - D.lmin + 1, {});
+  int iP[3], q[3];
+  for (int l = D.lmin; l < D.lmax; ++l) {
+    const LevelTables& C = D.L(l);
+    const int mf = dom.axis_nodes(l + 1), nf = 1 << (l + 1);
+    auto& tab = D.wide_idx[l - D.lmin];
+    tab.assign(C.n * W, 0);
+    for (int64_t P = 0; P < C.n; ++P) {
+      unflat(P, d, C.m, iP);
+      for (int w = 0; w < W; ++w) {
+        bool ok = true;
+        for (int a = 0; a < d; ++a) {
+          q[a] = 2 * iP[a] + D.woff[w][a];
+          if (dom.periodic) q[a] = ((q[a] % nf) + nf) % nf;
+          else if (q[a] < 0 || q[a] >= mf) ok = false;
+        }
+        if (!ok)
+          for (int a = 0; a < d; ++a) q[a] = dom.periodic ? ((2 * iP[a]) % nf) : 2 * iP[a];
+        int64_t f = 0;
+        for (int a = 0; a < d; ++a) f = f * mf + q[a];
+        tab[P * W + w] = int32_t(f);
+      }
+    }
+  }
+}
+
+void restrict_factor(DomainData& D, int fid) {
+  const int S = D.st.S, W = int(D.woff.size()), d = D.dom.d;
+  // slot of off_c + off_e in woff
+  std::vector<int> pair(S * S);
+  for (int c = 0; c < S; ++c)
+    for (int e = 0; e < S; ++e) {
+      std::array<int, 3> o{0, 0, 0};
+      for (int x = 0; x < d; ++x) o[x] = D.st.off[c][x] + D.st.off[e][x];
+      pair[c * S + e] = int(std::find(D.woff.begin(), D.woff.end(), o) - D.woff.begin());
+    }
+  auto& out = D.rvalues[fid];
+  out.assign(D.lmax - D.lmin + 1, {});
+  for (int l = D.lmin; l < D.lmax; ++l) {
+    const LevelTables& C = D.L(l);
+    const auto& fine = D.values[fid][l + 1 - D.lmin];
+    auto& r = out[l - D.lmin];
+    r.assign(C.n * W, 0.0);
+    for (int64_t P = 0; P < C.n; ++P)
+      for (int c = 0; c < S; ++c) {
+        const double wc = C.chiw[P * S + c];
+        if (wc == 0.0) continue;
+        const int64_t fc = C.chi[P * S + c];
+        for (int e = 0; e < S; ++e) r[P * W + pair[c * S + e]] += wc * fine[fc * S + e];
+      }
+  }
+}
+
 void assemble_factor(DomainData& D, int fid) {
   FactorKey key = D.factors[fid];
   const int nlev = D.lmax - D.lmin + 1;

@@ -1,0 +1,481 @@
+// Fused operator application for gfx950 (wave64, LDS-staged box tiles).
+//
+// For upper grid i (levels (lx, lv)), with V-groups j (terms sharing a v-factor)
+// and X-groups m (terms sharing an x-factor), the block row of the strip
+// operator is (Sect. 4.2, blockwise application with the embedding identities
+// X_{l,l'} = X_l E_{l<-l'} for l' < l and E_{l'<-l}^T X_{l'} for l' > l):
+//
+//   y_i = sum_k Tm_k (X_k (x) I) [ (I (x) V_k) u_i + (E^x (x) I) Pt_i^{j(k)} ]      diagonal + lower partners
+//       + sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt_i^{m(k)}                          upper partners
+//
+// where the partner sums are carried by two scans whose arrays live on the
+// lower diagonal (2^d times smaller than the upper grids):
+//   Pt_{i+1} = (I (x) E^vT) [ (I (x) V) u_i + (E^x (x) I) Pt_i ]      on (lx_i,   lv_i - 1)
+//   Qt_i     = (E^xT (x) I) [ (X (x) I) u_{i+1} + (I (x) E^v) Qt_{i+1} ] on (lx_i, lv_i - 1)
+//
+// The fused kernel works on a box of x-nodes times a box of v-nodes of one
+// grid: phase 1 stages Z = V u + E^x Pt on the x-box plus a one-node halo in
+// LDS, phase 2 applies every x-factor of the group from LDS; the upper part
+// stages E^v Qt on the v-box plus halo and applies the v-factors.  Halo nodes
+// are addressed by unwrapped box coordinates, so periodic wrap only appears
+// when the staged values are fetched.
+#include <hip/hip_runtime.h>
+
+#include "fused.h"
+
+namespace sgdg {
+
+constexpr int kFB = 256;   // threads per block
+constexpr int kRows = 4;   // box rows per thread: nxb <= kRows * (kFB / nvb)
+
+template <class T> __device__ __forceinline__ const T* fv(const DevDomain& D);
+template <> __device__ __forceinline__ const double* fv<double>(const DevDomain& D) { return D.vals; }
+template <> __device__ __forceinline__ const float* fv<float>(const DevDomain& D) { return D.vals32; }
+template <class T> __device__ __forceinline__ const T* tmx(const DevOp& op);
+template <> __device__ __forceinline__ const double* tmx<double>(const DevOp& op) { return op.term_tm; }
+template <> __device__ __forceinline__ const float* tmx<float>(const DevOp& op) { return op.term_tm32; }
+
+// lattice helpers ------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void unflat(int p, const int* dims, int* c) {
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    c[a] = p % dims[a];
+    p /= dims[a];
+  }
+}
+// node index of lattice coordinates (m nodes per axis); -1 if outside a non-periodic lattice
+template <int D>
+__device__ __forceinline__ int node_of(const int* c, int m, int periodic_cells) {
+  int p = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int x = c[a];
+    if (periodic_cells > 0) {
+      x %= periodic_cells;
+      if (x < 0) x += periodic_cells;
+    } else if (x < 0 || x >= m) {
+      return -1;
+    }
+    p = p * m + x;
+  }
+  return p;
+}
+
+// Per-block index tables live in LDS after the staging area:
+//   xh_node[nxh]  x node of each halo row (-1 outside a non-periodic lattice)
+//   xb_halo[nxb]  halo row of each box row;  xb_node[nxb] x node of each box row
+//   vb_node[nvb]  v node of each box column; vb_halo[nvb] halo column of each box column
+//   vh_node[nvh]  v node of each halo column (-1 outside)
+// Threads own one box column (col = tid % nvb) and a strided set of rows, so
+// stencil indices and v-factor values are loaded once per column and group.
+template <class T, int D, int R>
+__global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);  // Kuhn stencil size
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const FusedItem it = A.items[blockIdx.x];
+  const int b = blockIdx.y;
+  const DevGrids& G = A.G;
+  const int g = it.grid;
+  const int lx = G.lx[g], lv = G.lv[g];
+  const int nx = G.nx[g], nv = G.nv[g];
+  const int mx = A.mx[lx], mv = A.mv[lv];
+  const int pcx = A.xper ? (1 << lx) : 0, pcv = A.vper ? (1 << lv) : 0;
+  const DevOp& op = A.op;
+  constexpr int Rin = R, Rout = R;
+  const int64_t plane = int64_t(nx) * nv;
+  const int64_t total = G.off[G.n];
+  const T* ug = A.u + int64_t(b) * total + G.off[g];
+  constexpr int SX = SS, SV = SS;
+
+  int xs[3] = {1, 1, 1}, vs[3] = {1, 1, 1}, xh[3] = {1, 1, 1}, vh[3] = {1, 1, 1};
+  int nxb = 1, nvb = 1, nxh = 1, nvh = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    xs[a] = it.xs[a];
+    vs[a] = it.vs[a];
+    xh[a] = xs[a] + 2;
+    vh[a] = vs[a] + 2;
+    nxb *= xs[a];
+    nvb *= vs[a];
+    nxh *= xh[a];
+    nvh *= vh[a];
+  }
+  const bool has_p = !A.diag_only && g > 0;
+  const bool has_q = !A.diag_only && g + 1 < G.n;
+  // index tables
+  int* tab = reinterpret_cast<int*>(lds + A.max_stage);
+  int* xh_node = tab;
+  int* xb_halo = xh_node + nxh;
+  int* xb_node = xb_halo + nxb;
+  int* vb_node = xb_node + nxb;
+  int* vb_halo = vb_node + nvb;
+  int* vh_node = vb_halo + nvb;
+  for (int i = threadIdx.x; i < nxh; i += kFB) {
+    int c[3];
+    unflat<D>(i, xh, c);
+#pragma unroll
+    for (int a = 0; a < D; ++a) c[a] += it.xb[a] - 1;
+    xh_node[i] = node_of<D>(c, mx, pcx);
+  }
+  for (int i = threadIdx.x; i < nxb; i += kFB) {
+    int c[3];
+    unflat<D>(i, xs, c);
+    int h = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      h = h * xh[a] + c[a] + 1;
+      c[a] += it.xb[a];
+    }
+    xb_halo[i] = h;
+    xb_node[i] = node_of<D>(c, mx, 0);
+  }
+  for (int i = threadIdx.x; i < nvb; i += kFB) {
+    int c[3];
+    unflat<D>(i, vs, c);
+    int h = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      h = h * vh[a] + c[a] + 1;
+      c[a] += it.vb[a];
+    }
+    vb_halo[i] = h;
+    vb_node[i] = node_of<D>(c, mv, 0);
+  }
+  if (has_q)
+    for (int i = threadIdx.x; i < nvh; i += kFB) {
+      int c[3];
+      unflat<D>(i, vh, c);
+#pragma unroll
+      for (int a = 0; a < D; ++a) c[a] += it.vb[a] - 1;
+      vh_node[i] = node_of<D>(c, mv, pcv);
+    }
+  // halo offsets of the stencil slots
+  int dxh[SS], dvh[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) {
+    int ox = 0, ov = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ox = ox * xh[a] + A.off[e][a];
+      ov = ov * vh[a] + A.off[e][a];
+    }
+    dxh[e] = ox;
+    dvh[e] = ov;
+  }
+  __syncthreads();
+
+  const int nrg = kFB / nvb;            // row groups (nvb <= kFB)
+  const int col = threadIdx.x % nvb;
+  const int rg = threadIdx.x / nvb;
+  const bool active = rg < nrg;
+  const int vi = active ? vb_node[col] : 0;
+  const int vhc = active ? vb_halo[col] : 0;
+  const T* xvals = fv<T>(A.DX);
+  const T* vvals = fv<T>(A.DV);
+  const T* tm = tmx<T>(op);
+  const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
+  const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
+  int32_t nbv[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) nbv[e] = active ? A.DV.nbr[vlo + int64_t(vi) * SV + e] : 0;
+
+  T acc[kRows][R];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[r][s] = T(0);
+
+  // ---------------- diagonal + lower partners, one V-group at a time -------
+  const int gl = g - 1;  // lower grid holding Pt_g: (lx-1, lv)
+  const int64_t lplane = has_p ? int64_t(A.Gl.nx[gl]) * nv : 0;
+  const int64_t ltotal = A.Gl.off[A.Gl.n];
+  const int64_t po = has_p ? A.DX.par_off[lx - A.DX.lmin] : 0;
+  for (int j = 0; j < op.nvg; ++j) {
+    if (active) {
+      const T* vf = vvals + int64_t(op.vg_fac[j]) * A.DV.fac_stride + vlo + int64_t(vi) * SV;
+      T fvv[SS];
+#pragma unroll
+      for (int e = 0; e < SS; ++e) fvv[e] = vf[e];
+      const T* pt = has_p ? A.Pt + (int64_t(j) * A.B + b) * ltotal + A.Gl.off[gl] + vi : nullptr;
+      for (int r = rg; r < nxh; r += nrg) {
+        const int xi = xh_node[r];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          T z = T(0);
+          if (xi >= 0) {
+            const T* urow = ug + int64_t(s) * plane + int64_t(xi) * nv;
+#pragma unroll
+            for (int e = 0; e < SS; ++e) z += fvv[e] * urow[nbv[e]];
+            if (has_p) {
+              const int64_t pp = po + 2 * int64_t(xi);
+              const T* pr = pt + int64_t(s) * lplane;
+              z += T(A.DX.parw[pp]) * pr[int64_t(A.DX.par[pp]) * nv] +
+                   T(A.DX.parw[pp + 1]) * pr[int64_t(A.DX.par[pp + 1]) * nv];
+            }
+          }
+          lds[(s * nxh + r) * nvb + col] = z;
+        }
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int kk = op.vg_start[j]; kk < op.vg_start[j + 1]; ++kk) {
+        const int k = op.vg_terms[kk];
+        const T* xf = xvals + int64_t(op.term_xf[k]) * A.DX.fac_stride + xlo;
+        const T* tk = tm + int64_t(k) * Rout * Rin;
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) {
+          const int r = rg + q * nrg;
+          if (r >= nxb) break;
+          const T* fr = xf + int64_t(xb_node[r]) * SX;
+          const int hb = xb_halo[r];
+#pragma unroll
+          for (int s2 = 0; s2 < R; ++s2) {
+            const T* l = lds + (s2 * nxh + hb) * nvb + col;
+            T t = T(0);
+#pragma unroll
+            for (int e = 0; e < SS; ++e) t += fr[e] * l[dxh[e] * nvb];
+#pragma unroll
+            for (int s = 0; s < R; ++s) acc[q][s] += tk[s * R + s2] * t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---------------- upper partners, one X-group at a time ------------------
+  if (has_q) {
+    const int nvl = A.Gl.nv[g];  // lower grid g: (lx, lv-1)
+    const int64_t qplane = int64_t(nx) * nvl;
+    const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
+    const int nst = nxb * nvh;
+    for (int m = 0; m < op.nxg; ++m) {
+      const T* qt = A.Qt + (int64_t(m) * A.B + b) * ltotal + A.Gl.off[g];
+      for (int h = threadIdx.x; h < nst; h += kFB) {
+        const int r = h / nvh, c = h - (h / nvh) * nvh;
+        const int vn = vh_node[c];
+        const int xi = xb_node[r];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          T z = T(0);
+          if (vn >= 0) {
+            const int64_t pp = vpo + 2 * int64_t(vn);
+            const T* qr = qt + int64_t(s) * qplane + int64_t(xi) * nvl;
+            z = T(A.DV.parw[pp]) * qr[A.DV.par[pp]] + T(A.DV.parw[pp + 1]) * qr[A.DV.par[pp + 1]];
+          }
+          lds[(s * nxb + r) * nvh + c] = z;
+        }
+      }
+      __syncthreads();
+      if (active) {
+        for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
+          const int k = op.xg_terms[kk];
+          const T* vfk = vvals + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + int64_t(vi) * SV;
+          T fvv[SS];
+#pragma unroll
+          for (int e = 0; e < SS; ++e) fvv[e] = vfk[e];
+          const T* tk = tm + int64_t(k) * Rout * Rin;
+#pragma unroll
+          for (int q = 0; q < kRows; ++q) {
+            const int r = rg + q * nrg;
+            if (r >= nxb) break;
+#pragma unroll
+            for (int s2 = 0; s2 < R; ++s2) {
+              const T* l = lds + (s2 * nxb + r) * nvh + vhc;
+              T t = T(0);
+#pragma unroll
+              for (int e = 0; e < SS; ++e) t += fvv[e] * l[dvh[e]];
+#pragma unroll
+              for (int s = 0; s < R; ++s) acc[q][s] += tk[s * R + s2] * t;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---------------- store -------------------------------------------------
+  if (active) {
+    T* yg = A.y + int64_t(b) * (int64_t(Rout) * A.P.poff[G.n]) + int64_t(Rout) * A.P.poff[g] + vi;
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const int r = rg + q * nrg;
+      if (r >= nxb) break;
+      const int64_t p = int64_t(xb_node[r]) * nv;
+#pragma unroll
+      for (int s = 0; s < R; ++s) yg[int64_t(s) * plane + p] = acc[q][s];
+    }
+  }
+}
+
+// Scan step on the lower diagonal, all factor groups per thread.
+// blockIdx.z = 0: Pt_{t+1} on lower grid t; blockIdx.z = 1: Qt on lower grid
+// nlow-1-t.  The restricted stencils E^T V (resp. E^T X) of width W couple a
+// coarse node with the fine nodes 2P + o; the u values at those nodes are
+// loaded once and reused by every group.
+template <class T> __device__ __forceinline__ const T* rv(const DevDomain& D);
+template <> __device__ __forceinline__ const double* rv<double>(const DevDomain& D) { return D.rvals; }
+template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.rvals32; }
+
+template <class T, int D>
+__global__ void __launch_bounds__(kFB) k_scan2(FusedArgs<T> A, int t) {
+  constexpr int W = D == 1 ? 5 : (D == 2 ? 19 : 65);
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  const DevGrids& G = A.G;
+  const DevGrids& L = A.Gl;
+  const bool lower = blockIdx.z == 0;
+  const int b = blockIdx.y;
+  const DevOp& op = A.op;
+  const int lg = lower ? t : L.n - 1 - t;    // target lower grid
+  const int nxl = L.nx[lg], nvl = L.nv[lg];
+  const int64_t lplane = int64_t(nxl) * nvl;
+  const int64_t loc = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (loc >= int64_t(op.Rin) * lplane) return;
+  const int s = int(loc / lplane);
+  const int64_t rem = loc - int64_t(s) * lplane;
+  const int x = int(rem / nvl), v = int(rem - int64_t(x) * nvl);
+  const int64_t total = G.off[G.n], ltotal = L.off[L.n];
+  T un[W];
+  if (lower) {
+    // source grid t (lx, lv); target (lx, lv-1); previous Pt_t on lower grid t-1 (lx-1, lv)
+    const int src = t;
+    const int nv = G.nv[src];
+    const int lvc = G.lv[src] - 1 - A.DV.lmin;  // level of v (coarse)
+    const T* us = A.u + int64_t(b) * total + G.off[src] + int64_t(s) * G.nx[src] * nv + int64_t(x) * nv;
+    const int32_t* wi = A.DV.wide + A.DV.wlev_off[lvc] + int64_t(v) * W;
+#pragma unroll
+    for (int o = 0; o < W; ++o) un[o] = us[wi[o]];
+    const bool has_p = src > 0;
+    int32_t p0 = 0, p1 = 0;
+    T w0 = 0, w1 = 0;
+    int32_t ch[SS];
+    T cw[SS];
+    if (has_p) {
+      const int64_t po = A.DX.par_off[G.lx[src] - A.DX.lmin] + 2 * int64_t(x);
+      p0 = A.DX.par[po];
+      p1 = A.DX.par[po + 1];
+      w0 = T(A.DX.parw[po]);
+      w1 = T(A.DX.parw[po + 1]);
+      const int64_t co = A.DV.lev_off[lvc] + int64_t(v) * SS;
+#pragma unroll
+      for (int c = 0; c < SS; ++c) {
+        ch[c] = A.DV.chi[co + c];
+        cw[c] = T(A.DV.chiw[co + c]);
+      }
+    }
+    const int64_t pl = has_p ? int64_t(L.nx[src - 1]) * nv : 0;
+    for (int j = 0; j < op.nvg; ++j) {
+      const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + int64_t(v) * W;
+      T acc = T(0);
+#pragma unroll
+      for (int o = 0; o < W; ++o) acc += r[o] * un[o];
+      if (has_p) {
+        const T* pp = A.Pt + (int64_t(j) * A.B + b) * ltotal + L.off[src - 1] + int64_t(s) * pl;
+        const T* r0 = pp + int64_t(p0) * nv;
+        const T* r1 = pp + int64_t(p1) * nv;
+#pragma unroll
+        for (int c = 0; c < SS; ++c) acc += cw[c] * (w0 * r0[ch[c]] + w1 * r1[ch[c]]);
+      }
+      A.Pt[(int64_t(j) * A.B + b) * ltotal + L.off[lg] + loc] = acc;
+    }
+  } else {
+    // source grid lg+1 (lx+1, lv-1); target lower lg (lx, lv-1); previous Qt on lower grid lg+1 (lx+1, lv-2)
+    const int src = lg + 1;
+    const int nv = G.nv[src];
+    const int lxc = G.lx[src] - 1 - A.DX.lmin;  // level of x (coarse)
+    const T* us = A.u + int64_t(b) * total + G.off[src] + int64_t(s) * G.nx[src] * nv + v;
+    const int32_t* wi = A.DX.wide + A.DX.wlev_off[lxc] + int64_t(x) * W;
+#pragma unroll
+    for (int o = 0; o < W; ++o) un[o] = us[int64_t(wi[o]) * nv];
+    const bool has_q = src + 1 < G.n;
+    int32_t p0 = 0, p1 = 0;
+    T w0 = 0, w1 = 0;
+    int32_t ch[SS];
+    T cw[SS];
+    int nvq = 0;
+    if (has_q) {
+      const int64_t po = A.DV.par_off[G.lv[src] - A.DV.lmin] + 2 * int64_t(v);
+      p0 = A.DV.par[po];
+      p1 = A.DV.par[po + 1];
+      w0 = T(A.DV.parw[po]);
+      w1 = T(A.DV.parw[po + 1]);
+      const int64_t co = A.DX.lev_off[lxc] + int64_t(x) * SS;
+#pragma unroll
+      for (int c = 0; c < SS; ++c) {
+        ch[c] = A.DX.chi[co + c];
+        cw[c] = T(A.DX.chiw[co + c]);
+      }
+      nvq = L.nv[src];
+    }
+    const int64_t ql = has_q ? int64_t(L.nx[src]) * nvq : 0;
+    for (int m = 0; m < op.nxg; ++m) {
+      const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + int64_t(x) * W;
+      T acc = T(0);
+#pragma unroll
+      for (int o = 0; o < W; ++o) acc += r[o] * un[o];
+      if (has_q) {
+        const T* qq = A.Qt + (int64_t(m) * A.B + b) * ltotal + L.off[src] + int64_t(s) * ql;
+#pragma unroll
+        for (int c = 0; c < SS; ++c) {
+          const T* row = qq + int64_t(ch[c]) * nvq;
+          acc += cw[c] * (w0 * row[p0] + w1 * row[p1]);
+        }
+      }
+      A.Qt[(int64_t(m) * A.B + b) * ltotal + L.off[lg] + loc] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+template <class T>
+size_t fused_smem(const FusedArgs<T>& A, int d) {
+  (void)d;
+  return size_t(A.max_stage) * sizeof(T) + size_t(A.max_tab) * sizeof(int);
+}
+
+template <class T>
+void fused_scans(const FusedArgs<T>& A, int d, hipStream_t s) {
+  const DevOp& op = A.op;
+  if (!A.diag_only && A.G.n > 1) {
+    for (int t = 0; t + 1 < A.G.n; ++t) {
+      const int lo = t, up = A.Gl.n - 1 - t;
+      const int64_t n1 = int64_t(op.Rin) * A.Gl.nx[lo] * A.Gl.nv[lo];
+      const int64_t n2 = int64_t(op.Rin) * A.Gl.nx[up] * A.Gl.nv[up];
+      const int64_t n = n1 > n2 ? n1 : n2;
+      dim3 grid(unsigned((n + kFB - 1) / kFB), A.B, 2);
+      if (d == 1) hipLaunchKernelGGL((k_scan2<T, 1>), grid, dim3(kFB), 0, s, A, t);
+      else if (d == 2) hipLaunchKernelGGL((k_scan2<T, 2>), grid, dim3(kFB), 0, s, A, t);
+      else hipLaunchKernelGGL((k_scan2<T, 3>), grid, dim3(kFB), 0, s, A, t);
+      SGDG_CHECK_HIP(hipGetLastError());
+    }
+  }
+}
+
+template <class T>
+void fused_tiles(const FusedArgs<T>& A, int d, hipStream_t s) {
+  const size_t sm = fused_smem(A, d);
+  dim3 grid(unsigned(A.nitems), A.B);
+  const int R = A.op.Rin;
+#define SGDG_FUSED_CASE(DD, RR) \
+  if (d == DD && R == RR) hipLaunchKernelGGL((k_fused<T, DD, RR>), grid, dim3(kFB), sm, s, A);
+  SGDG_FUSED_CASE(1, 1) SGDG_FUSED_CASE(1, 2) SGDG_FUSED_CASE(1, 3)
+  SGDG_FUSED_CASE(2, 1) SGDG_FUSED_CASE(2, 2) SGDG_FUSED_CASE(2, 3)
+  SGDG_FUSED_CASE(3, 1) SGDG_FUSED_CASE(3, 2) SGDG_FUSED_CASE(3, 3)
+#undef SGDG_FUSED_CASE
+  SGDG_CHECK_HIP(hipGetLastError());
+}
+
+template void fused_scans<double>(const FusedArgs<double>&, int, hipStream_t);
+template void fused_scans<float>(const FusedArgs<float>&, int, hipStream_t);
+template void fused_tiles<double>(const FusedArgs<double>&, int, hipStream_t);
+template void fused_tiles<float>(const FusedArgs<float>&, int, hipStream_t);
+
+int fused_points_per_block() { return kFB * kRows; }
+int fused_rows_per_thread() { return kRows; }
+int fused_threads() { return kFB; }
+
+}  // namespace sgdg

@@ -18,16 +18,6 @@ struct GridPts {
 
 template <class T>
 struct KernelsT {
-  // W[j] = (I (x) V_j) u for every V group j; if Rr != null also Rr[m] = (X_m (x) I) u.
-  static void sweeps(const DevGrids& G, const DevDomain& DX, const DevDomain& DV, const DevOp& op,
-                     const T* u, T* W, T* Rr, int B, hipStream_t s);
-  // One scan step: lower  Z[j][i] += (E^x (x) E^vT) Z[j][i-1]       (i = step)
-  //                upper  Q[m][i]  = (E^xT (x) E^v) (Q + Rr)[m][i+1] (i = n-1-step)
-  static void scan_step(const DevGrids& G, const DevDomain& DX, const DevDomain& DV, const DevOp& op,
-                        T* Z, T* Q, const T* Rr, int step, int B, hipStream_t s);
-  // y = sum_k Tm_k (X_k (x) I) Z[vg_k]  (+ sum_k Tm_k (I (x) V_k) Q[xg_k] if Q != null)
-  static void final_(const DevGrids& G, const GridPts& P, const DevDomain& DX, const DevDomain& DV,
-                     const DevOp& op, const T* Z, const T* Q, T* y, int B, hipStream_t s);
   // lower grid g (lx, lv) = (I (x) E^x_{lx+1,lx}^T (x) I) upper grid g+1 (lx+1, lv)
   static void restrict_x(const DevGrids& Gout, const DevGrids& Gin, const DevDomain& DX, const T* in, T* out,
                          hipStream_t s);

@@ -1,17 +1,8 @@
-// Device kernels of libsgdg for gfx950 (wave64).
-//
-// Operator application (Sect. 4.2).  A block of the strip matrix is
-//   A_{l,l'} = sum_k Tm_k (x) X_k(lx,lx') (x) V_k(lv,lv').
-// On the upper diagonal lx + lv is constant, so lx' < lx implies lv' > lv and
-//   X_k(lx,lx') = X_k(lx) E^x_{lx<-lx'},   V_k(lv,lv') = E^v_{lv'<-lv}^T V_k(lv')
-// (both from X_{l,l'} = E_{L,l}^T X_L E_{L,l'}).  The sum over all lower
-// partners l' of grid i is therefore a prefix scan along the chain of grids,
-//   Z_i = W_i + (E^x (x) E^vT) Z_{i-1},     W_i = (I (x) V) u_i,
-// one array per distinct v-factor V, after which y_i = sum_k Tm_k (X_k (x) I) Z_i.
-// The upper partners give the mirror scan over distinct x-factors X,
-//   Q_i = (E^xT (x) E^v)(Q_{i+1} + (X (x) I) u_{i+1}),  y_i += sum_k Tm_k (I (x) V_k) Q_i.
-// Each step reads a grid once per stencil entry and is streamed from HBM;
-// factor values are per-level [n][S] tables shared by all rows (L2 resident).
+// Device kernels of libsgdg for gfx950 (wave64): transfers between component
+// grids (embedding E and its transpose), the combination step, the inner
+// preconditioner, Krylov primitives (segmented dot products / updates with
+// FP64 accumulation, deterministic two-pass reductions), GMRES bookkeeping and
+// right-hand-side helpers.  The operator itself is applied by fused.hip.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -32,186 +23,6 @@ __device__ __forceinline__ int locate(const DevGrids& G, int64_t idx) {
   int g = 0;
   while (g + 1 < G.n && idx >= G.off[g + 1]) ++g;
   return g;
-}
-
-// ---------------------------------------------------------------- sweeps --
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_sweeps(DevGrids G, DevDomain DX, DevDomain DV, DevOp op,
-                                                   const T* __restrict__ u, T* __restrict__ W,
-                                                   T* __restrict__ Rr, int B) {
-  const int64_t total = G.off[G.n];
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (idx >= total) return;
-  const int g = locate(G, idx);
-  const int nx = G.nx[g], nv = G.nv[g];
-  const int64_t loc = idx - G.off[g];
-  const int64_t plane = int64_t(nx) * nv;
-  const int s = int(loc / plane);
-  const int64_t rem = loc - int64_t(s) * plane;
-  const int x = int(rem / nv), v = int(rem - int64_t(x) * nv);
-  const T* ub = u + int64_t(b) * total + G.off[g] + int64_t(s) * plane;
-  {
-    const int Sv = DV.S;
-    const int64_t lo = DV.lev_off[G.lv[g] - DV.lmin] + int64_t(v) * Sv;
-    const int32_t* nb = DV.nbr + lo;
-    T un[kMaxS];
-#pragma unroll
-    for (int e = 0; e < kMaxS; ++e) un[e] = e < Sv ? ub[int64_t(x) * nv + nb[e]] : T(0);
-    const T* vals = fvals<T>(DV);
-    for (int j = 0; j < op.nvg; ++j) {
-      const T* fv = vals + int64_t(op.vg_fac[j]) * DV.fac_stride + lo;
-      T acc = 0;
-#pragma unroll
-      for (int e = 0; e < kMaxS; ++e)
-        if (e < Sv) acc += fv[e] * un[e];
-      W[(int64_t(j) * B + b) * total + idx] = acc;
-    }
-  }
-  if (Rr) {
-    const int Sx = DX.S;
-    const int64_t lo = DX.lev_off[G.lx[g] - DX.lmin] + int64_t(x) * Sx;
-    const int32_t* nb = DX.nbr + lo;
-    T un[kMaxS];
-#pragma unroll
-    for (int e = 0; e < kMaxS; ++e) un[e] = e < Sx ? ub[int64_t(nb[e]) * nv + v] : T(0);
-    const T* vals = fvals<T>(DX);
-    for (int m = 0; m < op.nxg; ++m) {
-      const T* fx = vals + int64_t(op.xg_fac[m]) * DX.fac_stride + lo;
-      T acc = 0;
-#pragma unroll
-      for (int e = 0; e < kMaxS; ++e)
-        if (e < Sx) acc += fx[e] * un[e];
-      Rr[(int64_t(m) * B + b) * total + idx] = acc;
-    }
-  }
-}
-
-// One step of both scans.  blockIdx.z = 0: lower scan into grid `step`;
-// blockIdx.z = 1: upper scan into grid n-1-step.  blockIdx.y = group*B + b.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_scan(DevGrids G, DevDomain DX, DevDomain DV, int ngroups_lo,
-                                                 int ngroups_up, T* __restrict__ Z, T* __restrict__ Q,
-                                                 const T* __restrict__ Rr, int step, int B) {
-  const int64_t total = G.off[G.n];
-  const bool lower = blockIdx.z == 0;
-  const int gb = blockIdx.y;
-  if (lower && gb >= ngroups_lo * B) return;
-  if (!lower && gb >= ngroups_up * B) return;
-  const int i = lower ? step : G.n - 1 - step;
-  const int src = lower ? i - 1 : i + 1;
-  const int nx = G.nx[i], nv = G.nv[i];
-  const int64_t plane = int64_t(nx) * nv;
-  const int64_t loc = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (loc >= int64_t(G.R) * plane) return;
-  const int s = int(loc / plane);
-  const int64_t rem = loc - int64_t(s) * plane;
-  const int x = int(rem / nv), v = int(rem - int64_t(x) * nv);
-  const int nvs = G.nv[src];
-  const int64_t splane = int64_t(G.nx[src]) * nvs;
-  if (lower) {
-    // out(lx, lv) += sum_parents(x) w sum_children(v) w Z(lx-1, lv+1)
-    const T* in = Z + int64_t(gb) * total + G.off[src] + int64_t(s) * splane;
-    const int64_t po = DX.par_off[G.lx[i] - DX.lmin] + 2 * int64_t(x);
-    const int Sv = DV.S;
-    const int64_t co = DV.lev_off[G.lv[i] - DV.lmin] + int64_t(v) * Sv;
-    T acc = 0;
-    for (int k = 0; k < 2; ++k) {
-      const double wx = DX.parw[po + k];
-      if (wx == 0.0) continue;
-      const T* row = in + int64_t(DX.par[po + k]) * nvs;
-      T a = 0;
-      for (int e = 0; e < Sv; ++e) a += T(DV.chiw[co + e]) * row[DV.chi[co + e]];
-      acc += T(wx) * a;
-    }
-    Z[int64_t(gb) * total + G.off[i] + loc] += acc;
-  } else {
-    // out(lx, lv) = sum_children(x) w sum_parents(v) w (Q + Rr)(lx+1, lv-1)
-    // the last grid has no upper partners: its Q is zero and never stored
-    const bool top = src == G.n - 1;
-    const T* q = Q + int64_t(gb) * total + G.off[src] + int64_t(s) * splane;
-    const T* r = Rr + int64_t(gb) * total + G.off[src] + int64_t(s) * splane;
-    const int Sx = DX.S;
-    const int64_t co = DX.lev_off[G.lx[i] - DX.lmin] + int64_t(x) * Sx;
-    const int64_t po = DV.par_off[G.lv[i] - DV.lmin] + 2 * int64_t(v);
-    const int32_t p0 = DV.par[po], p1 = DV.par[po + 1];
-    const T w0 = T(DV.parw[po]), w1 = T(DV.parw[po + 1]);
-    T acc = 0;
-    for (int e = 0; e < Sx; ++e) {
-      const double wx = DX.chiw[co + e];
-      if (wx == 0.0) continue;
-      const int64_t rowo = int64_t(DX.chi[co + e]) * nvs;
-      T a0 = r[rowo + p0], a1 = r[rowo + p1];
-      if (!top) {
-        a0 += q[rowo + p0];
-        a1 += q[rowo + p1];
-      }
-      acc += T(wx) * (w0 * a0 + w1 * a1);
-    }
-    Q[int64_t(gb) * total + G.off[i] + loc] = acc;
-  }
-}
-
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_final(DevGrids G, GridPts P, DevDomain DX, DevDomain DV, DevOp op,
-                                                  const T* __restrict__ Z, const T* __restrict__ Q,
-                                                  T* __restrict__ y, int B) {
-  const int64_t npts = P.poff[G.n];
-  const int64_t pidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (pidx >= npts) return;
-  int g = 0;
-  while (g + 1 < G.n && pidx >= P.poff[g + 1]) ++g;
-  const int nx = G.nx[g], nv = G.nv[g];
-  const int64_t p = pidx - P.poff[g];
-  const int x = int(p / nv), v = int(p - int64_t(x) * nv);
-  const int64_t plane = int64_t(nx) * nv;
-  const int64_t total = G.off[G.n];
-  const int Rin = op.Rin, Rout = op.Rout;
-  T acc[kMaxR];
-#pragma unroll
-  for (int s = 0; s < kMaxR; ++s) acc[s] = 0;
-  const T* tm = tmats<T>(op);
-  {
-    const int Sx = DX.S;
-    const int64_t lo = DX.lev_off[G.lx[g] - DX.lmin] + int64_t(x) * Sx;
-    int32_t nb[kMaxS];
-#pragma unroll
-    for (int e = 0; e < kMaxS; ++e) nb[e] = e < Sx ? DX.nbr[lo + e] : 0;
-    const T* vals = fvals<T>(DX);
-    for (int k = 0; k < op.nterms; ++k) {
-      const T* fx = vals + int64_t(op.term_xf[k]) * DX.fac_stride + lo;
-      const T* zb = Z + (int64_t(op.term_vg[k]) * B + b) * total + G.off[g] + v;
-      for (int s2 = 0; s2 < Rin; ++s2) {
-        T t = 0;
-#pragma unroll
-        for (int e = 0; e < kMaxS; ++e)
-          if (e < Sx) t += fx[e] * zb[int64_t(s2) * plane + int64_t(nb[e]) * nv];
-        for (int s = 0; s < Rout; ++s) acc[s] += tm[(int64_t(k) * Rout + s) * Rin + s2] * t;
-      }
-    }
-  }
-  if (Q && g + 1 < G.n) {  // the last grid has no upper partners
-    const int Sv = DV.S;
-    const int64_t lo = DV.lev_off[G.lv[g] - DV.lmin] + int64_t(v) * Sv;
-    int32_t nb[kMaxS];
-#pragma unroll
-    for (int e = 0; e < kMaxS; ++e) nb[e] = e < Sv ? DV.nbr[lo + e] : 0;
-    const T* vals = fvals<T>(DV);
-    for (int k = 0; k < op.nterms; ++k) {
-      const T* fv = vals + int64_t(op.term_vf[k]) * DV.fac_stride + lo;
-      const T* qb = Q + (int64_t(op.term_xg[k]) * B + b) * total + G.off[g] + int64_t(x) * nv;
-      for (int s2 = 0; s2 < Rin; ++s2) {
-        T t = 0;
-#pragma unroll
-        for (int e = 0; e < kMaxS; ++e)
-          if (e < Sv) t += fv[e] * qb[int64_t(s2) * plane + nb[e]];
-        for (int s = 0; s < Rout; ++s) acc[s] += tm[(int64_t(k) * Rout + s) * Rin + s2] * t;
-      }
-    }
-  }
-  T* yb = y + int64_t(b) * (int64_t(Rout) * npts) + int64_t(Rout) * P.poff[g] + p;
-  for (int s = 0; s < Rout; ++s) yb[int64_t(s) * plane] = acc[s];
 }
 
 // ------------------------------------------------------------- transfers --
@@ -549,37 +360,6 @@ __global__ void k_spread(DevGrids G, int R, const double* __restrict__ m, double
 // ================================================================ launchers =
 static inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 #define LAUNCH_CHECK() SGDG_CHECK_HIP(hipGetLastError())
-
-template <class T>
-void KernelsT<T>::sweeps(const DevGrids& G, const DevDomain& DX, const DevDomain& DV, const DevOp& op, const T* u,
-                         T* W, T* Rr, int B, hipStream_t s) {
-  const int64_t total = G.off[G.n];
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_sweeps<T>, dim3(nblk(total), B), dim3(kBlock), 0, s, G, DX, DV, op, u, W, Rr, B);
-  LAUNCH_CHECK();
-}
-
-template <class T>
-void KernelsT<T>::scan_step(const DevGrids& G, const DevDomain& DX, const DevDomain& DV, const DevOp& op, T* Z, T* Q,
-                            const T* Rr, int step, int B, hipStream_t s) {
-  const int i_lo = step, i_up = G.n - 1 - step;
-  const int64_t n_lo = int64_t(G.R) * G.nx[i_lo] * G.nv[i_lo];
-  const int64_t n_up = int64_t(G.R) * G.nx[i_up] * G.nv[i_up];
-  const int64_t n = n_lo > n_up ? n_lo : n_up;
-  const int gy = (op.nvg > op.nxg ? op.nvg : op.nxg) * B;
-  hipLaunchKernelGGL(k_scan<T>, dim3(nblk(n), gy, Q ? 2 : 1), dim3(kBlock), 0, s, G, DX, DV, op.nvg, op.nxg, Z, Q,
-                     Rr, step, B);
-  LAUNCH_CHECK();
-}
-
-template <class T>
-void KernelsT<T>::final_(const DevGrids& G, const GridPts& P, const DevDomain& DX, const DevDomain& DV,
-                         const DevOp& op, const T* Z, const T* Q, T* y, int B, hipStream_t s) {
-  const int64_t npts = P.poff[G.n];
-  if (npts == 0) return;
-  hipLaunchKernelGGL(k_final<T>, dim3(nblk(npts), B), dim3(kBlock), 0, s, G, P, DX, DV, op, Z, Q, y, B);
-  LAUNCH_CHECK();
-}
 
 template <class T>
 void KernelsT<T>::restrict_x(const DevGrids& Go, const DevGrids& Gi, const DevDomain& DX, const T* in, T* out,

@@ -12,6 +12,7 @@
 #include <functional>
 #include <stdexcept>
 
+#include "fused.h"
 #include "kernels.h"
 #include "sgdg_internal.h"
 
@@ -198,19 +199,27 @@ extern "C" void sgdg_grid_destroy(sgdg_grid g) { delete g; }
 
 // --------------------------------------------------------------------- ops --
 struct DomDev {
-  DevBuf nbr, par, parw, chi, chiw, vals, vals32;
+  DevBuf nbr, par, parw, chi, chiw, vals, vals32, wide, rvals, rvals32;
   DevDomain d;
 };
 
 struct OpDev {
   TermList host;
-  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf;
+  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs;
   DevOp op;
+};
+
+// Box tiling of a grid set for the fused kernel (cached per set and precision).
+struct ItemTable {
+  DevBuf buf;
+  int n = 0;
+  int max_stage = 0;
+  int max_tab = 0;
 };
 
 template <class T>
 struct Work {  // scratch of one precision
-  DevBuf W, Rr, Q;            // operator scans
+  DevBuf Pt, Qt;              // partner-sum scans on the lower diagonal
   DevBuf ctb, ctx, ctw, cttmp, ctV, ctin;  // CT inner solves
   DevBuf r32, z32, a32, b32;  // conversions
 };
@@ -234,7 +243,8 @@ struct sgdg_ops_s {
   // rhs
   DevBuf rhs_a, rhs_b, rhs_c, rhs_d, rhs_w;
   int64_t inner_iters = 0;
-  // event timing of the operator kernels: slot 0 sweeps, 1 scan steps, 2 final
+  std::map<std::string, std::unique_ptr<ItemTable>> items;
+  // event timing of the operator kernels: slot 0 level scans, 1 fused tiles, 2 unused
   bool prof = false;
   struct Ev {
     hipEvent_t a, b;
@@ -329,6 +339,30 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   for (size_t i = 0; i < vals.size(); ++i) v32[i] = float(vals[i]);
   d.vals = upload(dd.vals, vals);
   d.vals32 = upload(dd.vals32, v32);
+  // restricted stencils
+  const int W = int(D.woff.size());
+  d.W = W;
+  std::vector<int32_t> wide;
+  int64_t wo = 0;
+  for (int l = D.lmin; l <= D.lmax; ++l) {
+    d.wlev_off[l - D.lmin] = wo;
+    const int64_t n = D.L(l).n;
+    if (l < D.lmax) wide.insert(wide.end(), D.wide_idx[l - D.lmin].begin(), D.wide_idx[l - D.lmin].end());
+    else wide.insert(wide.end(), size_t(n) * W, 0);
+    wo += n * W;
+  }
+  d.wide = upload(dd.wide, wide);
+  d.rstride = wo;
+  std::vector<double> rv(nf * wo, 0.0);
+  for (size_t f = 0; f < nf; ++f)
+    for (int l = D.lmin; l < D.lmax; ++l) {
+      const auto& src = D.rvalues[f][l - D.lmin];
+      std::copy(src.begin(), src.end(), rv.begin() + f * wo + d.wlev_off[l - D.lmin]);
+    }
+  std::vector<float> rv32(rv.size());
+  for (size_t i = 0; i < rv.size(); ++i) rv32[i] = float(rv[i]);
+  d.rvals = upload(dd.rvals, rv);
+  d.rvals32 = upload(dd.rvals32, rv32);
 }
 
 static void upload_op(OpDev& od) {
@@ -356,7 +390,24 @@ static void upload_op(OpDev& od) {
       tm32.push_back(float(t.tm[i]));
     }
   }
+  std::vector<int> vgt, vgs(vgf.size() + 1, 0), xgt, xgs(xgf.size() + 1, 0);
+  for (size_t j = 0; j < vgf.size(); ++j) {
+    vgs[j] = int(vgt.size());
+    for (size_t k = 0; k < vg.size(); ++k)
+      if (vg[k] == int(j)) vgt.push_back(int(k));
+  }
+  vgs[vgf.size()] = int(vgt.size());
+  for (size_t m = 0; m < xgf.size(); ++m) {
+    xgs[m] = int(xgt.size());
+    for (size_t k = 0; k < xg.size(); ++k)
+      if (xg[k] == int(m)) xgt.push_back(int(k));
+  }
+  xgs[xgf.size()] = int(xgt.size());
   DevOp& op = od.op;
+  op.vg_terms = upload(od.vgt, vgt);
+  op.vg_start = upload(od.vgs, vgs);
+  op.xg_terms = upload(od.xgt, xgt);
+  op.xg_start = upload(od.xgs, xgs);
   op.Rin = L.Rin;
   op.Rout = L.Rout;
   op.nterms = int(L.terms.size());
@@ -439,8 +490,13 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   for (int side = 0; side < 2; ++side) {
     DomainData& D = side == 0 ? o->X : o->V;
     D.values.assign(D.factors.size(), {});
+    D.rvalues.assign(D.factors.size(), {});
+    build_wide_tables(D);
 #pragma omp parallel for schedule(dynamic)
-    for (int f = 0; f < int(D.factors.size()); ++f) assemble_factor(D, f);
+    for (int f = 0; f < int(D.factors.size()); ++f) {
+      assemble_factor(D, f);
+      restrict_factor(D, f);
+    }
   }
   const int mfx = o->dx.d.mass_fac, mfv = o->dv.d.mass_fac;
   upload_domain(o->X, o->dx);
@@ -473,27 +529,138 @@ Work<double>& work<double>(sgdg_ops o) { return o->w64; }
 template <>
 Work<float>& work<float>(sgdg_ops o) { return o->w32; }
 
-// y = Op u on grid set G (G.R == op.Rin); full cross-grid coupling unless diag_only.
+// Box shape of one grid for the fused kernel: x-box and v-box sizes per axis,
+// at most fused_points_per_block() outputs and a bounded LDS stage.
+static void choose_boxes(int d, int mx, int mv, int R, int elem, int* xs, int* vs) {
+  const int nthr = fused_threads(), rows = fused_rows_per_thread();
+  const int bx = d == 1 ? 32 : (d == 2 ? 8 : 4);
+  const size_t lds_cap = 60 * 1024;
+  for (int a = 0; a < 3; ++a) {
+    xs[a] = a < d ? std::min(bx, mx) : 1;
+    vs[a] = 1;
+  }
+  auto fits = [&](const int* v) {
+    size_t nvb = 1, nvh = 1, nxh = 1, nx = 1;
+    for (int a = 0; a < d; ++a) {
+      nvb *= v[a];
+      nvh *= v[a] + 2;
+      nxh *= xs[a] + 2;
+      nx *= xs[a];
+    }
+    if (nvb > size_t(nthr)) return false;
+    if (nx > size_t(rows) * (nthr / nvb)) return false;
+    const size_t st = std::max(nxh * nvb, nx * nvh) * size_t(R) * elem;
+    const size_t tab = (nxh + 2 * nx + 2 * nvb + nvh) * sizeof(int);
+    return st + tab <= lds_cap;
+  };
+  // grow the v-box, fastest axis first, by doubling
+  bool grew = true;
+  while (grew) {
+    grew = false;
+    for (int a = d - 1; a >= 0; --a) {
+      if (vs[a] >= mv) continue;
+      int t[3] = {vs[0], vs[1], vs[2]};
+      t[a] = std::min(mv, vs[a] * 2);
+      if (fits(t)) {
+        vs[a] = t[a];
+        grew = true;
+      }
+    }
+  }
+}
+
+static ItemTable& item_table(sgdg_ops o, const std::string& key, const DevGrids& G, int elem) {
+  auto it = o->items.find(key);
+  if (it != o->items.end()) return *it->second;
+  auto tab = std::make_unique<ItemTable>();
+  std::vector<FusedItem> items;
+  const int d = o->X.dom.d;
+  int max_stage = 1, max_tab = 1;
+  for (int g = 0; g < G.n; ++g) {
+    const int mx = o->X.dom.axis_nodes(G.lx[g]), mv = o->V.dom.axis_nodes(G.lv[g]);
+    int xs[3], vs[3];
+    choose_boxes(d, mx, mv, G.R, elem, xs, vs);
+    int nbx[3] = {1, 1, 1}, nbv[3] = {1, 1, 1};
+    int64_t nx_h = 1, nv_b = 1, nx_b = 1, nv_h = 1;
+    for (int a = 0; a < d; ++a) {
+      nbx[a] = (mx + xs[a] - 1) / xs[a];
+      nbv[a] = (mv + vs[a] - 1) / vs[a];
+      nx_h *= xs[a] + 2;
+      nx_b *= xs[a];
+      nv_b *= vs[a];
+      nv_h *= vs[a] + 2;
+    }
+    max_stage = std::max<int64_t>(max_stage, std::max(nx_h * nv_b, nx_b * nv_h) * G.R);
+    max_tab = std::max<int64_t>(max_tab, nx_h + 2 * nx_b + 2 * nv_b + nv_h);
+    for (int i0 = 0; i0 < nbx[0]; ++i0)
+      for (int i1 = 0; i1 < nbx[1]; ++i1)
+        for (int i2 = 0; i2 < nbx[2]; ++i2)
+          for (int j0 = 0; j0 < nbv[0]; ++j0)
+            for (int j1 = 0; j1 < nbv[1]; ++j1)
+              for (int j2 = 0; j2 < nbv[2]; ++j2) {
+                FusedItem f{};
+                f.grid = g;
+                const int ix[3] = {i0, i1, i2}, iv[3] = {j0, j1, j2};
+                for (int a = 0; a < 3; ++a) {
+                  f.xb[a] = a < d ? ix[a] * xs[a] : 0;
+                  f.xs[a] = a < d ? std::min(xs[a], mx - f.xb[a]) : 1;
+                  f.vb[a] = a < d ? iv[a] * vs[a] : 0;
+                  f.vs[a] = a < d ? std::min(vs[a], mv - f.vb[a]) : 1;
+                }
+                items.push_back(f);
+              }
+  }
+  upload(tab->buf, items);
+  tab->n = int(items.size());
+  tab->max_stage = max_stage;
+  tab->max_tab = max_tab;
+  ItemTable& ref = *tab;
+  o->items[key] = std::move(tab);
+  return ref;
+}
+
+// y = Op u on grid set G (G.R == op.Rin).  With full coupling the partner sums
+// of the lower diagonal Gl are scanned first; diag_only applies the blocks A_{l,l}.
 template <class T>
 static void apply_on(sgdg_ops o, const DevOp& op, const DevGrids& G, bool diag_only, const T* u, T* y, int B,
-                     hipStream_t s) {
+                     hipStream_t s, const char* set_name = "up") {
   Work<T>& w = work<T>(o);
-  const int64_t total = G.off[G.n];
-  const GridPts P = points_of(G);
-  w.W.ensure(sizeof(T) * size_t(op.nvg) * B * total);
-  if (diag_only || G.n == 1) {
-    timed(o, 0, s, [&] { KernelsT<T>::sweeps(G, o->dx.d, o->dv.d, op, u, ptr<T>(w.W), nullptr, B, s); });
-    timed(o, 2, s, [&] { KernelsT<T>::final_(G, P, o->dx.d, o->dv.d, op, ptr<T>(w.W), nullptr, y, B, s); });
-    return;
+  sgdg_grid g = o->grid;
+  FusedArgs<T> A{};
+  A.G = G;
+  A.P = points_of(G);
+  A.DX = o->dx.d;
+  A.DV = o->dv.d;
+  A.op = op;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    A.mx[l] = g->x.axis_nodes(l);
+    A.mv[l] = g->v.axis_nodes(l);
   }
-  w.Rr.ensure(sizeof(T) * size_t(op.nxg) * B * total);
-  w.Q.ensure(sizeof(T) * size_t(op.nxg) * B * total);
-  timed(o, 0, s, [&] { KernelsT<T>::sweeps(G, o->dx.d, o->dv.d, op, u, ptr<T>(w.W), ptr<T>(w.Rr), B, s); });
-  timed(o, 1, s, [&] {
-    for (int step = 1; step < G.n; ++step)
-      KernelsT<T>::scan_step(G, o->dx.d, o->dv.d, op, ptr<T>(w.W), ptr<T>(w.Q), ptr<T>(w.Rr), step, B, s);
-  });
-  timed(o, 2, s, [&] { KernelsT<T>::final_(G, P, o->dx.d, o->dv.d, op, ptr<T>(w.W), ptr<T>(w.Q), y, B, s); });
+  A.xper = g->x.periodic;
+  A.vper = g->v.periodic;
+  for (int e = 0; e < kMaxS; ++e)
+    for (int a = 0; a < 3; ++a) A.off[e][a] = e < o->X.st.S ? o->X.st.off[e][a] : 0;
+  const bool full = !diag_only && G.n > 1;
+  A.diag_only = full ? 0 : 1;
+  A.B = B;
+  A.u = u;
+  A.y = y;
+  if (full) {
+    A.Gl = g->make(g->low, G.R);
+    const int64_t lt = A.Gl.off[A.Gl.n];
+    w.Pt.ensure(sizeof(T) * std::max(1, op.nvg) * size_t(B) * lt);
+    w.Qt.ensure(sizeof(T) * std::max(1, op.nxg) * size_t(B) * lt);
+    A.Pt = ptr<T>(w.Pt);
+    A.Qt = ptr<T>(w.Qt);
+  }
+  const std::string key = std::string(set_name) + "/R" + std::to_string(G.R) + "/e" + std::to_string(sizeof(T));
+  ItemTable& tab = item_table(o, key, G, int(sizeof(T)));
+  A.items = ptr<FusedItem>(tab.buf);
+  A.nitems = tab.n;
+  A.max_stage = tab.max_stage;
+  A.max_tab = tab.max_tab;
+  if (full) timed(o, 0, s, [&] { fused_scans<T>(A, o->X.dom.d, s); });
+  timed(o, 1, s, [&] { fused_tiles<T>(A, o->X.dom.d, s); });
 }
 
 extern "C" sgdg_status sgdg_apply_operator(sgdg_ops o, int kind, const void* u_dev, void* y_dev, sgdg_dtype t,
@@ -644,7 +811,7 @@ static void ct_apply(sgdg_ops o, const T* r, T* z, const sgdg_precond_opts& po, 
   KernelsT<T>::copy(nup, r, b, s);
   KernelsT<T>::restrict_x(Glow, Gup, o->dx.d, r, b + nup, s);
   const DevOp& op = o->ops[0].op;
-  auto A = [&](const T* in, T* out) { apply_on<T>(o, op, Gct, true, in, out, 1, s); };
+  auto A = [&](const T* in, T* out) { apply_on<T>(o, op, Gct, true, in, out, 1, s, "ct"); };
   auto M = [&](const T* in, T* out) {
     KernelsT<T>::minv(Gct, Pct, o->dx.d, o->dv.d, o->pinv_dev.as<double>(), po.mass_sweeps, in, out, nullptr,
                       nullptr, s);
@@ -960,9 +1127,12 @@ extern "C" sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double*
       apply_on<float>(o, op, G, false, a32, b32, 1, s);
       convert_f32_to_f64(n, b32, out, s);
     };
+    // FP32 grid problems cannot reach FP64 tolerances: solve them to >= 1e-5
+    sgdg_precond_opts pc32 = pc;
+    pc32.inner_rtol = std::max(pc.inner_rtol, 1e-5);
     auto P32 = [&](const double* in, double* out) {
       convert_f64_to_f32(n, in, a32, s);
-      ct_apply<float>(o, a32, b32, pc, s, &nan);
+      ct_apply<float>(o, a32, b32, pc32, s, &nan);
       convert_f32_to_f64(n, b32, out, s);
     };
     double* rr = o->fr.as<double>();

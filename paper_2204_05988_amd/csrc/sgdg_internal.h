@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -95,6 +96,11 @@ struct DomainData {
   std::vector<const double*> field_src;    // caller pointers (identity for de-duplication)
   std::vector<FactorKey> factors;          // registry of factors
   std::vector<std::vector<std::vector<double>>> values;  // [factor][level-lmin][n*S]
+  // restricted stencils E_{l+1,l}^T X_{l+1}: coarse node P couples to the fine
+  // nodes 2P + o, o in woff (sums of two Kuhn offsets); levels lmin..lmax-1
+  std::vector<std::array<int, 3>> woff;
+  std::vector<std::vector<int32_t>> wide_idx;             // [level-lmin][n*W] fine node index
+  std::vector<std::vector<std::vector<double>>> rvalues;  // [factor][level-lmin][n*W]
   int field_id(const double* src, int64_t n);
   int factor_id(const FactorKey& k);
   const LevelTables& L(int l) const { return lev[l - lmin]; }
@@ -114,6 +120,8 @@ struct TermList {
 // Host-side construction (mesh.cpp, assembly.cpp, terms.cpp).
 void build_domain_tables(DomainData& D);
 void assemble_factor(DomainData& D, int fid);  // all levels of one factor
+void build_wide_tables(DomainData& D);          // woff and wide_idx
+void restrict_factor(DomainData& D, int fid);   // rvalues of one factor
 struct ProblemIn {
   const sgdg_problem* p;
   int d, r;
@@ -136,6 +144,12 @@ struct DevDomain {
   const float* vals32 = nullptr;      // same, FP32
   int64_t fac_stride = 0;             // elements per factor
   int mass_fac = -1;                  // plain mass factor (Jacobi / Chebyshev preconditioner)
+  int W = 0;                          // restricted-stencil width
+  int64_t wlev_off[kMaxLevels] = {};  // start of level l in the [n][W] tables
+  const int32_t* wide = nullptr;      // fine node of each restricted slot
+  const double* rvals = nullptr;      // [factor][levels [n][W]] FP64
+  const float* rvals32 = nullptr;
+  int64_t rstride = 0;                // elements per factor
 };
 
 struct DevGrids {
@@ -155,6 +169,10 @@ struct DevOp {
   const float* term_tm32 = nullptr;
   const int* vg_fac = nullptr;       // v factor of each V group
   const int* xg_fac = nullptr;       // x factor of each X group
+  const int* vg_terms = nullptr;     // term indices ordered by V group
+  const int* vg_start = nullptr;     // [nvg + 1]
+  const int* xg_terms = nullptr;     // term indices ordered by X group
+  const int* xg_start = nullptr;     // [nxg + 1]
 };
 
 // Device buffer helper.
