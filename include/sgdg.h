@@ -195,6 +195,7 @@ typedef struct {
   int mixed_precision;  /* 1: FP64 refinement around an FP32 inner FGMRES (FP32 applies + FP32 CT) */
   double inner_outer_rtol; /* mixed precision: tolerance of each FP32 correction solve */
   sgdg_precond_opts pc;
+  int use_graph;          /* 1: replay each grid-problem GMRES cycle from a captured hipGraph */
 } sgdg_solve_opts;
 
 typedef struct {
@@ -213,6 +214,31 @@ typedef struct {
  * SGDG_E_NAN if a residual norm is not finite.  Synchronises s. */
 sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
                              sgdg_solve_stats* st, hipStream_t s);
+
+/* ------------------------------------------------------ batched problems -- */
+
+/* A batch of independent strip problems (same dimension and time degree,
+ * any levels and coefficients), solved in lockstep: every device launch
+ * covers all problems (work tables map blocks to problem, grid and tile), so
+ * uneven component grids and uneven problems share launches.  Batch vectors
+ * are the concatenation of the problems' vectors in the order given. */
+typedef struct sgdg_batch_s* sgdg_batch;
+
+/* ops: n handles (n >= 1) that must outlive the batch.  SGDG_E_ARG if they
+ * differ in dimension or time degree or live on different devices. */
+sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch* out);
+/* offsets[i] = start of problem i in a batch vector, offsets[n] = total (n+1 entries). */
+sgdg_status sgdg_batch_layout(sgdg_batch b, int64_t* offsets);
+/* y = A^(delta) u for every problem (FP64 or FP32), one scan sequence and one
+ * tiled launch for the whole batch. */
+sgdg_status sgdg_batch_apply(sgdg_batch b, const void* u_dev, void* y_dev, sgdg_dtype t, hipStream_t s);
+/* Solves every problem's strip system in lockstep (FGMRES with the batched
+ * combination-technique preconditioner; mixed precision as in
+ * sgdg_solve_strip).  st receives the totals and the largest relative
+ * residual.  SGDG_E_NOCONV if any problem misses the tolerance. */
+sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
+                             sgdg_solve_stats* st, hipStream_t s);
+void sgdg_batch_destroy(sgdg_batch b);
 
 /* ------------------------------------------------------------ diagnostics -- */
 

@@ -1,0 +1,91 @@
+// Multi-problem device descriptors and work tables.
+//
+// Every device launch of the library works on a *batch* of independent strip
+// problems (one problem is a batch of one).  Vectors of a batch are the
+// concatenation of the problems' vectors; static per-problem descriptors live
+// in device memory and carry the problem's offsets into the concatenated
+// layouts, and every launch is driven by a work table that maps a block to
+// (problem, grid, tile) or (segment, chunk).
+#pragma once
+
+#include "sgdg_internal.h"
+
+namespace sgdg {
+
+// Static description of one problem's grid set for the operator kernels.
+struct ProbDesc {
+  DevGrids G;          // grid set (upper diagonal, or upper+lower for the grid problems)
+  DevGrids Gl;         // lower diagonal (scan arrays), same R
+  int64_t poff[kMaxGrids + 1];  // point offsets (nx*nv) of G
+  DevDomain DX, DV;
+  DevOp op;
+  int mx[kMaxLevels], mv[kMaxLevels];  // nodes per axis by level
+  int xper, vper;
+  int off[kMaxS][3];   // Kuhn stencil offsets
+  int diag_only;       // 1: diagonal blocks only (no scans, no partner sums)
+  int64_t u_off;       // start of this problem's vector in the concatenated layout
+  int64_t y_off;       // start of its output vector
+  int64_t pt_off, qt_off;  // start of its scan arrays
+};
+
+// A box of x-nodes times a box of v-nodes of one grid of one problem.
+struct FusedItem {
+  int prob, grid;
+  int xb[3], xs[3];
+  int vb[3], vs[3];
+};
+
+// One block of a scan step: target lower grid of one problem, one side.
+struct ScanItem {
+  int prob, side;      // side 0: lower partners (Pt), 1: upper partners (Qt)
+  int lg;              // target lower grid
+  int64_t start;       // first element of the block in the target
+};
+
+template <class T>
+struct FusedCall {
+  const ProbDesc* descs;
+  const FusedItem* items;
+  const ScanItem* sitems;
+  int nitems;
+  int max_stage, max_tab;  // LDS elements / ints per block
+  int B;                   // vectors per problem
+  int64_t u_bstride, y_bstride, pt_bstride, qt_bstride;  // batch strides
+  const T* u;
+  T* y;
+  T* Pt;
+  T* Qt;
+};
+
+// A contiguous segment of a concatenated vector: one component grid of one
+// problem (grid problems of the combination technique) or one whole problem
+// (strip FGMRES).  The CT fields describe the transfers.
+struct SegInfo {
+  int prob, lx, lv, nx, nv, R;
+  int64_t off;          // start in the segment layout
+  int64_t len;          // elements
+  int chunk0, nchunk;   // reduction chunks owned by the segment
+  // combination technique (lower segments: restriction source; upper: combination partner)
+  int kind;             // 0 upper grid, 1 lower grid, 2 whole problem
+  int64_t src_off;      // upper: start of the grid in the residual (upper-diagonal) layout;
+                        // lower: start of its source upper grid (lx+1, lv) there
+  int64_t low_off;      // upper with lx > lmin: start of the lower grid (lx-1, lv) in the CT layout, else -1
+  int nx_src;           // lower: nx of the source upper grid; upper: nx of the lower partner
+  int S;                // stencil size of the x-domain
+  const int32_t* xchi;  // x children table of level lx (lower segments)
+  const double* xchiw;
+  const int32_t* xpar;  // x parent table of level lx (upper segments)
+  const double* xparw;
+  const double* mxd;    // x mass factor rows of level lx ([nx][Sx], slot 0 = diagonal)
+  const double* mvd;    // v mass factor rows of level lv ([nv][Sv])
+  int Sx, Sv;
+  double pinv[kMaxR * kMaxR];
+};
+
+struct BlockRef {  // one block of a segmented launch
+  int seg, chunk;
+};
+
+constexpr int kChunk = 4096;  // elements per block in segmented launches
+
+}  // namespace sgdg

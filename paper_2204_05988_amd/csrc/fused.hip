@@ -70,12 +70,13 @@ __device__ __forceinline__ int node_of(const int* c, int m, int periodic_cells) 
 // Threads own one box column (col = tid % nvb) and a strided set of rows, so
 // stencil indices and v-factor values are loaded once per column and group.
 template <class T, int D, int R>
-__global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
+__global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);  // Kuhn stencil size
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const FusedItem it = A.items[blockIdx.x];
+  const FusedItem it = C.items[blockIdx.x];
   const int b = blockIdx.y;
+  const ProbDesc& A = C.descs[it.prob];
   const DevGrids& G = A.G;
   const int g = it.grid;
   const int lx = G.lx[g], lv = G.lv[g];
@@ -86,8 +87,9 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
   constexpr int Rin = R, Rout = R;
   const int64_t plane = int64_t(nx) * nv;
   const int64_t total = G.off[G.n];
-  const T* ug = A.u + int64_t(b) * total + G.off[g];
+  const T* ug = C.u + int64_t(b) * C.u_bstride + A.u_off + G.off[g];
   constexpr int SX = SS, SV = SS;
+  (void)total;
 
   int xs[3] = {1, 1, 1}, vs[3] = {1, 1, 1}, xh[3] = {1, 1, 1}, vh[3] = {1, 1, 1};
   int nxb = 1, nvb = 1, nxh = 1, nvh = 1;
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
   const bool has_p = !A.diag_only && g > 0;
   const bool has_q = !A.diag_only && g + 1 < G.n;
   // index tables
-  int* tab = reinterpret_cast<int*>(lds + A.max_stage);
+  int* tab = reinterpret_cast<int*>(lds + C.max_stage);
   int* xh_node = tab;
   int* xb_halo = xh_node + nxh;
   int* xb_node = xb_halo + nxb;
@@ -198,7 +200,8 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
       T fvv[SS];
 #pragma unroll
       for (int e = 0; e < SS; ++e) fvv[e] = vf[e];
-      const T* pt = has_p ? A.Pt + (int64_t(j) * A.B + b) * ltotal + A.Gl.off[gl] + vi : nullptr;
+      const T* pt = has_p ? C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + A.Gl.off[gl] + vi
+                          : nullptr;
       for (int r = rg; r < nxh; r += nrg) {
         const int xi = xh_node[r];
 #pragma unroll
@@ -221,22 +224,27 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
     }
     __syncthreads();
     if (active) {
-      for (int kk = op.vg_start[j]; kk < op.vg_start[j + 1]; ++kk) {
-        const int k = op.vg_terms[kk];
-        const T* xf = xvals + int64_t(op.term_xf[k]) * A.DX.fac_stride + xlo;
-        const T* tk = tm + int64_t(k) * Rout * Rin;
+      const int k0 = op.vg_start[j], k1 = op.vg_start[j + 1];
 #pragma unroll
-        for (int q = 0; q < kRows; ++q) {
-          const int r = rg + q * nrg;
-          if (r >= nxb) break;
-          const T* fr = xf + int64_t(xb_node[r]) * SX;
-          const int hb = xb_halo[r];
+      for (int q = 0; q < kRows; ++q) {
+        const int r = rg + q * nrg;
+        if (r >= nxb) break;
+        const int hb = xb_halo[r];
+        const int64_t xo = xlo + int64_t(xb_node[r]) * SX;
 #pragma unroll
-          for (int s2 = 0; s2 < R; ++s2) {
-            const T* l = lds + (s2 * nxh + hb) * nvb + col;
+        for (int s2 = 0; s2 < R; ++s2) {
+          // staged values of the x-neighbourhood, shared by every term of the group
+          const T* l = lds + (s2 * nxh + hb) * nvb + col;
+          T z[SS];
+#pragma unroll
+          for (int e = 0; e < SS; ++e) z[e] = l[dxh[e] * nvb];
+          for (int kk = k0; kk < k1; ++kk) {
+            const int k = op.vg_terms[kk];
+            const T* fr = xvals + int64_t(op.term_xf[k]) * A.DX.fac_stride + xo;
+            const T* tk = tm + int64_t(k) * R * R;
             T t = T(0);
 #pragma unroll
-            for (int e = 0; e < SS; ++e) t += fr[e] * l[dxh[e] * nvb];
+            for (int e = 0; e < SS; ++e) t += fr[e] * z[e];
 #pragma unroll
             for (int s = 0; s < R; ++s) acc[q][s] += tk[s * R + s2] * t;
           }
@@ -253,7 +261,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
     const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
     const int nst = nxb * nvh;
     for (int m = 0; m < op.nxg; ++m) {
-      const T* qt = A.Qt + (int64_t(m) * A.B + b) * ltotal + A.Gl.off[g];
+      const T* qt = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g];
       for (int h = threadIdx.x; h < nst; h += kFB) {
         const int r = h / nvh, c = h - (h / nvh) * nvh;
         const int vn = vh_node[c];
@@ -300,7 +308,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedArgs<T> A) {
 
   // ---------------- store -------------------------------------------------
   if (active) {
-    T* yg = A.y + int64_t(b) * (int64_t(Rout) * A.P.poff[G.n]) + int64_t(Rout) * A.P.poff[g] + vi;
+    T* yg = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(Rout) * A.poff[g] + vi;
 #pragma unroll
     for (int q = 0; q < kRows; ++q) {
       const int r = rg + q * nrg;
@@ -322,30 +330,35 @@ template <> __device__ __forceinline__ const double* rv<double>(const DevDomain&
 template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.rvals32; }
 
 template <class T, int D>
-__global__ void __launch_bounds__(kFB) k_scan2(FusedArgs<T> A, int t) {
+__global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   constexpr int W = D == 1 ? 5 : (D == 2 ? 19 : 65);
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  const ScanItem si = C.sitems[blockIdx.x];
+  const ProbDesc& A = C.descs[si.prob];
   const DevGrids& G = A.G;
   const DevGrids& L = A.Gl;
-  const bool lower = blockIdx.z == 0;
+  const bool lower = si.side == 0;
   const int b = blockIdx.y;
   const DevOp& op = A.op;
-  const int lg = lower ? t : L.n - 1 - t;    // target lower grid
+  const int lg = si.lg;
   const int nxl = L.nx[lg], nvl = L.nv[lg];
   const int64_t lplane = int64_t(nxl) * nvl;
-  const int64_t loc = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t loc = si.start + threadIdx.x;
   if (loc >= int64_t(op.Rin) * lplane) return;
   const int s = int(loc / lplane);
   const int64_t rem = loc - int64_t(s) * lplane;
   const int x = int(rem / nvl), v = int(rem - int64_t(x) * nvl);
-  const int64_t total = G.off[G.n], ltotal = L.off[L.n];
+  const int64_t ltotal = L.off[L.n];
+  const T* ub = C.u + int64_t(b) * C.u_bstride + A.u_off;
+  T* Ptb = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off;
+  T* Qtb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off;
   T un[W];
   if (lower) {
     // source grid t (lx, lv); target (lx, lv-1); previous Pt_t on lower grid t-1 (lx-1, lv)
-    const int src = t;
+    const int src = lg;
     const int nv = G.nv[src];
     const int lvc = G.lv[src] - 1 - A.DV.lmin;  // level of v (coarse)
-    const T* us = A.u + int64_t(b) * total + G.off[src] + int64_t(s) * G.nx[src] * nv + int64_t(x) * nv;
+    const T* us = ub + G.off[src] + int64_t(s) * G.nx[src] * nv + int64_t(x) * nv;
     const int32_t* wi = A.DV.wide + A.DV.wlev_off[lvc] + int64_t(v) * W;
 #pragma unroll
     for (int o = 0; o < W; ++o) un[o] = us[wi[o]];
@@ -374,20 +387,20 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedArgs<T> A, int t) {
 #pragma unroll
       for (int o = 0; o < W; ++o) acc += r[o] * un[o];
       if (has_p) {
-        const T* pp = A.Pt + (int64_t(j) * A.B + b) * ltotal + L.off[src - 1] + int64_t(s) * pl;
+        const T* pp = Ptb + int64_t(j) * ltotal + L.off[src - 1] + int64_t(s) * pl;
         const T* r0 = pp + int64_t(p0) * nv;
         const T* r1 = pp + int64_t(p1) * nv;
 #pragma unroll
         for (int c = 0; c < SS; ++c) acc += cw[c] * (w0 * r0[ch[c]] + w1 * r1[ch[c]]);
       }
-      A.Pt[(int64_t(j) * A.B + b) * ltotal + L.off[lg] + loc] = acc;
+      Ptb[int64_t(j) * ltotal + L.off[lg] + loc] = acc;
     }
   } else {
     // source grid lg+1 (lx+1, lv-1); target lower lg (lx, lv-1); previous Qt on lower grid lg+1 (lx+1, lv-2)
     const int src = lg + 1;
     const int nv = G.nv[src];
     const int lxc = G.lx[src] - 1 - A.DX.lmin;  // level of x (coarse)
-    const T* us = A.u + int64_t(b) * total + G.off[src] + int64_t(s) * G.nx[src] * nv + v;
+    const T* us = ub + G.off[src] + int64_t(s) * G.nx[src] * nv + v;
     const int32_t* wi = A.DX.wide + A.DX.wlev_off[lxc] + int64_t(x) * W;
 #pragma unroll
     for (int o = 0; o < W; ++o) un[o] = us[int64_t(wi[o]) * nv];
@@ -418,50 +431,35 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedArgs<T> A, int t) {
 #pragma unroll
       for (int o = 0; o < W; ++o) acc += r[o] * un[o];
       if (has_q) {
-        const T* qq = A.Qt + (int64_t(m) * A.B + b) * ltotal + L.off[src] + int64_t(s) * ql;
+        const T* qq = Qtb + int64_t(m) * ltotal + L.off[src] + int64_t(s) * ql;
 #pragma unroll
         for (int c = 0; c < SS; ++c) {
           const T* row = qq + int64_t(ch[c]) * nvq;
           acc += cw[c] * (w0 * row[p0] + w1 * row[p1]);
         }
       }
-      A.Qt[(int64_t(m) * A.B + b) * ltotal + L.off[lg] + loc] = acc;
+      Qtb[int64_t(m) * ltotal + L.off[lg] + loc] = acc;
     }
   }
 }
 
 // ------------------------------------------------------------- launchers --
 template <class T>
-size_t fused_smem(const FusedArgs<T>& A, int d) {
-  (void)d;
-  return size_t(A.max_stage) * sizeof(T) + size_t(A.max_tab) * sizeof(int);
+void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, hipStream_t s) {
+  if (nsitems == 0) return;
+  dim3 grid(unsigned(nsitems), C.B);
+  if (d == 1) hipLaunchKernelGGL((k_scan2<T, 1>), grid, dim3(kFB), 0, s, C);
+  else if (d == 2) hipLaunchKernelGGL((k_scan2<T, 2>), grid, dim3(kFB), 0, s, C);
+  else hipLaunchKernelGGL((k_scan2<T, 3>), grid, dim3(kFB), 0, s, C);
+  SGDG_CHECK_HIP(hipGetLastError());
 }
 
 template <class T>
-void fused_scans(const FusedArgs<T>& A, int d, hipStream_t s) {
-  const DevOp& op = A.op;
-  if (!A.diag_only && A.G.n > 1) {
-    for (int t = 0; t + 1 < A.G.n; ++t) {
-      const int lo = t, up = A.Gl.n - 1 - t;
-      const int64_t n1 = int64_t(op.Rin) * A.Gl.nx[lo] * A.Gl.nv[lo];
-      const int64_t n2 = int64_t(op.Rin) * A.Gl.nx[up] * A.Gl.nv[up];
-      const int64_t n = n1 > n2 ? n1 : n2;
-      dim3 grid(unsigned((n + kFB - 1) / kFB), A.B, 2);
-      if (d == 1) hipLaunchKernelGGL((k_scan2<T, 1>), grid, dim3(kFB), 0, s, A, t);
-      else if (d == 2) hipLaunchKernelGGL((k_scan2<T, 2>), grid, dim3(kFB), 0, s, A, t);
-      else hipLaunchKernelGGL((k_scan2<T, 3>), grid, dim3(kFB), 0, s, A, t);
-      SGDG_CHECK_HIP(hipGetLastError());
-    }
-  }
-}
-
-template <class T>
-void fused_tiles(const FusedArgs<T>& A, int d, hipStream_t s) {
-  const size_t sm = fused_smem(A, d);
-  dim3 grid(unsigned(A.nitems), A.B);
-  const int R = A.op.Rin;
+void fused_tiles(const FusedCall<T>& C, int d, int R, hipStream_t s) {
+  const size_t sm = size_t(C.max_stage) * sizeof(T) + size_t(C.max_tab) * sizeof(int);
+  dim3 grid(unsigned(C.nitems), C.B);
 #define SGDG_FUSED_CASE(DD, RR) \
-  if (d == DD && R == RR) hipLaunchKernelGGL((k_fused<T, DD, RR>), grid, dim3(kFB), sm, s, A);
+  if (d == DD && R == RR) hipLaunchKernelGGL((k_fused<T, DD, RR>), grid, dim3(kFB), sm, s, C);
   SGDG_FUSED_CASE(1, 1) SGDG_FUSED_CASE(1, 2) SGDG_FUSED_CASE(1, 3)
   SGDG_FUSED_CASE(2, 1) SGDG_FUSED_CASE(2, 2) SGDG_FUSED_CASE(2, 3)
   SGDG_FUSED_CASE(3, 1) SGDG_FUSED_CASE(3, 2) SGDG_FUSED_CASE(3, 3)
@@ -469,12 +467,11 @@ void fused_tiles(const FusedArgs<T>& A, int d, hipStream_t s) {
   SGDG_CHECK_HIP(hipGetLastError());
 }
 
-template void fused_scans<double>(const FusedArgs<double>&, int, hipStream_t);
-template void fused_scans<float>(const FusedArgs<float>&, int, hipStream_t);
-template void fused_tiles<double>(const FusedArgs<double>&, int, hipStream_t);
-template void fused_tiles<float>(const FusedArgs<float>&, int, hipStream_t);
+template void fused_scan_step<double>(const FusedCall<double>&, int, int, hipStream_t);
+template void fused_scan_step<float>(const FusedCall<float>&, int, int, hipStream_t);
+template void fused_tiles<double>(const FusedCall<double>&, int, int, hipStream_t);
+template void fused_tiles<float>(const FusedCall<float>&, int, int, hipStream_t);
 
-int fused_points_per_block() { return kFB * kRows; }
 int fused_rows_per_thread() { return kRows; }
 int fused_threads() { return kFB; }
 

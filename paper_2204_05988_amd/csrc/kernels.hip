@@ -1,8 +1,17 @@
-// Device kernels of libsgdg for gfx950 (wave64): transfers between component
-// grids (embedding E and its transpose), the combination step, the inner
-// preconditioner, Krylov primitives (segmented dot products / updates with
-// FP64 accumulation, deterministic two-pass reductions), GMRES bookkeeping and
-// right-hand-side helpers.  The operator itself is applied by fused.hip.
+// Device kernels of libsgdg for gfx950 (wave64), all driven by segment tables:
+//  * Krylov primitives over segments (one component grid of one problem, or
+//    one whole problem): dot products of a block of basis vectors, fused
+//    multi-axpy with the norm of the result, per-segment scaling.  Reductions
+//    run in FP64 and in a fixed order (per-chunk partial sums, then per
+//    segment), so results are reproducible run to run.
+//  * GMRES bookkeeping, one thread per segment (Givens rotations, residual
+//    estimates, convergence and breakdown flags, back substitution).
+//  * The transfers of the combination technique (Algorithm 1): restriction of
+//    the residual in x to the lower diagonal, the combination step, and the
+//    preconditioner of the grid problems, the inverse of
+//    (Tt + delta Ct + Gt) (x) M^x (x) M^v with the mass matrices replaced by
+//    their diagonals.
+//  * Right-hand-side helpers of one strip.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -10,101 +19,15 @@
 namespace sgdg {
 
 constexpr int kBlock = 256;
-constexpr int kChunk = 4096;  // elements per block in segment reductions
+constexpr int kPer = kChunk / kBlock;
 
-template <class T> __device__ __forceinline__ const T* fvals(const DevDomain& D);
-template <> __device__ __forceinline__ const double* fvals<double>(const DevDomain& D) { return D.vals; }
-template <> __device__ __forceinline__ const float* fvals<float>(const DevDomain& D) { return D.vals32; }
-template <class T> __device__ __forceinline__ const T* tmats(const DevOp& op);
-template <> __device__ __forceinline__ const double* tmats<double>(const DevOp& op) { return op.term_tm; }
-template <> __device__ __forceinline__ const float* tmats<float>(const DevOp& op) { return op.term_tm32; }
-
-__device__ __forceinline__ int locate(const DevGrids& G, int64_t idx) {
-  int g = 0;
-  while (g + 1 < G.n && idx >= G.off[g + 1]) ++g;
-  return g;
-}
-
-// ------------------------------------------------------------- transfers --
-// lower grid g (lx, lv) <- upper grid g+1 (lx+1, lv)
-template <class T>
-__global__ void k_restrict_x(DevGrids Go, DevGrids Gi, DevDomain DX, const T* __restrict__ in, T* __restrict__ out) {
-  const int64_t total = Go.off[Go.n];
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int g = locate(Go, idx);
-  const int gi = g + 1;
-  const int nx = Go.nx[g], nv = Go.nv[g];
-  const int64_t loc = idx - Go.off[g];
-  const int64_t plane = int64_t(nx) * nv;
-  const int s = int(loc / plane);
-  const int64_t rem = loc - int64_t(s) * plane;
-  const int x = int(rem / nv), v = int(rem - int64_t(x) * nv);
-  const int S = DX.S;
-  const int64_t co = DX.lev_off[Go.lx[g] - DX.lmin] + int64_t(x) * S;
-  const T* src = in + Gi.off[gi] + int64_t(s) * int64_t(Gi.nx[gi]) * nv;
-  T acc = 0;
-  for (int e = 0; e < S; ++e) acc += T(DX.chiw[co + e]) * src[int64_t(DX.chi[co + e]) * nv + v];
-  out[idx] = acc;
-}
-
-template <class T>
-__global__ void k_combine(DevGrids Gu, DevGrids Gl, int lmin, DevDomain DX, const T* __restrict__ up,
-                          const T* __restrict__ low, T* __restrict__ out) {
-  const int64_t total = Gu.off[Gu.n];
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int g = locate(Gu, idx);
-  T val = up[idx];
-  if (Gu.lx[g] > lmin) {
-    const int gl = g - 1;  // lower grid (lx-1, lv) has index g-1 on the lower diagonal
-    const int nx = Gu.nx[g], nv = Gu.nv[g];
-    const int64_t loc = idx - Gu.off[g];
-    const int64_t plane = int64_t(nx) * nv;
-    const int s = int(loc / plane);
-    const int64_t rem = loc - int64_t(s) * plane;
-    const int x = int(rem / nv), v = int(rem - int64_t(x) * nv);
-    const int64_t po = DX.par_off[Gu.lx[g] - DX.lmin] + 2 * int64_t(x);
-    const T* src = low + Gl.off[gl] + int64_t(s) * int64_t(Gl.nx[gl]) * nv;
-    val -= T(DX.parw[po]) * src[int64_t(DX.par[po]) * nv + v] + T(DX.parw[po + 1]) * src[int64_t(DX.par[po + 1]) * nv + v];
-  }
-  out[idx] = val;
-}
-
-// Jacobi approximation of (Pinv (x) Mx^-1 (x) Mv^-1): y[s] = sum_s' Pinv[s][s'] x[s'] / (Dx Dv)
-template <class T>
-__global__ void k_minv_jacobi(DevGrids G, GridPts P, DevDomain DX, DevDomain DV, const double* __restrict__ pinv,
-                              const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t npts = P.poff[G.n];
-  const int64_t pidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (pidx >= npts) return;
-  int g = 0;
-  while (g + 1 < G.n && pidx >= P.poff[g + 1]) ++g;
-  const int nx = G.nx[g], nv = G.nv[g];
-  const int64_t p = pidx - P.poff[g];
-  const int xi = int(p / nv), vi = int(p - int64_t(xi) * nv);
-  const int64_t plane = int64_t(nx) * nv;
-  const int R = G.R;
-  const T dx = T(fvals<T>(DX)[int64_t(DX.mass_fac) * DX.fac_stride + DX.lev_off[G.lx[g] - DX.lmin] + int64_t(xi) * DX.S]);
-  const T dv = T(fvals<T>(DV)[int64_t(DV.mass_fac) * DV.fac_stride + DV.lev_off[G.lv[g] - DV.lmin] + int64_t(vi) * DV.S]);
-  const T sc = T(1) / (dx * dv);
-  const int64_t base = G.off[g] + p;
-  T in[kMaxR];
-  for (int s = 0; s < R; ++s) in[s] = x[base + s * plane];
-  for (int s = 0; s < R; ++s) {
-    T a = 0;
-    for (int s2 = 0; s2 < R; ++s2) a += T(pinv[s * R + s2]) * in[s2];
-    y[base + s * plane] = a * sc;
-  }
-}
-
-// ------------------------------------------------------- reductions -------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
 }
 
+// block-wide sum, valid in thread 0
 __device__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -114,24 +37,26 @@ __device__ double block_sum(double v, double* sh) {
   double r = 0;
   if (threadIdx.x == 0)
     for (int i = 0; i < int(blockDim.x >> 6); ++i) r += sh[i];
-  return r;  // valid in thread 0
+  return r;
 }
 
+// ------------------------------------------------------------ segments ----
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_seg_dots(Segs S, const T* __restrict__ V, int64_t vstride, int nvec,
-                                                     const T* __restrict__ w, double* __restrict__ partial,
-                                                     int nchunks) {
+__global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                     const T* __restrict__ V, int64_t vstride, int nvec,
+                                                     const T* __restrict__ w, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  const int seg = blockIdx.y, chunk = blockIdx.x;
-  const int64_t beg = S.off[seg] + int64_t(chunk) * kChunk;
-  const int64_t end = S.off[seg + 1];
-  constexpr int kPer = kChunk / kBlock;
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
+  const int64_t end = S.off + S.len;
   double wl[kPer];
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
     wl[t] = i < end ? double(w[i]) : 0.0;
   }
+  double* out = partial + int64_t(S.chunk0 + br.chunk) * nvec;
   for (int k = 0; k < nvec; ++k) {
     const T* vk = V + int64_t(k) * vstride;
     double acc = 0;
@@ -141,21 +66,22 @@ __global__ void __launch_bounds__(kBlock) k_seg_dots(Segs S, const T* __restrict
       if (i < end) acc += double(vk[i]) * wl[t];
     }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t(seg) * nchunks + chunk) * nvec + k] = acc;
+    if (threadIdx.x == 0) out[k] = acc;
   }
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_seg_axpy(Segs S, const T* __restrict__ V, int64_t vstride, int nvec,
+__global__ void __launch_bounds__(kBlock) k_seg_axpy(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                     const T* __restrict__ V, int64_t vstride, int nvec,
                                                      const double* __restrict__ coef, int cstride, T* __restrict__ w,
-                                                     double sign, double* __restrict__ partial, int nchunks) {
+                                                     double sign, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  const int seg = blockIdx.y, chunk = blockIdx.x;
-  const int64_t beg = S.off[seg] + int64_t(chunk) * kChunk;
-  const int64_t end = S.off[seg + 1];
-  constexpr int kPer = kChunk / kBlock;
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
+  const int64_t end = S.off + S.len;
+  const double* c = coef + int64_t(br.seg) * cstride;
   double nrm = 0;
-  const double* c = coef + int64_t(seg) * cstride;
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
@@ -169,16 +95,24 @@ __global__ void __launch_bounds__(kBlock) k_seg_axpy(Segs S, const T* __restrict
   }
   if (partial) {
     nrm = block_sum(nrm, sh);
-    if (threadIdx.x == 0) partial[int64_t(seg) * nchunks + chunk] = nrm;
+    if (threadIdx.x == 0) partial[S.chunk0 + br.chunk] = nrm;
   }
 }
 
 template <class T>
-__global__ void k_seg_scale(Segs S, const T* __restrict__ w, const double* __restrict__ scal, T* __restrict__ out) {
-  const int seg = blockIdx.y;
-  const int64_t i = S.off[seg] + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= S.off[seg + 1]) return;
-  out[i] = T(double(w[i]) * scal[seg]);
+__global__ void __launch_bounds__(kBlock) k_seg_scale(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                      const T* __restrict__ w, const double* __restrict__ scal,
+                                                      T* __restrict__ out) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
+  const int64_t end = S.off + S.len;
+  const double sc = scal[br.seg];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
+    if (i < end) out[i] = T(double(w[i]) * sc);
+  }
 }
 
 template <class T>
@@ -204,30 +138,17 @@ __global__ void k_f2d(int64_t n, const float* __restrict__ x, double* __restrict
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) y[i] = double(x[i]);
 }
-__global__ void k_addf2d(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += double(x[i]);
-}
-
-__global__ void k_finish(int nseg, int nvec, int nchunks, const double* __restrict__ partial, double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nseg * nvec) return;
-  const int seg = t / nvec, k = t - seg * nvec;
-  double a = 0;
-  for (int c = 0; c < nchunks; ++c) a += partial[(int64_t(seg) * nchunks + c) * nvec + k];
-  out[t] = a;
-}
 
 // ------------------------------------------------------ GMRES bookkeeping --
 __device__ __forceinline__ bool finite(double x) { return x == x && x - x == 0.0; }
 
-__global__ void k_gmres_start(int nseg, GmresState st, const double* __restrict__ partial, int nchunks, double tol,
-                              int first) {
+__global__ void k_gmres_start(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                              const double* __restrict__ partial, double tol, int first) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nseg) return;
   const int m = st.m;
   double s = 0;
-  for (int c = 0; c < nchunks; ++c) s += partial[int64_t(g) * nchunks + c];
+  for (int c = 0; c < segs[g].nchunk; ++c) s += partial[segs[g].chunk0 + c];
   const double beta = sqrt(s);
   if (first) st.bnorm[g] = beta;
   st.beta[g] = beta;
@@ -240,21 +161,22 @@ __global__ void k_gmres_start(int nseg, GmresState st, const double* __restrict_
   st.inv[g] = act ? 1.0 / beta : 0.0;
 }
 
-__global__ void k_gmres_proj(int nseg, GmresState st, const double* __restrict__ partial, int nchunks, int j) {
+__global__ void k_gmres_proj(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                             const double* __restrict__ partial, int j) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int nv = j + 1;
   if (t >= nseg * nv) return;
   const int g = t / nv, i = t - g * nv;
   const int m = st.m;
   double a = 0;
-  for (int c = 0; c < nchunks; ++c) a += partial[(int64_t(g) * nchunks + c) * nv + i];
+  for (int c = 0; c < segs[g].nchunk; ++c) a += partial[int64_t(segs[g].chunk0 + c) * nv + i];
   if (st.active[g] != 1) a = 0.0;
   st.hcol[int64_t(g) * (m + 1) + i] = a;
   st.H[int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1) + i] += a;
 }
 
-__global__ void k_gmres_givens(int nseg, GmresState st, const double* __restrict__ partial, int nchunks, int j,
-                               double tol) {
+__global__ void k_gmres_givens(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                               const double* __restrict__ partial, int j, double tol) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nseg) return;
   const int m = st.m;
@@ -263,7 +185,7 @@ __global__ void k_gmres_givens(int nseg, GmresState st, const double* __restrict
     return;
   }
   double s = 0;
-  for (int c = 0; c < nchunks; ++c) s += partial[int64_t(g) * nchunks + c];
+  for (int c = 0; c < segs[g].nchunk; ++c) s += partial[segs[g].chunk0 + c];
   const double hn = sqrt(s);
   double* H = st.H + int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1);
   double* cs = st.cs + int64_t(g) * m;
@@ -312,6 +234,84 @@ __global__ void k_gmres_lsq(int nseg, GmresState st) {
   }
 }
 
+// ---------------------------------------------- combination technique ----
+__device__ __forceinline__ void decode(const SegInfo& S, int64_t loc, int& s, int& x, int& v) {
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  s = int(loc / plane);
+  const int64_t rem = loc - int64_t(s) * plane;
+  x = int(rem / S.nv);
+  v = int(rem - int64_t(x) * S.nv);
+}
+
+// CT layout <- residual layout: upper grids copied, lower grids restricted in x
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_ct_gather(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                      const T* __restrict__ r, T* __restrict__ b) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t loc = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (loc >= S.len) return;
+    if (S.kind == 0) {
+      b[S.off + loc] = r[S.src_off + loc];
+    } else {
+      int s, x, v;
+      decode(S, loc, s, x, v);
+      const T* src = r + S.src_off + int64_t(s) * S.nx_src * S.nv + v;
+      const int32_t* c = S.xchi + int64_t(x) * S.Sx;
+      const double* cw = S.xchiw + int64_t(x) * S.Sx;
+      T acc = 0;
+      for (int e = 0; e < S.Sx; ++e) acc += T(cw[e]) * src[int64_t(c[e]) * S.nv];
+      b[S.off + loc] = acc;
+    }
+  }
+}
+
+// residual layout <- combination of the CT solution: dU_up - (E^x (x) I) dU_low
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_ct_combine(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                       const T* __restrict__ ct, T* __restrict__ z) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  if (S.kind != 0) return;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t loc = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (loc >= S.len) return;
+    T val = ct[S.off + loc];
+    if (S.low_off >= 0) {
+      int s, x, v;
+      decode(S, loc, s, x, v);
+      const T* src = ct + S.low_off + int64_t(s) * S.nx_src * S.nv + v;
+      const int32_t* p = S.xpar + 2 * int64_t(x);
+      const double* pw = S.xparw + 2 * int64_t(x);
+      val -= T(pw[0]) * src[int64_t(p[0]) * S.nv] + T(pw[1]) * src[int64_t(p[1]) * S.nv];
+    }
+    z[S.src_off + loc] = val;
+  }
+}
+
+// y = (Pinv (x) diag(M^x)^-1 (x) diag(M^v)^-1) x on every grid segment
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_minv(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                 const T* __restrict__ x, T* __restrict__ y) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t p = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (p >= plane) return;
+    const int xi = int(p / S.nv), vi = int(p - int64_t(p / S.nv) * S.nv);
+    const T sc = T(1.0 / (S.mxd[int64_t(xi) * S.Sx] * S.mvd[int64_t(vi) * S.Sv]));
+    T in[kMaxR];
+    for (int s = 0; s < S.R; ++s) in[s] = x[S.off + s * plane + p];
+    for (int s = 0; s < S.R; ++s) {
+      T a = 0;
+      for (int s2 = 0; s2 < S.R; ++s2) a += T(S.pinv[s * S.R + s2]) * in[s2];
+      y[S.off + s * plane + p] = a * sc;
+    }
+  }
+}
+
 // ------------------------------------------------------------- data / rhs --
 __global__ void k_project(int64_t n, int nq, int R, const double* __restrict__ wts, const double* __restrict__ samples,
                           double* __restrict__ out) {
@@ -324,37 +324,33 @@ __global__ void k_project(int64_t n, int nq, int R, const double* __restrict__ w
   }
 }
 
-__global__ void k_trace(DevGrids G, const double* __restrict__ u, double* __restrict__ out, int64_t npts_total) {
-  // out is one-slice [grid][nx][nv]; u is G (R slices)
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= npts_total) return;
-  int g = 0;
-  int64_t acc = 0;
-  while (g + 1 < G.n && idx >= acc + int64_t(G.nx[g]) * G.nv[g]) {
-    acc += int64_t(G.nx[g]) * G.nv[g];
-    ++g;
+// trace of a previous solution with Rprev slices: out[poff + p] = sum_s u[Rprev poff + s plane + p]
+__global__ void k_trace(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk, int Rprev,
+                        const double* __restrict__ u, double* __restrict__ out) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t p = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (p >= plane) return;
+    double a = 0;
+    for (int s = 0; s < Rprev; ++s) a += u[S.src_off * Rprev + s * plane + p];
+    out[S.src_off + p] = a;
   }
-  const int64_t p = idx - acc;
-  const int64_t plane = int64_t(G.nx[g]) * G.nv[g];
-  double a = 0;
-  for (int s = 0; s < G.R; ++s) a += u[G.off[g] + s * plane + p];
-  out[idx] = a;
 }
 
-__global__ void k_spread(DevGrids G, int R, const double* __restrict__ m, double* __restrict__ b,
-                         int64_t npts_total) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= npts_total) return;
-  int g = 0;
-  int64_t acc = 0;
-  while (g + 1 < G.n && idx >= acc + int64_t(G.nx[g]) * G.nv[g]) {
-    acc += int64_t(G.nx[g]) * G.nv[g];
-    ++g;
+// b[off + s plane + p] = (-1)^s m[poff + p]
+__global__ void k_spread(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                         const double* __restrict__ m, double* __restrict__ b) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t p = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (p >= plane) return;
+    const double val = m[S.src_off + p];
+    for (int s = 0; s < S.R; ++s) b[S.off + s * plane + p] = (s & 1) ? -val : val;
   }
-  const int64_t p = idx - acc;
-  const int64_t plane = int64_t(G.nx[g]) * G.nv[g];
-  const double val = m[idx];
-  for (int s = 0; s < R; ++s) b[int64_t(R) * acc + s * plane + p] = (s & 1) ? -val : val;
 }
 
 // ================================================================ launchers =
@@ -362,64 +358,48 @@ static inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlo
 #define LAUNCH_CHECK() SGDG_CHECK_HIP(hipGetLastError())
 
 template <class T>
-void KernelsT<T>::restrict_x(const DevGrids& Go, const DevGrids& Gi, const DevDomain& DX, const T* in, T* out,
-                             hipStream_t s) {
-  const int64_t total = Go.off[Go.n];
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_restrict_x<T>, dim3(nblk(total)), dim3(kBlock), 0, s, Go, Gi, DX, in, out);
+void KernelsT<T>::seg_dots(const SegTable& S, const T* V, int64_t vstride, int nvec, const T* w, double* partial,
+                           hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_seg_dots<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, V, vstride, nvec, w, partial);
   LAUNCH_CHECK();
 }
-
 template <class T>
-void KernelsT<T>::combine(const DevGrids& Gu, const DevGrids& Gl, int lmin, const DevDomain& DX, const T* up,
-                          const T* low, T* out, int R, hipStream_t s) {
-  (void)R;
-  const int64_t total = Gu.off[Gu.n];
-  hipLaunchKernelGGL(k_combine<T>, dim3(nblk(total)), dim3(kBlock), 0, s, Gu, Gl, lmin, DX, up, low, out);
+void KernelsT<T>::seg_axpy(const SegTable& S, const T* V, int64_t vstride, int nvec, const double* coef, int cstride,
+                           T* w, double sign, double* partial_norm, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_seg_axpy<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, V, vstride, nvec, coef, cstride,
+                     w, sign, partial_norm);
   LAUNCH_CHECK();
 }
-
 template <class T>
-void KernelsT<T>::minv(const DevGrids& G, const GridPts& P, const DevDomain& DX, const DevDomain& DV,
-                       const double* pinv, int sweeps, const T* x, T* y, T* tmp1, T* tmp2, hipStream_t s) {
-  (void)sweeps;
-  (void)tmp1;
-  (void)tmp2;
-  const int64_t npts = P.poff[G.n];
-  hipLaunchKernelGGL(k_minv_jacobi<T>, dim3(nblk(npts)), dim3(kBlock), 0, s, G, P, DX, DV, pinv, x, y);
+void KernelsT<T>::seg_scale(const SegTable& S, const T* w, const double* scal, T* out, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_seg_scale<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, w, scal, out);
   LAUNCH_CHECK();
 }
-
 template <class T>
-void KernelsT<T>::seg_dots(const Segs& S, const T* V, int64_t vstride, int nvec, const T* w, double* partial,
-                           int nchunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_dots<T>, dim3(nchunks, S.n), dim3(kBlock), 0, s, S, V, vstride, nvec, w, partial, nchunks);
-  LAUNCH_CHECK();
+void KernelsT<T>::seg_norm2(const SegTable& S, const T* w, double* partial, hipStream_t s) {
+  seg_dots(S, w, 0, 1, w, partial, s);
 }
-
 template <class T>
-void KernelsT<T>::seg_axpy_multi(const Segs& S, const T* V, int64_t vstride, int nvec, const double* coef, int cstride,
-                                 T* w, double sign, double* partial_norm, int nchunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_axpy<T>, dim3(nchunks, S.n), dim3(kBlock), 0, s, S, V, vstride, nvec, coef, cstride, w,
-                     sign, partial_norm, nchunks);
+void KernelsT<T>::ct_gather(const SegTable& S, const T* r, T* b, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_ct_gather<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, r, b);
   LAUNCH_CHECK();
 }
-
 template <class T>
-void KernelsT<T>::seg_scale(const Segs& S, const T* w, const double* scal, T* out, hipStream_t s) {
-  int64_t mx = 0;
-  for (int i = 0; i < S.n; ++i) mx = mx > S.off[i + 1] - S.off[i] ? mx : S.off[i + 1] - S.off[i];
-  if (mx == 0) return;
-  hipLaunchKernelGGL(k_seg_scale<T>, dim3(nblk(mx), S.n), dim3(kBlock), 0, s, S, w, scal, out);
+void KernelsT<T>::ct_combine(const SegTable& S, const T* ct, T* z, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_ct_combine<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, ct, z);
   LAUNCH_CHECK();
 }
-
 template <class T>
-void KernelsT<T>::seg_norm2(const Segs& S, const T* w, double* partial, int nchunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_dots<T>, dim3(nchunks, S.n), dim3(kBlock), 0, s, S, w, int64_t(0), 1, w, partial, nchunks);
+void KernelsT<T>::minv(const SegTable& S, const T* x, T* y, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_minv<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, x, y);
   LAUNCH_CHECK();
 }
-
 template <class T>
 void KernelsT<T>::axpby(int64_t n, T a, const T* x, T b, T* y, hipStream_t s) {
   if (n == 0) return;
@@ -452,28 +432,18 @@ void convert_f32_to_f64(int64_t n, const float* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_f2d, dim3(nblk(n)), dim3(kBlock), 0, s, n, x, y);
   LAUNCH_CHECK();
 }
-void add_f32_to_f64(int64_t n, const float* x, double* y, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_addf2d, dim3(nblk(n)), dim3(kBlock), 0, s, n, x, y);
-  LAUNCH_CHECK();
-}
-void finish_dots(int nseg, int nvec, int nchunks, const double* partial, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(nblk(int64_t(nseg) * nvec)), dim3(kBlock), 0, s, nseg, nvec, nchunks, partial, out);
-  LAUNCH_CHECK();
-}
-void gmres_start(int nseg, const GmresState& st, const double* partial, int nchunks, double tol, int first,
+void gmres_start(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, double tol, int first,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_start, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, partial, nchunks, tol, first);
+  hipLaunchKernelGGL(k_gmres_start, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, segs, partial, tol, first);
   LAUNCH_CHECK();
 }
-void gmres_add_proj(int nseg, const GmresState& st, const double* partial, int nchunks, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_proj, dim3(nblk(int64_t(nseg) * (j + 1))), dim3(kBlock), 0, s, nseg, st, partial, nchunks,
-                     j);
+void gmres_add_proj(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_proj, dim3(nblk(int64_t(nseg) * (j + 1))), dim3(kBlock), 0, s, nseg, st, segs, partial, j);
   LAUNCH_CHECK();
 }
-void gmres_givens(int nseg, const GmresState& st, const double* partial, int nchunks, int j, double tol,
+void gmres_givens(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, double tol,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, partial, nchunks, j, tol);
+  hipLaunchKernelGGL(k_gmres_givens, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, segs, partial, j, tol);
   LAUNCH_CHECK();
 }
 void gmres_lsq(int nseg, const GmresState& st, hipStream_t s) {
@@ -485,16 +455,14 @@ void project_time(int64_t n, int nq, int R, const double* wts, const double* sam
   hipLaunchKernelGGL(k_project, dim3(nblk(n)), dim3(kBlock), 0, s, n, nq, R, wts, samples, out);
   LAUNCH_CHECK();
 }
-void trace_sum(const DevGrids& G, const double* u, double* out, hipStream_t s) {
-  int64_t np = 0;
-  for (int g = 0; g < G.n; ++g) np += int64_t(G.nx[g]) * G.nv[g];
-  hipLaunchKernelGGL(k_trace, dim3(nblk(np)), dim3(kBlock), 0, s, G, u, out, np);
+void trace_sum(const SegTable& S, int Rprev, const double* u, double* out, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_trace, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, Rprev, u, out);
   LAUNCH_CHECK();
 }
-void spread_left(const DevGrids& G, int R, const double* m, double* b, hipStream_t s) {
-  int64_t np = 0;
-  for (int g = 0; g < G.n; ++g) np += int64_t(G.nx[g]) * G.nv[g];
-  hipLaunchKernelGGL(k_spread, dim3(nblk(np)), dim3(kBlock), 0, s, G, R, m, b, np);
+void spread_left(const SegTable& S, const double* m, double* b, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_spread, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, m, b);
   LAUNCH_CHECK();
 }
 

@@ -1,0 +1,125 @@
+// Internal structures shared by problem.hip (layout, assembly, upload) and
+// solver.hip (operator application, preconditioners, solvers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fused.h"
+#include "kernels.h"
+#include "sgdg_internal.h"
+
+using namespace sgdg;
+
+#define API_BEGIN try {
+#define API_END                                          \
+  }                                                      \
+  catch (const Error& e) {                               \
+    set_error(e.msg);                                    \
+    return e.code;                                       \
+  }                                                      \
+  catch (const std::bad_alloc&) {                        \
+    set_error("host allocation failed");                 \
+    return SGDG_E_ALLOC;                                 \
+  }                                                      \
+  catch (const std::exception& e) {                      \
+    set_error(e.what());                                 \
+    return SGDG_E_STATE;                                 \
+  }                                                      \
+  return SGDG_OK;
+
+static inline void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error{SGDG_E_ARG, msg};
+}
+
+template <class T>
+static inline T* ptr(const DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+template <class T>
+static inline T* upload(DevBuf& b, const std::vector<T>& h) {
+  b.alloc(h.size() * sizeof(T));
+  if (!h.empty()) SGDG_CHECK_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return ptr<T>(b);
+}
+
+struct GridDesc {
+  int lx, lv;
+  int64_t nx, nv;
+};
+
+struct sgdg_grid_s {
+  Dom x, v;
+  int lmin = 0, lmax = 0, r = 0, R = 1;
+  std::vector<GridDesc> up, low;
+  int64_t up_pts = 0, low_pts = 0;
+
+  DevGrids make(const std::vector<GridDesc>& gs, int R_, int first = 0, int count = -1) const {
+    DevGrids G;
+    if (count < 0) count = int(gs.size()) - first;
+    G.n = count;
+    G.R = R_;
+    int64_t o = 0;
+    for (int i = 0; i < count; ++i) {
+      const GridDesc& d = gs[first + i];
+      G.lx[i] = d.lx;
+      G.lv[i] = d.lv;
+      G.nx[i] = int(d.nx);
+      G.nv[i] = int(d.nv);
+      G.off[i] = o;
+      o += int64_t(R_) * d.nx * d.nv;
+    }
+    G.off[count] = o;
+    return G;
+  }
+  // upper then lower grids in one set (the combination-technique grid problems)
+  DevGrids make_ct(int R_) const {
+    std::vector<GridDesc> all = up;
+    all.insert(all.end(), low.begin(), low.end());
+    return make(all, R_);
+  }
+};
+
+struct DomDev {
+  DevBuf nbr, par, parw, chi, chiw, vals, vals32, wide, rvals, rvals32;
+  DevDomain d;
+};
+
+struct OpDev {
+  TermList host;
+  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs;
+  DevOp op;
+};
+
+// A batch of independent strip problems sharing dimension and time degree
+// (the C type sgdg_batch); a single problem is used as a batch of one.
+using Batch = sgdg_batch_s;
+void destroy_batch(Batch* b);
+struct BatchDeleter {
+  void operator()(Batch* b) const { destroy_batch(b); }
+};
+
+struct sgdg_ops_s {
+  sgdg_grid grid = nullptr;
+  DomainData X, V;
+  DomDev dx, dv;
+  OpDev ops[4];  // FULL, MASS, DATA_F, DATA_G term lists
+  double pinv[kMaxR * kMaxR] = {};  // (Tt + delta Ct + Gt)^-1
+  int device = 0;
+  std::unique_ptr<Batch, BatchDeleter> self;  // this problem as a batch of one
+};
+
+// the problem as a batch of one (created on first use)
+Batch& self_batch(sgdg_ops o);

@@ -1,0 +1,338 @@
+// The C ABI of libsgdg: layout, assembly/upload, operator application, the
+// combination-technique preconditioner (Algorithm 1's body, Sect. 4.3), the
+// strip right-hand side (eq:weak_form_j) and the flexible-GMRES strip solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <stdexcept>
+
+#include "ops_internal.h"
+
+using namespace sgdg;
+
+// ------------------------------------------------------------------ errors --
+namespace sgdg {
+static thread_local std::string g_err = "no error";
+void set_error(const std::string& m) { g_err = m; }
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+void DevBuf::alloc(size_t b) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (b == 0) return;
+  if (hipMalloc(&p, b) != hipSuccess) {
+    p = nullptr;
+    throw Error{SGDG_E_ALLOC, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+  }
+  bytes = b;
+}
+void DevBuf::ensure(size_t b) {
+  if (b > bytes) {
+    // work queued earlier may still use the old allocation
+    if (p) SGDG_CHECK_HIP(hipDeviceSynchronize());
+    alloc(b);
+  }
+}
+}  // namespace sgdg
+
+extern "C" const char* sgdg_last_error(void) { return g_err.c_str(); }
+
+// -------------------------------------------------------------------- grid --
+extern "C" sgdg_status sgdg_build_sparse_grid(const sgdg_domain* x, const sgdg_domain* v, int level_min,
+                                              int level_max, int time_degree, sgdg_grid* out) {
+  API_BEGIN
+  require(x && v && out, "null argument");
+  require(x->dim == v->dim && x->dim >= 1 && x->dim <= 3, "domains must share dim in 1..3");
+  require(level_min >= 0 && level_min <= level_max && level_max <= 12, "levels must satisfy 0 <= min <= max <= 12");
+  require(time_degree >= 0 && time_degree <= 2, "time degree must be 0..2");
+  const int n_up = level_max - level_min + 1;
+  require(n_up <= kMaxGrids / 2, "too many component grids");
+  auto* g = new sgdg_grid_s;
+  for (int side = 0; side < 2; ++side) {
+    const sgdg_domain* s = side == 0 ? x : v;
+    Dom& D = side == 0 ? g->x : g->v;
+    D.d = s->dim;
+    D.periodic = s->periodic != 0;
+    for (int a = 0; a < 3; ++a) {
+      D.lo[a] = s->lo[a];
+      D.hi[a] = s->hi[a];
+      if (a < s->dim && !(s->hi[a] > s->lo[a])) {
+        delete g;
+        throw Error{SGDG_E_ARG, "domain must have lo < hi on every axis"};
+      }
+    }
+  }
+  g->lmin = level_min;
+  g->lmax = level_max;
+  g->r = time_degree;
+  g->R = time_degree + 1;
+  const int S = level_max + level_min;
+  for (int lx = level_min; lx <= level_max; ++lx) g->up.push_back({lx, S - lx, g->x.nodes(lx), g->v.nodes(S - lx)});
+  for (int lx = level_min; lx < level_max; ++lx)
+    g->low.push_back({lx, S - 1 - lx, g->x.nodes(lx), g->v.nodes(S - 1 - lx)});
+  for (auto& d : g->up) g->up_pts += d.nx * d.nv;
+  for (auto& d : g->low) g->low_pts += d.nx * d.nv;
+  *out = g;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_grid_info(sgdg_grid g, int which, int* n_comp, int64_t* n_dof, int* lx, int* lv,
+                                      int64_t* nx, int64_t* nv, int64_t* offset) {
+  API_BEGIN
+  require(g != nullptr, "null grid");
+  require(which == 0 || which == 1, "which must be 0 (upper) or 1 (lower)");
+  const auto& gs = which == 0 ? g->up : g->low;
+  if (n_comp) *n_comp = int(gs.size());
+  if (n_dof) *n_dof = which == 0 ? g->R * g->up_pts : g->low_pts;
+  int64_t o = 0;
+  for (size_t i = 0; i < gs.size(); ++i) {
+    if (lx) lx[i] = gs[i].lx;
+    if (lv) lv[i] = gs[i].lv;
+    if (nx) nx[i] = gs[i].nx;
+    if (nv) nv[i] = gs[i].nv;
+    if (offset) offset[i] = o;
+    o += gs[i].nx * gs[i].nv;
+  }
+  API_END
+}
+
+extern "C" void sgdg_grid_destroy(sgdg_grid g) { delete g; }
+
+// --------------------------------------------------------------------- ops --
+static void upload_domain(DomainData& D, DomDev& dd) {
+  const int S = D.st.S;
+  std::vector<int32_t> nbr, par, chi;
+  std::vector<double> parw, chiw;
+  DevDomain& d = dd.d;
+  d.S = S;
+  d.lmin = D.lmin;
+  d.lmax = D.lmax;
+  int64_t o = 0, po = 0;
+  for (int l = D.lmin; l <= D.lmax; ++l) {
+    const LevelTables& T = D.L(l);
+    d.lev_off[l - D.lmin] = o;
+    d.par_off[l - D.lmin] = po;
+    nbr.insert(nbr.end(), T.nbr.begin(), T.nbr.end());
+    if (l < D.lmax) {
+      chi.insert(chi.end(), T.chi.begin(), T.chi.end());
+      chiw.insert(chiw.end(), T.chiw.begin(), T.chiw.end());
+    } else {
+      chi.insert(chi.end(), size_t(T.n) * S, 0);
+      chiw.insert(chiw.end(), size_t(T.n) * S, 0.0);
+    }
+    if (l > D.lmin) {
+      par.insert(par.end(), T.par.begin(), T.par.end());
+      parw.insert(parw.end(), T.parw.begin(), T.parw.end());
+    } else {
+      par.insert(par.end(), size_t(T.n) * 2, 0);
+      parw.insert(parw.end(), size_t(T.n) * 2, 0.0);
+    }
+    o += T.n * S;
+    po += T.n * 2;
+  }
+  d.nbr = upload(dd.nbr, nbr);
+  d.chi = upload(dd.chi, chi);
+  d.chiw = upload(dd.chiw, chiw);
+  d.par = upload(dd.par, par);
+  d.parw = upload(dd.parw, parw);
+  d.fac_stride = o;
+  const size_t nf = D.factors.size();
+  std::vector<double> vals(nf * o);
+  std::vector<float> v32(nf * o);
+  for (size_t f = 0; f < nf; ++f)
+    for (int l = D.lmin; l <= D.lmax; ++l) {
+      const auto& src = D.values[f][l - D.lmin];
+      std::copy(src.begin(), src.end(), vals.begin() + f * o + d.lev_off[l - D.lmin]);
+    }
+  for (size_t i = 0; i < vals.size(); ++i) v32[i] = float(vals[i]);
+  d.vals = upload(dd.vals, vals);
+  d.vals32 = upload(dd.vals32, v32);
+  // restricted stencils
+  const int W = int(D.woff.size());
+  d.W = W;
+  std::vector<int32_t> wide;
+  int64_t wo = 0;
+  for (int l = D.lmin; l <= D.lmax; ++l) {
+    d.wlev_off[l - D.lmin] = wo;
+    const int64_t n = D.L(l).n;
+    if (l < D.lmax) wide.insert(wide.end(), D.wide_idx[l - D.lmin].begin(), D.wide_idx[l - D.lmin].end());
+    else wide.insert(wide.end(), size_t(n) * W, 0);
+    wo += n * W;
+  }
+  d.wide = upload(dd.wide, wide);
+  d.rstride = wo;
+  std::vector<double> rv(nf * wo, 0.0);
+  for (size_t f = 0; f < nf; ++f)
+    for (int l = D.lmin; l < D.lmax; ++l) {
+      const auto& src = D.rvalues[f][l - D.lmin];
+      std::copy(src.begin(), src.end(), rv.begin() + f * wo + d.wlev_off[l - D.lmin]);
+    }
+  std::vector<float> rv32(rv.size());
+  for (size_t i = 0; i < rv.size(); ++i) rv32[i] = float(rv[i]);
+  d.rvals = upload(dd.rvals, rv);
+  d.rvals32 = upload(dd.rvals32, rv32);
+}
+
+static void upload_op(OpDev& od) {
+  const TermList& L = od.host;
+  std::vector<int> xf, vf, vg, xg, vgf, xgf;
+  std::vector<double> tm;
+  std::vector<float> tm32;
+  for (const Term& t : L.terms) {
+    xf.push_back(t.xf);
+    vf.push_back(t.vf);
+    auto iv = std::find(vgf.begin(), vgf.end(), t.vf);
+    if (iv == vgf.end()) {
+      vgf.push_back(t.vf);
+      iv = vgf.end() - 1;
+    }
+    vg.push_back(int(iv - vgf.begin()));
+    auto ix = std::find(xgf.begin(), xgf.end(), t.xf);
+    if (ix == xgf.end()) {
+      xgf.push_back(t.xf);
+      ix = xgf.end() - 1;
+    }
+    xg.push_back(int(ix - xgf.begin()));
+    for (int i = 0; i < L.Rout * L.Rin; ++i) {
+      tm.push_back(t.tm[i]);
+      tm32.push_back(float(t.tm[i]));
+    }
+  }
+  std::vector<int> vgt, vgs(vgf.size() + 1, 0), xgt, xgs(xgf.size() + 1, 0);
+  for (size_t j = 0; j < vgf.size(); ++j) {
+    vgs[j] = int(vgt.size());
+    for (size_t k = 0; k < vg.size(); ++k)
+      if (vg[k] == int(j)) vgt.push_back(int(k));
+  }
+  vgs[vgf.size()] = int(vgt.size());
+  for (size_t m = 0; m < xgf.size(); ++m) {
+    xgs[m] = int(xgt.size());
+    for (size_t k = 0; k < xg.size(); ++k)
+      if (xg[k] == int(m)) xgt.push_back(int(k));
+  }
+  xgs[xgf.size()] = int(xgt.size());
+  DevOp& op = od.op;
+  op.vg_terms = upload(od.vgt, vgt);
+  op.vg_start = upload(od.vgs, vgs);
+  op.xg_terms = upload(od.xgt, xgt);
+  op.xg_start = upload(od.xgs, xgs);
+  op.Rin = L.Rin;
+  op.Rout = L.Rout;
+  op.nterms = int(L.terms.size());
+  op.nvg = int(vgf.size());
+  op.nxg = int(xgf.size());
+  op.term_xf = upload(od.xf, xf);
+  op.term_vf = upload(od.vf, vf);
+  op.term_vg = upload(od.vg, vg);
+  op.term_xg = upload(od.xg, xg);
+  op.term_tm = upload(od.tm, tm);
+  op.term_tm32 = upload(od.tm32, tm32);
+  op.vg_fac = upload(od.vgf, vgf);
+  op.xg_fac = upload(od.xgf, xgf);
+}
+
+static void invert_small(int R, const double* A, double* inv) {
+  double a[9], b[9];
+  std::memcpy(a, A, sizeof(double) * R * R);
+  for (int i = 0; i < R * R; ++i) b[i] = 0;
+  for (int i = 0; i < R; ++i) b[i * R + i] = 1;
+  for (int c = 0; c < R; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < R; ++i)
+      if (std::fabs(a[i * R + c]) > std::fabs(a[piv * R + c])) piv = i;
+    for (int k = 0; k < R; ++k) {
+      std::swap(a[c * R + k], a[piv * R + k]);
+      std::swap(b[c * R + k], b[piv * R + k]);
+    }
+    const double d = a[c * R + c];
+    if (d == 0.0) throw Error{SGDG_E_STATE, "singular time block"};
+    for (int k = 0; k < R; ++k) {
+      a[c * R + k] /= d;
+      b[c * R + k] /= d;
+    }
+    for (int i = 0; i < R; ++i)
+      if (i != c) {
+        const double f = a[i * R + c];
+        for (int k = 0; k < R; ++k) {
+          a[i * R + k] -= f * a[c * R + k];
+          b[i * R + k] -= f * b[c * R + k];
+        }
+      }
+  }
+  std::memcpy(inv, b, sizeof(double) * R * R);
+}
+
+extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out) {
+  API_BEGIN
+  require(g && p && out, "null argument");
+  require(p->dt > 0 && p->delta >= 0, "dt must be > 0 and delta >= 0");
+  const int d = g->x.d;
+  for (int c = 0; c < 2 * d; ++c)
+    if (p->beta[c]) {
+      require(p->beta[c]->n_xf >= 0 && p->beta[c]->n_vf >= 0 && p->beta[c]->n_xf <= 2 && p->beta[c]->n_vf <= 2,
+              "each beta component may carry at most two field factors per domain");
+      for (int i = 0; i < p->beta[c]->n_xf; ++i) require(p->beta[c]->xf[i] != nullptr, "null field");
+      for (int i = 0; i < p->beta[c]->n_vf; ++i) require(p->beta[c]->vf[i] != nullptr, "null field");
+    }
+  require(p->n_sigma >= 0 && p->n_sigma <= 8, "n_sigma must be 0..8");
+  for (int t = 0; t < p->n_sigma; ++t)
+    require(p->sigma[t].n_xf >= 0 && p->sigma[t].n_vf >= 0 && p->sigma[t].n_xf <= 2 && p->sigma[t].n_vf <= 2,
+            "each sigma term may carry at most two field factors per domain");
+  std::unique_ptr<sgdg_ops_s> o(new sgdg_ops_s);
+  o->grid = g;
+  SGDG_CHECK_HIP(hipGetDevice(&o->device));
+  for (int side = 0; side < 2; ++side) {
+    DomainData& D = side == 0 ? o->X : o->V;
+    D.dom = side == 0 ? g->x : g->v;
+    D.lmin = g->lmin;
+    D.lmax = g->lmax;
+    build_domain_tables(D);
+  }
+  TermList tl[4];
+  build_terms(o->X, o->V, *p, g->r, tl);
+  // the plain mass factor drives the inner preconditioner
+  FactorKey mk;
+  mk.kind = kMass;
+  o->dx.d.mass_fac = o->X.factor_id(mk);
+  o->dv.d.mass_fac = o->V.factor_id(mk);
+  for (int side = 0; side < 2; ++side) {
+    DomainData& D = side == 0 ? o->X : o->V;
+    D.values.assign(D.factors.size(), {});
+    D.rvalues.assign(D.factors.size(), {});
+    build_wide_tables(D);
+#pragma omp parallel for schedule(dynamic)
+    for (int f = 0; f < int(D.factors.size()); ++f) {
+      assemble_factor(D, f);
+      restrict_factor(D, f);
+    }
+  }
+  const int mfx = o->dx.d.mass_fac, mfv = o->dv.d.mass_fac;
+  upload_domain(o->X, o->dx);
+  upload_domain(o->V, o->dv);
+  o->dx.d.mass_fac = mfx;
+  o->dv.d.mass_fac = mfv;
+  for (int k = 0; k < 4; ++k) {
+    o->ops[k].host = tl[k];
+    upload_op(o->ops[k]);
+  }
+  // inner preconditioner time block (Tt + delta Ct + Gt)^-1
+  const int R = g->R;
+  double Mt[9], Tt[9], Ct[9], Gt[9], P[9];
+  time_matrices(g->r, p->dt, Mt, Tt, Ct, Gt);
+  for (int i = 0; i < R * R; ++i) P[i] = Tt[i] + p->delta * Ct[i] + Gt[i];
+  invert_small(R, P, o->pinv);
+  *out = o.release();
+  API_END
+}
+
+extern "C" void sgdg_ops_destroy(sgdg_ops o) { delete o; }
+

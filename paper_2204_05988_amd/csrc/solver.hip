@@ -1,0 +1,1134 @@
+// Batched operator application, the combination-technique preconditioner
+// (Algorithm 1's body, Sect. 4.3), the strip right-hand side
+// (eq:weak_form_j) and the flexible-GMRES strip solves, for a batch of
+// independent problems.  The single-problem entry points use a batch of one.
+#include <chrono>
+#include <fstream>
+#include <sstream>
+
+#include "ops_internal.h"
+
+// ----------------------------------------------------------------- batch ---
+namespace {
+
+enum Kind { K_FULL = 0, K_DIAG = 1, K_MASS = 2, K_DATAF = 3, K_DATAG = 4, K_CT = 5, K_COUNT = 6 };
+
+struct GBufs {
+  DevBuf H, cs, sn, g, bn, beta, act, k, hc, inv, y, partial;
+};
+
+struct SegTab {
+  DevBuf segs, blk;
+  std::vector<SegInfo> host;
+  SegTable t;
+};
+
+struct Items {
+  DevBuf items, sitems;
+  int n = 0, max_stage = 0, max_tab = 0;
+  std::vector<int> step_first, step_count;
+  bool built = false;
+};
+
+struct KindData {
+  DevBuf desc;
+  std::vector<ProbDesc> host;
+  int64_t pt_bstride = 0, qt_bstride = 0, total = 0;
+  int R = 1;
+  bool any_scan = false;
+  Items it[2];  // FP64, FP32
+};
+
+template <class T>
+struct BWork {
+  DevBuf Pt, Qt, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
+};
+
+}  // namespace
+
+struct sgdg_batch_s {
+  std::vector<sgdg_ops> P;
+  int d = 1, R = 1;
+  KindData kinds[K_COUNT];
+  std::map<int, std::unique_ptr<SegTab>> ct_tabs, prob_tabs;
+  std::unique_ptr<SegTab> pts;
+  GBufs gb[3];  // grid problems, strip FGMRES, norms
+  BWork<double> w64;
+  BWork<float> w32;
+  DevBuf fV, fZ, fw, fr, fe, ftmp, a32, b32;
+  DevBuf rhs_a, rhs_b, rhs_c, rhs_d, rhs_w;
+  int64_t inner_iters = 0;
+  bool owned_by_ops = false;
+  // box-shape choice of the fused kernel per element size (tuned or default)
+  int xbox[2] = {0, 0};
+  // graphs of grid-problem GMRES cycles
+  std::map<std::string, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+  // event timing: slot 0 level scans, 1 fused tiles, 2 grid-problem cycles
+  bool prof = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int slot;
+  };
+  std::vector<Ev> events;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+  ~sgdg_batch_s() {
+    for (auto& e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+void destroy_batch(Batch* b) { delete b; }
+
+Batch& self_batch(sgdg_ops o) {
+  if (!o->self) {
+    Batch* b = new Batch;
+    b->P = {o};
+    b->d = o->X.dom.d;
+    b->R = o->grid->R;
+    b->owned_by_ops = true;
+    o->self.reset(b);
+  }
+  return *o->self;
+}
+
+template <class T>
+static BWork<T>& work(Batch& B);
+template <>
+BWork<double>& work<double>(Batch& B) { return B.w64; }
+template <>
+BWork<float>& work<float>(Batch& B) { return B.w32; }
+
+template <class F>
+static void timed(Batch& B, int slot, hipStream_t s, F&& launch) {
+  if (!B.prof) {
+    launch();
+    return;
+  }
+  Batch::Ev e;
+  e.slot = slot;
+  SGDG_CHECK_HIP(hipEventCreate(&e.a));
+  SGDG_CHECK_HIP(hipEventCreate(&e.b));
+  SGDG_CHECK_HIP(hipEventRecord(e.a, s));
+  launch();
+  SGDG_CHECK_HIP(hipEventRecord(e.b, s));
+  B.events.push_back(e);
+}
+
+static void drain_events(Batch& B) {
+  for (auto& e : B.events) {
+    SGDG_CHECK_HIP(hipEventSynchronize(e.b));
+    float ms = 0;
+    SGDG_CHECK_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    B.prof_ms[e.slot] += ms;
+    B.prof_n[e.slot] += 1;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  B.events.clear();
+}
+
+// ------------------------------------------------------- descriptors -----
+static int64_t up_pts(sgdg_ops o) { return o->grid->up_pts; }
+
+static KindData& kind(Batch& B, int k) {
+  KindData& K = B.kinds[k];
+  if (!K.host.empty()) return K;
+  const bool ct = k == K_CT;
+  const int opidx = (k == K_FULL || k == K_DIAG || k == K_CT) ? 0 : (k == K_MASS ? 1 : (k == K_DATAF ? 2 : 3));
+  const int R = B.P[0]->ops[opidx].op.Rin;
+  K.R = R;
+  int64_t off = 0, pt = 0, qt = 0;
+  for (size_t p = 0; p < B.P.size(); ++p) {
+    sgdg_ops o = B.P[p];
+    sgdg_grid g = o->grid;
+    ProbDesc D{};
+    require(o->ops[opidx].op.Rin == R && o->ops[opidx].op.Rout == R, "operator slices differ within the batch");
+    require(int(g->up.size() + (ct ? g->low.size() : 0)) <= kMaxGrids, "too many component grids");
+    D.G = ct ? g->make_ct(R) : g->make(g->up, R);
+    D.Gl = g->make(g->low, R);
+    int64_t po = 0;
+    for (int i = 0; i < D.G.n; ++i) {
+      D.poff[i] = po;
+      po += int64_t(D.G.nx[i]) * D.G.nv[i];
+    }
+    D.poff[D.G.n] = po;
+    D.DX = o->dx.d;
+    D.DV = o->dv.d;
+    D.op = o->ops[opidx].op;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      D.mx[l] = g->x.axis_nodes(l);
+      D.mv[l] = g->v.axis_nodes(l);
+    }
+    D.xper = g->x.periodic;
+    D.vper = g->v.periodic;
+    for (int e = 0; e < kMaxS; ++e)
+      for (int a = 0; a < 3; ++a) D.off[e][a] = e < o->X.st.S ? o->X.st.off[e][a] : 0;
+    D.diag_only = (k == K_DIAG || ct || D.G.n == 1) ? 1 : 0;
+    D.u_off = D.y_off = off;
+    off += D.G.off[D.G.n];
+    D.pt_off = pt;
+    D.qt_off = qt;
+    if (!D.diag_only) {
+      K.any_scan = true;
+      const int64_t lt = D.Gl.off[D.Gl.n];
+      pt += int64_t(std::max(1, D.op.nvg)) * lt;
+      qt += int64_t(std::max(1, D.op.nxg)) * lt;
+    }
+    K.host.push_back(D);
+  }
+  K.total = off;
+  K.pt_bstride = pt;
+  K.qt_bstride = qt;
+  upload(K.desc, K.host);
+  return K;
+}
+
+// Box shape of one grid for the fused kernel: x-box and v-box sizes per axis
+// under the per-thread row limit and a bounded LDS stage.
+static void choose_boxes(int d, int bx, int mx, int mv, int R, int elem, int* xs, int* vs) {
+  const int nthr = fused_threads(), rows = fused_rows_per_thread();
+  const size_t lds_cap = 60 * 1024;
+  for (int a = 0; a < 3; ++a) {
+    xs[a] = a < d ? std::min(bx, mx) : 1;
+    vs[a] = 1;
+  }
+  auto fits = [&](const int* v) {
+    size_t nvb = 1, nvh = 1, nxh = 1, nx = 1;
+    for (int a = 0; a < d; ++a) {
+      nvb *= v[a];
+      nvh *= v[a] + 2;
+      nxh *= xs[a] + 2;
+      nx *= xs[a];
+    }
+    if (nvb > size_t(nthr)) return false;
+    if (nx > size_t(rows) * (nthr / nvb)) return false;
+    const size_t st = std::max(nxh * nvb, nx * nvh) * size_t(R) * elem;
+    const size_t tab = (nxh + 2 * nx + 2 * nvb + nvh) * sizeof(int);
+    return st + tab <= lds_cap;
+  };
+  bool grew = true;
+  while (grew) {
+    grew = false;
+    for (int a = d - 1; a >= 0; --a) {
+      if (vs[a] >= mv) continue;
+      int t[3] = {vs[0], vs[1], vs[2]};
+      t[a] = std::min(mv, vs[a] * 2);
+      if (fits(t)) {
+        vs[a] = t[a];
+        grew = true;
+      }
+    }
+  }
+}
+
+static int default_xbox(int d) { return d == 1 ? 32 : (d == 2 ? 8 : 4); }
+
+static Items& items(Batch& B, int k, int elem) {
+  KindData& K = kind(B, k);
+  Items& I = K.it[elem == 8 ? 0 : 1];
+  if (I.built) return I;
+  const int bx = B.xbox[elem == 8 ? 0 : 1] > 0 ? B.xbox[elem == 8 ? 0 : 1] : default_xbox(B.d);
+  std::vector<FusedItem> its;
+  int64_t max_stage = 1, max_tab = 1;
+  int maxn = 0;
+  for (size_t p = 0; p < B.P.size(); ++p) {
+    const ProbDesc& D = K.host[p];
+    sgdg_grid g = B.P[p]->grid;
+    maxn = std::max(maxn, D.G.n);
+    for (int gi = 0; gi < D.G.n; ++gi) {
+      const int mx = g->x.axis_nodes(D.G.lx[gi]), mv = g->v.axis_nodes(D.G.lv[gi]);
+      int xs[3], vs[3];
+      choose_boxes(B.d, bx, mx, mv, K.R, elem, xs, vs);
+      int nbx[3] = {1, 1, 1}, nbv[3] = {1, 1, 1};
+      int64_t nx_h = 1, nv_b = 1, nx_b = 1, nv_h = 1;
+      for (int a = 0; a < B.d; ++a) {
+        nbx[a] = (mx + xs[a] - 1) / xs[a];
+        nbv[a] = (mv + vs[a] - 1) / vs[a];
+        nx_h *= xs[a] + 2;
+        nx_b *= xs[a];
+        nv_b *= vs[a];
+        nv_h *= vs[a] + 2;
+      }
+      max_stage = std::max<int64_t>(max_stage, std::max(nx_h * nv_b, nx_b * nv_h) * K.R);
+      max_tab = std::max<int64_t>(max_tab, nx_h + 2 * nx_b + 2 * nv_b + nv_h);
+      for (int i0 = 0; i0 < nbx[0]; ++i0)
+        for (int i1 = 0; i1 < nbx[1]; ++i1)
+          for (int i2 = 0; i2 < nbx[2]; ++i2)
+            for (int j0 = 0; j0 < nbv[0]; ++j0)
+              for (int j1 = 0; j1 < nbv[1]; ++j1)
+                for (int j2 = 0; j2 < nbv[2]; ++j2) {
+                  FusedItem f{};
+                  f.prob = int(p);
+                  f.grid = gi;
+                  const int ix[3] = {i0, i1, i2}, iv[3] = {j0, j1, j2};
+                  for (int a = 0; a < 3; ++a) {
+                    f.xb[a] = a < B.d ? ix[a] * xs[a] : 0;
+                    f.xs[a] = a < B.d ? std::min(xs[a], mx - f.xb[a]) : 1;
+                    f.vb[a] = a < B.d ? iv[a] * vs[a] : 0;
+                    f.vs[a] = a < B.d ? std::min(vs[a], mv - f.vb[a]) : 1;
+                  }
+                  its.push_back(f);
+                }
+    }
+  }
+  upload(I.items, its);
+  I.n = int(its.size());
+  I.max_stage = int(max_stage);
+  I.max_tab = int(max_tab);
+  // scan work: one table per step, all problems
+  std::vector<ScanItem> sits;
+  I.step_first.clear();
+  I.step_count.clear();
+  if (K.any_scan) {
+    for (int t = 0; t + 1 < maxn; ++t) {
+      I.step_first.push_back(int(sits.size()));
+      for (size_t p = 0; p < B.P.size(); ++p) {
+        const ProbDesc& D = K.host[p];
+        if (D.diag_only || t + 1 >= D.G.n) continue;
+        for (int side = 0; side < 2; ++side) {
+          const int lg = side == 0 ? t : D.Gl.n - 1 - t;
+          const int64_t len = int64_t(K.R) * D.Gl.nx[lg] * D.Gl.nv[lg];
+          for (int64_t st = 0; st < len; st += fused_threads()) sits.push_back(ScanItem{int(p), side, lg, st});
+        }
+      }
+      I.step_count.push_back(int(sits.size()) - I.step_first.back());
+    }
+  }
+  upload(I.sitems, sits);
+  I.built = true;
+  return I;
+}
+
+template <class T>
+static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
+  KindData& K = kind(B, k);
+  Items& I = items(B, k, int(sizeof(T)));
+  BWork<T>& w = work<T>(B);
+  FusedCall<T> C{};
+  C.descs = ptr<ProbDesc>(K.desc);
+  C.items = ptr<FusedItem>(I.items);
+  C.sitems = ptr<ScanItem>(I.sitems);
+  C.nitems = I.n;
+  C.max_stage = I.max_stage;
+  C.max_tab = I.max_tab;
+  C.B = nb;
+  C.u_bstride = C.y_bstride = K.total;
+  C.u = u;
+  C.y = y;
+  if (K.any_scan) {
+    w.Pt.ensure(sizeof(T) * size_t(K.pt_bstride) * nb);
+    w.Qt.ensure(sizeof(T) * size_t(K.qt_bstride) * nb);
+    C.Pt = ptr<T>(w.Pt);
+    C.Qt = ptr<T>(w.Qt);
+    C.pt_bstride = K.pt_bstride;
+    C.qt_bstride = K.qt_bstride;
+    timed(B, 0, s, [&] {
+      for (size_t t = 0; t < I.step_first.size(); ++t) {
+        FusedCall<T> Cs = C;
+        Cs.sitems = C.sitems + I.step_first[t];
+        fused_scan_step<T>(Cs, I.step_count[t], B.d, s);
+      }
+    });
+  }
+  timed(B, 1, s, [&] { fused_tiles<T>(C, B.d, K.R, s); });
+}
+
+// ---------------------------------------------------------- segments -----
+static void finish_tab(SegTab& T) {
+  std::vector<BlockRef> blk;
+  int chunk = 0;
+  for (size_t i = 0; i < T.host.size(); ++i) {
+    SegInfo& S = T.host[i];
+    S.chunk0 = chunk;
+    S.nchunk = int(std::max<int64_t>(1, (S.len + kChunk - 1) / kChunk));
+    for (int c = 0; c < S.nchunk; ++c) blk.push_back(BlockRef{int(i), c});
+    chunk += S.nchunk;
+  }
+  T.t.segs = upload(T.segs, T.host);
+  T.t.blk = upload(T.blk, blk);
+  T.t.nseg = int(T.host.size());
+  T.t.nblk = int(blk.size());
+  T.t.nchunks = chunk;
+}
+
+static void fill_domain_ptrs(sgdg_ops o, SegInfo& S) {
+  const DevDomain& X = o->dx.d;
+  const DevDomain& V = o->dv.d;
+  S.Sx = X.S;
+  S.Sv = V.S;
+  S.S = X.S;
+  S.mxd = X.vals + int64_t(X.mass_fac) * X.fac_stride + X.lev_off[S.lx - X.lmin];
+  S.mvd = V.vals + int64_t(V.mass_fac) * V.fac_stride + V.lev_off[S.lv - V.lmin];
+  S.xchi = X.chi + X.lev_off[S.lx - X.lmin];
+  S.xchiw = X.chiw + X.lev_off[S.lx - X.lmin];
+  S.xpar = X.par + X.par_off[S.lx - X.lmin];
+  S.xparw = X.parw + X.par_off[S.lx - X.lmin];
+  for (int i = 0; i < kMaxR * kMaxR; ++i) S.pinv[i] = o->pinv[i];
+}
+
+// grid problems of the combination technique: upper then lower grids of each problem
+static SegTab& ct_tab(Batch& B, int Rs) {
+  auto it = B.ct_tabs.find(Rs);
+  if (it != B.ct_tabs.end()) return *it->second;
+  auto T = std::make_unique<SegTab>();
+  int64_t ct = 0, up = 0;
+  for (size_t p = 0; p < B.P.size(); ++p) {
+    sgdg_ops o = B.P[p];
+    sgdg_grid g = o->grid;
+    std::vector<int64_t> up_start, low_start;
+    int64_t c = ct;
+    for (auto& gd : g->up) {
+      up_start.push_back(c);
+      c += int64_t(Rs) * gd.nx * gd.nv;
+    }
+    for (auto& gd : g->low) {
+      low_start.push_back(c);
+      c += int64_t(Rs) * gd.nx * gd.nv;
+    }
+    int64_t u = up;
+    std::vector<int64_t> up_res;
+    for (auto& gd : g->up) {
+      up_res.push_back(u);
+      u += int64_t(Rs) * gd.nx * gd.nv;
+    }
+    for (size_t i = 0; i < g->up.size(); ++i) {
+      SegInfo S{};
+      S.prob = int(p);
+      S.kind = 0;
+      S.lx = g->up[i].lx;
+      S.lv = g->up[i].lv;
+      S.nx = int(g->up[i].nx);
+      S.nv = int(g->up[i].nv);
+      S.R = Rs;
+      S.off = up_start[i];
+      S.len = int64_t(Rs) * S.nx * S.nv;
+      S.src_off = up_res[i];
+      S.low_off = i > 0 ? low_start[i - 1] : -1;
+      S.nx_src = i > 0 ? int(g->low[i - 1].nx) : 0;
+      fill_domain_ptrs(o, S);
+      T->host.push_back(S);
+    }
+    for (size_t i = 0; i < g->low.size(); ++i) {
+      SegInfo S{};
+      S.prob = int(p);
+      S.kind = 1;
+      S.lx = g->low[i].lx;
+      S.lv = g->low[i].lv;
+      S.nx = int(g->low[i].nx);
+      S.nv = int(g->low[i].nv);
+      S.R = Rs;
+      S.off = low_start[i];
+      S.len = int64_t(Rs) * S.nx * S.nv;
+      S.src_off = up_res[i + 1];
+      S.low_off = -1;
+      S.nx_src = int(g->up[i + 1].nx);
+      fill_domain_ptrs(o, S);
+      T->host.push_back(S);
+    }
+    ct = c;
+    up = u;
+  }
+  finish_tab(*T);
+  SegTab& ref = *T;
+  B.ct_tabs[Rs] = std::move(T);
+  return ref;
+}
+
+// one segment per problem over the upper-diagonal layout with Rs slices
+static SegTab& prob_tab(Batch& B, int Rs) {
+  auto it = B.prob_tabs.find(Rs);
+  if (it != B.prob_tabs.end()) return *it->second;
+  auto T = std::make_unique<SegTab>();
+  int64_t off = 0;
+  for (size_t p = 0; p < B.P.size(); ++p) {
+    SegInfo S{};
+    S.prob = int(p);
+    S.kind = 2;
+    S.R = Rs;
+    S.off = off;
+    S.len = int64_t(Rs) * up_pts(B.P[p]);
+    S.low_off = -1;
+    off += S.len;
+    T->host.push_back(S);
+  }
+  finish_tab(*T);
+  SegTab& ref = *T;
+  B.prob_tabs[Rs] = std::move(T);
+  return ref;
+}
+
+// single problem: one segment per upper grid over points (jump term)
+static SegTab& pts_tab(Batch& B) {
+  if (B.pts) return *B.pts;
+  auto T = std::make_unique<SegTab>();
+  sgdg_grid g = B.P[0]->grid;
+  int64_t po = 0;
+  for (auto& gd : g->up) {
+    SegInfo S{};
+    S.kind = 0;
+    S.lx = gd.lx;
+    S.lv = gd.lv;
+    S.nx = int(gd.nx);
+    S.nv = int(gd.nv);
+    S.R = B.R;
+    S.off = int64_t(B.R) * po;
+    S.src_off = po;
+    S.len = gd.nx * gd.nv;
+    S.low_off = -1;
+    po += gd.nx * gd.nv;
+    T->host.push_back(S);
+  }
+  finish_tab(*T);
+  B.pts = std::move(T);
+  return *B.pts;
+}
+
+// ------------------------------------------------------ batched GMRES -----
+static GmresState gstate(GBufs& b, int nseg, int m) {
+  b.H.ensure(sizeof(double) * nseg * (m + 1) * m);
+  b.cs.ensure(sizeof(double) * nseg * m);
+  b.sn.ensure(sizeof(double) * nseg * m);
+  b.g.ensure(sizeof(double) * nseg * (m + 1));
+  b.bn.ensure(sizeof(double) * nseg);
+  b.beta.ensure(sizeof(double) * nseg);
+  b.act.ensure(sizeof(int) * nseg);
+  b.k.ensure(sizeof(int) * nseg);
+  b.hc.ensure(sizeof(double) * nseg * (m + 1));
+  b.inv.ensure(sizeof(double) * nseg);
+  b.y.ensure(sizeof(double) * nseg * m);
+  GmresState st;
+  st.H = ptr<double>(b.H);
+  st.cs = ptr<double>(b.cs);
+  st.sn = ptr<double>(b.sn);
+  st.g = ptr<double>(b.g);
+  st.bnorm = ptr<double>(b.bn);
+  st.beta = ptr<double>(b.beta);
+  st.active = ptr<int>(b.act);
+  st.kused = ptr<int>(b.k);
+  st.hcol = ptr<double>(b.hc);
+  st.inv = ptr<double>(b.inv);
+  st.y = ptr<double>(b.y);
+  st.m = m;
+  return st;
+}
+
+// Right-preconditioned restarted GMRES on the independent grid problems
+// A_{l,l} dU_l = r_l (one segment each), preconditioner M fixed and linear.
+// A cycle of m iterations needs no host synchronisation.  Eagerly, the host
+// polls the convergence flags every 8 iterations; with use_graph the whole
+// cycle is captured once (per buffer set) and replayed, and converged
+// segments idle through the remaining iterations.
+template <class T>
+static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(const T*, T*, hipStream_t)>& A,
+                         const std::function<void(const T*, T*, hipStream_t)>& M, const T* b, T* x, T* V, T* w, T* tmp, int m,
+                         int maxit, double tol, bool use_graph, hipStream_t s, bool* nan) {
+  const SegTable& S = ST.t;
+  const int nseg = S.nseg;
+  const int64_t total = ST.host.back().off + ST.host.back().len;
+  GBufs& gb = B.gb[0];
+  gb.partial.ensure(sizeof(double) * size_t(S.nchunks) * (m + 1));
+  double* part = ptr<double>(gb.partial);
+  GmresState st = gstate(gb, nseg, m);
+  KernelsT<T>::fill(total, T(0), x, s);
+  std::vector<int> act(nseg);
+  bool bad = false;
+  int it = 0;
+  auto step = [&](int j, hipStream_t q) {
+    M(V + int64_t(j) * total, tmp, q);
+    A(tmp, w, q);
+    for (int pass = 0; pass < 2; ++pass) {
+      KernelsT<T>::seg_dots(S, V, total, j + 1, w, part, q);
+      gmres_add_proj(nseg, st, S.segs, part, j, q);
+      KernelsT<T>::seg_axpy(S, V, total, j + 1, st.hcol, m + 1, w, -1.0, pass == 1 ? part : nullptr, q);
+    }
+    gmres_givens(nseg, st, S.segs, part, j, tol, q);
+    KernelsT<T>::seg_scale(S, w, st.inv, V + int64_t(j + 1) * total, q);
+  };
+  auto any_active = [&]() {
+    SGDG_CHECK_HIP(hipMemcpyAsync(act.data(), st.active, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+    SGDG_CHECK_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int a : act) {
+      any = any || a == 1;
+      bad = bad || a == -1;
+    }
+    return any;
+  };
+  for (int cycle = 0; it < maxit; ++cycle) {
+    KernelsT<T>::copy(total, b, V, s);
+    if (cycle > 0) {
+      A(x, w, s);
+      KernelsT<T>::axpby(total, T(-1), w, T(1), V, s);
+    }
+    KernelsT<T>::seg_norm2(S, V, part, s);
+    gmres_start(nseg, st, S.segs, part, tol, cycle == 0, s);
+    KernelsT<T>::seg_scale(S, V, st.inv, V, s);
+    if (!any_active()) break;
+    const int mm = std::min(m, maxit - it);
+    int j = 0;
+    if (use_graph && mm == m) {
+      std::ostringstream key;
+      key << sizeof(T) << '/' << m << '/' << total << '/' << (const void*)V << '/' << (const void*)w << '/'
+          << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b;
+      auto g = B.graphs.find(key.str());
+      if (g == B.graphs.end()) {
+        // capture on a private stream (the caller's may be the null stream, which cannot be captured)
+        if (!B.cap_stream) SGDG_CHECK_HIP(hipStreamCreate(&B.cap_stream));
+        const bool prof = B.prof;
+        B.prof = false;
+        hipGraph_t graph = nullptr;
+        SGDG_CHECK_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+          for (int jj = 0; jj < m; ++jj) step(jj, B.cap_stream);
+        } catch (...) {
+          (void)hipStreamEndCapture(B.cap_stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          B.prof = prof;
+          throw;
+        }
+        B.prof = prof;
+        SGDG_CHECK_HIP(hipStreamEndCapture(B.cap_stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        SGDG_CHECK_HIP(e);
+        g = B.graphs.emplace(key.str(), exec).first;
+      }
+      timed(B, 2, s, [&] { SGDG_CHECK_HIP(hipGraphLaunch(g->second, s)); });
+      j = m;
+    } else {
+      timed(B, 2, s, [&] {
+        for (; j < mm; ++j) {
+          step(j, s);
+          if ((j + 1) % 8 == 0 && j + 1 < mm && !any_active()) {
+            ++j;
+            break;
+          }
+        }
+      });
+    }
+    it += j;
+    gmres_lsq(nseg, st, s);
+    KernelsT<T>::fill(total, T(0), w, s);
+    KernelsT<T>::seg_axpy(S, V, total, j, st.y, m, w, 1.0, nullptr, s);
+    M(w, tmp, s);
+    KernelsT<T>::axpby(total, T(1), tmp, T(1), x, s);
+  }
+  *nan = *nan || bad;
+  return it;
+}
+
+// --------------------------------------------------- CT preconditioner ----
+template <class T>
+static void ct_apply(Batch& B, const T* r, T* z, const sgdg_precond_opts& po, bool use_graph, hipStream_t s,
+                     bool* nan) {
+  SegTab& ST = ct_tab(B, B.R);
+  const int64_t nct = kind(B, K_CT).total;
+  BWork<T>& w = work<T>(B);
+  const int m = std::max(1, std::min(po.inner_restart, 64));
+  w.ctb.ensure(sizeof(T) * nct);
+  w.ctx.ensure(sizeof(T) * nct);
+  w.ctw.ensure(sizeof(T) * nct);
+  w.cttmp.ensure(sizeof(T) * nct);
+  w.ctV.ensure(sizeof(T) * nct * (m + 1));
+  T* b = ptr<T>(w.ctb);
+  KernelsT<T>::ct_gather(ST.t, r, b, s);
+  items(B, K_CT, int(sizeof(T)));  // tables exist before any capture
+  auto A = [&](const T* in, T* out, hipStream_t q) { apply<T>(B, K_CT, in, out, 1, q); };
+  auto M = [&](const T* in, T* out, hipStream_t q) { KernelsT<T>::minv(ST.t, in, out, q); };
+  B.inner_iters += batched_gmres<T>(B, ST, A, M, b, ptr<T>(w.ctx), ptr<T>(w.ctV), ptr<T>(w.ctw), ptr<T>(w.cttmp), m,
+                                    po.inner_maxit, po.inner_rtol, use_graph, s, nan);
+  KernelsT<T>::ct_combine(ST.t, ptr<T>(w.ctx), z, s);
+}
+
+static sgdg_precond_opts default_pc() {
+  sgdg_precond_opts p;
+  p.kind = 0;
+  p.inner_rtol = 1e-8;
+  p.inner_maxit = 200;
+  p.inner_restart = 30;
+  p.mass_sweeps = 0;
+  return p;
+}
+
+// ------------------------------------------------------------- FGMRES -----
+struct FgmresResult {
+  int iters = 0;
+  double rel = 0;  // largest relative residual over the problems
+  bool nan = false;
+};
+
+static std::vector<double> seg_norms(Batch& B, const SegTab& ST, const double* v, hipStream_t s) {
+  GBufs& gb = B.gb[2];
+  gb.partial.ensure(sizeof(double) * ST.t.nchunks);
+  KernelsT<double>::seg_norm2(ST.t, v, ptr<double>(gb.partial), s);
+  std::vector<double> h(ST.t.nchunks);
+  SGDG_CHECK_HIP(hipMemcpyAsync(h.data(), gb.partial.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  SGDG_CHECK_HIP(hipStreamSynchronize(s));
+  std::vector<double> out(ST.host.size(), 0.0);
+  for (size_t i = 0; i < ST.host.size(); ++i) {
+    double a = 0;
+    for (int c = 0; c < ST.host[i].nchunk; ++c) a += h[ST.host[i].chunk0 + c];
+    out[i] = std::sqrt(a);
+  }
+  return out;
+}
+
+// Flexible GMRES on every problem of the batch in lockstep (one segment per
+// problem, FP64 Arnoldi), stopping per problem at ||b - A u|| <= tol ||b||.
+static FgmresResult fgmres(Batch& B, const std::function<void(const double*, double*)>& A,
+                           const std::function<void(const double*, double*)>& P, const double* b, double* x,
+                           double tol, int m, int maxit, hipStream_t s) {
+  SegTab& ST = prob_tab(B, B.R);
+  const SegTable& S = ST.t;
+  const int nseg = S.nseg;
+  const int64_t n = kind(B, K_FULL).total;
+  B.fV.ensure(sizeof(double) * n * (m + 1));
+  B.fZ.ensure(sizeof(double) * n * m);
+  B.fw.ensure(sizeof(double) * n);
+  double* V = ptr<double>(B.fV);
+  double* Z = ptr<double>(B.fZ);
+  double* w = ptr<double>(B.fw);
+  GBufs& gb = B.gb[1];
+  gb.partial.ensure(sizeof(double) * size_t(S.nchunks) * (m + 1));
+  double* part = ptr<double>(gb.partial);
+  GmresState st = gstate(gb, nseg, m);
+  const bool verbose = getenv("SGDG_VERBOSE") != nullptr;
+  FgmresResult res;
+  // ||b|| per problem into st.bnorm
+  KernelsT<double>::seg_norm2(S, b, part, s);
+  gmres_start(nseg, st, S.segs, part, 0.0, 1, s);
+  const std::vector<double> bn = seg_norms(B, ST, b, s);
+  for (double v : bn)
+    if (!std::isfinite(v)) {
+      res.nan = true;
+      return res;
+    }
+  for (int i = 0; i < nseg; ++i)  // b = 0 has the solution 0
+    if (bn[i] == 0.0) KernelsT<double>::fill(ST.host[i].len, 0.0, x + ST.host[i].off, s);
+  std::vector<int> act(nseg);
+  std::vector<double> beta(nseg);
+  for (;;) {
+    A(x, w);
+    KernelsT<double>::copy(n, b, V, s);
+    KernelsT<double>::axpby(n, -1.0, w, 1.0, V, s);
+    const std::vector<double> rn = seg_norms(B, ST, V, s);
+    res.rel = 0;
+    bool nanr = false;
+    for (int i = 0; i < nseg; ++i) {
+      const double rel = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+      nanr = nanr || !std::isfinite(rel);
+      res.rel = std::max(res.rel, rel);
+    }
+    if (verbose) fprintf(stderr, "[sgdg fgmres] true residual %.3e after %d\n", res.rel, res.iters);
+    if (nanr) {
+      res.nan = true;
+      return res;
+    }
+    if (res.rel <= tol || res.iters >= maxit) return res;
+    KernelsT<double>::seg_norm2(S, V, part, s);
+    gmres_start(nseg, st, S.segs, part, tol, 0, s);  // converged problems start inactive
+    KernelsT<double>::seg_scale(S, V, st.inv, V, s);
+    const int mm = std::min(m, maxit - res.iters);
+    int j = 0;
+    for (; j < mm; ++j) {
+      P(V + int64_t(j) * n, Z + int64_t(j) * n);
+      A(Z + int64_t(j) * n, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        KernelsT<double>::seg_dots(S, V, n, j + 1, w, part, s);
+        gmres_add_proj(nseg, st, S.segs, part, j, s);
+        KernelsT<double>::seg_axpy(S, V, n, j + 1, st.hcol, m + 1, w, -1.0, pass == 1 ? part : nullptr, s);
+      }
+      gmres_givens(nseg, st, S.segs, part, j, tol * 0.5, s);
+      KernelsT<double>::seg_scale(S, w, st.inv, V + int64_t(j + 1) * n, s);
+      SGDG_CHECK_HIP(hipMemcpyAsync(act.data(), st.active, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+      SGDG_CHECK_HIP(hipMemcpyAsync(beta.data(), st.beta, sizeof(double) * nseg, hipMemcpyDeviceToHost, s));
+      SGDG_CHECK_HIP(hipStreamSynchronize(s));
+      bool any = false, bad = false;
+      double est = 0;
+      for (int i = 0; i < nseg; ++i) {
+        any = any || act[i] == 1;
+        bad = bad || act[i] == -1;
+        if (bn[i] > 0) est = std::max(est, beta[i] / bn[i]);
+      }
+      if (verbose) fprintf(stderr, "[sgdg fgmres] it %d  est %.3e\n", res.iters + j + 1, est);
+      if (bad) {
+        res.nan = true;
+        return res;
+      }
+      if (!any) {
+        ++j;
+        break;
+      }
+    }
+    res.iters += j;
+    gmres_lsq(nseg, st, s);
+    KernelsT<double>::seg_axpy(S, Z, n, j, st.y, m, x, 1.0, nullptr, s);
+  }
+}
+
+static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const sgdg_solve_opts& so, hipStream_t s,
+                                    bool* nan) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = kind(B, K_FULL).total;
+  sgdg_precond_opts pc = so.pc;
+  if (pc.inner_restart <= 0) pc = default_pc();
+  const bool graph = so.use_graph != 0;
+  B.inner_iters = 0;
+  auto A64 = [&](const double* in, double* out) { apply<double>(B, K_FULL, in, out, 1, s); };
+  auto P64 = [&](const double* in, double* out) { ct_apply<double>(B, in, out, pc, graph, s, nan); };
+  sgdg_solve_stats st{};
+  if (!so.mixed_precision) {
+    FgmresResult r = fgmres(B, A64, P64, b, u, so.rtol, so.restart, so.maxit, s);
+    st.outer_iters = r.iters;
+    st.rel_residual = r.rel;
+    *nan = *nan || r.nan;
+  } else {
+    // FP64 iterative refinement; each correction solved by FGMRES with FP32
+    // operator applications and an FP32 combination-technique preconditioner.
+    B.a32.ensure(sizeof(float) * n);
+    B.b32.ensure(sizeof(float) * n);
+    B.fr.ensure(sizeof(double) * n);
+    B.fe.ensure(sizeof(double) * n);
+    B.ftmp.ensure(sizeof(double) * n);
+    float* a32 = ptr<float>(B.a32);
+    float* b32 = ptr<float>(B.b32);
+    sgdg_precond_opts pc32 = pc;
+    pc32.inner_rtol = std::max(pc.inner_rtol, 1e-5);  // FP32 grid problems cannot reach FP64 tolerances
+    auto A32 = [&](const double* in, double* out) {
+      convert_f64_to_f32(n, in, a32, s);
+      apply<float>(B, K_FULL, a32, b32, 1, s);
+      convert_f32_to_f64(n, b32, out, s);
+    };
+    auto P32 = [&](const double* in, double* out) {
+      convert_f64_to_f32(n, in, a32, s);
+      ct_apply<float>(B, a32, b32, pc32, graph, s, nan);
+      convert_f32_to_f64(n, b32, out, s);
+    };
+    double* rr = ptr<double>(B.fr);
+    double* e = ptr<double>(B.fe);
+    double* tmp = ptr<double>(B.ftmp);
+    const double inner_tol = so.inner_outer_rtol > 0 ? so.inner_outer_rtol : 1e-4;
+    SegTab& ST = prob_tab(B, B.R);
+    const std::vector<double> bn = seg_norms(B, ST, b, s);
+    int total = 0, steps = 0;
+    double rel = 1;
+    for (;;) {
+      A64(u, tmp);
+      KernelsT<double>::copy(n, b, rr, s);
+      KernelsT<double>::axpby(n, -1.0, tmp, 1.0, rr, s);
+      const std::vector<double> rn = seg_norms(B, ST, rr, s);
+      rel = 0;
+      for (size_t i = 0; i < rn.size(); ++i) rel = std::max(rel, bn[i] > 0 ? rn[i] / bn[i] : 0.0);
+      if (!std::isfinite(rel)) {
+        *nan = true;
+        break;
+      }
+      if (rel <= so.rtol || total >= so.maxit || steps >= 20) break;
+      KernelsT<double>::fill(n, 0.0, e, s);
+      FgmresResult ri = fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s);
+      total += std::max(ri.iters, 1);
+      ++steps;
+      if (ri.nan) {
+        *nan = true;
+        break;
+      }
+      KernelsT<double>::axpby(n, 1.0, e, 1.0, u, s);
+    }
+    st.outer_iters = total;
+    st.refinement_steps = steps;
+    st.rel_residual = rel;
+  }
+  SGDG_CHECK_HIP(hipStreamSynchronize(s));
+  st.inner_iters_total = int(B.inner_iters);
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+// ------------------------------------------------------------------ data --
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0);
+  w.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pn = n == 1 ? z : p1, pm = n == 1 ? 1 : p0;
+      dp = n * (z * pn - pm) / (z * z - 1);
+      const double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double pn = n == 1 ? z : p1, pm = n == 1 ? 1 : p0;
+    dp = n * (z * pn - pm) / (z * z - 1);
+    x[i] = z;
+    w[i] = 2.0 / ((1 - z * z) * dp * dp);
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(n), ws(n);
+  for (int i = 0; i < n; ++i) {
+    xs[i] = x[idx[i]];
+    ws[i] = w[idx[i]];
+  }
+  x = xs;
+  w = ws;
+}
+
+static double legendre(int s, double z) {
+  if (s == 0) return 1;
+  double p0 = 1, p1 = z;
+  for (int k = 2; k <= s; ++k) {
+    const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// nodal [nq][up nodes + low nodes] -> slices (projection weights) in the CT
+// layout [upper grids][lower grids] -> combination into spanning coefficients
+static void nodal_to_coef(Batch& B, const double* samples, int nq, const double* wts_host, int Rs, double* coef,
+                          hipStream_t s) {
+  sgdg_grid g = B.P[0]->grid;
+  const int64_t nall = g->up_pts + g->low_pts;
+  B.rhs_w.ensure(sizeof(double) * Rs * nq);
+  SGDG_CHECK_HIP(hipStreamSynchronize(s));  // rhs_w may still be read by earlier work
+  SGDG_CHECK_HIP(hipMemcpy(B.rhs_w.p, wts_host, sizeof(double) * Rs * nq, hipMemcpyHostToDevice));
+  B.rhs_a.ensure(sizeof(double) * Rs * nall);
+  B.rhs_b.ensure(sizeof(double) * Rs * nall);
+  double* proj = ptr<double>(B.rhs_a);
+  double* blk = ptr<double>(B.rhs_b);
+  project_time(nall, nq, Rs, ptr<double>(B.rhs_w), samples, proj, s);
+  int64_t node = 0, out = 0;
+  for (int part = 0; part < 2; ++part) {
+    const auto& gs = part == 0 ? g->up : g->low;
+    for (const auto& gd : gs) {
+      const int64_t np = gd.nx * gd.nv;
+      for (int sl = 0; sl < Rs; ++sl)
+        SGDG_CHECK_HIP(hipMemcpyAsync(blk + out + sl * np, proj + int64_t(sl) * nall + node, sizeof(double) * np,
+                                      hipMemcpyDeviceToDevice, s));
+      node += np;
+      out += int64_t(Rs) * np;
+    }
+  }
+  KernelsT<double>::ct_combine(ct_tab(B, Rs).t, blk, coef, s);
+}
+
+// ================================================================== ABI ===
+extern "C" sgdg_status sgdg_apply_operator(sgdg_ops o, int kind_, const void* u_dev, void* y_dev, sgdg_dtype t,
+                                           int batch, hipStream_t s) {
+  API_BEGIN
+  require(o != nullptr, "null ops");
+  require(kind_ >= SGDG_OP_FULL && kind_ <= SGDG_OP_DATA_G, "unknown operator kind");
+  require(u_dev && y_dev && u_dev != y_dev, "u and y must be distinct non-null device buffers");
+  require(batch >= 1, "batch must be >= 1");
+  require(t == SGDG_F64 || t == SGDG_F32, "dtype must be F64 or F32");
+  static const int map[5] = {K_FULL, K_DIAG, K_MASS, K_DATAF, K_DATAG};
+  Batch& B = self_batch(o);
+  if (t == SGDG_F64) apply<double>(B, map[kind_], static_cast<const double*>(u_dev), static_cast<double*>(y_dev), batch, s);
+  else apply<float>(B, map[kind_], static_cast<const float*>(u_dev), static_cast<float*>(y_dev), batch, s);
+  API_END
+}
+
+extern "C" sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_dev, sgdg_dtype t, int batch,
+                                         const sgdg_precond_opts* po_in, hipStream_t s) {
+  API_BEGIN
+  require(o && r_dev && z_dev && r_dev != z_dev, "null or aliased argument");
+  require(batch == 1, "precondition supports batch == 1");
+  const sgdg_precond_opts po = po_in ? *po_in : default_pc();
+  require(po.kind == 0, "only the combination-technique preconditioner (kind 0) is available");
+  require(po.inner_rtol > 0 && po.inner_maxit >= 1 && po.inner_restart >= 1, "invalid inner solver options");
+  Batch& B = self_batch(o);
+  bool nan = false;
+  if (t == SGDG_F64)
+    ct_apply<double>(B, static_cast<const double*>(r_dev), static_cast<double*>(z_dev), po, false, s, &nan);
+  else
+    ct_apply<float>(B, static_cast<const float*>(r_dev), static_cast<float*>(z_dev), po, false, s, &nan);
+  if (nan) throw Error{SGDG_E_NAN, "non-finite residual in a grid problem"};
+  API_END
+}
+
+extern "C" sgdg_status sgdg_combine(sgdg_ops o, const double* nodal_dev, double* coef_dev, int nslices, hipStream_t s) {
+  API_BEGIN
+  require(o && nodal_dev && coef_dev, "null argument");
+  require(nslices >= 1 && nslices <= kMaxR, "nslices must be 1..3");
+  std::vector<double> wts(nslices * nslices, 0.0);
+  for (int i = 0; i < nslices; ++i) wts[i * nslices + i] = 1.0;
+  nodal_to_coef(self_batch(o), nodal_dev, nslices, wts.data(), nslices, coef_dev, s);
+  API_END
+}
+
+extern "C" sgdg_status sgdg_rhs(sgdg_ops o, const double* u_prev_dev, int prev_slices, const double* f_nodal_dev,
+                                const double* g_nodal_dev, double* b_dev, hipStream_t s) {
+  API_BEGIN
+  require(o && u_prev_dev && b_dev, "null argument");
+  require(prev_slices >= 1 && prev_slices <= kMaxR, "prev_slices must be 1..3");
+  Batch& B = self_batch(o);
+  sgdg_grid g = o->grid;
+  const int R = g->R;
+  const int64_t npts = g->up_pts;
+  // jump term (U_{j-1}^-, w_{j-1}^+)
+  B.rhs_c.ensure(sizeof(double) * 2 * npts);
+  double* tr = ptr<double>(B.rhs_c);
+  double* mtr = tr + npts;
+  SegTab& PT = pts_tab(B);
+  trace_sum(PT.t, prev_slices, u_prev_dev, tr, s);
+  apply<double>(B, K_MASS, tr, mtr, 1, s);
+  spread_left(PT.t, mtr, b_dev, s);
+  // data functionals of f and g
+  if (f_nodal_dev || g_nodal_dev) {
+    const int nq = g->r + 2;
+    std::vector<double> xg, wg;
+    gauss_legendre(nq, xg, wg);
+    std::vector<double> wts(R * nq);
+    // c_s = (2s+1)/dt int f eta_s = (2s+1)/2 sum_q wg_q P_s(xg_q) f_q
+    for (int k = 0; k < R; ++k)
+      for (int q = 0; q < nq; ++q) wts[k * nq + q] = 0.5 * (2 * k + 1) * wg[q] * legendre(k, xg[q]);
+    const int64_t ndof = int64_t(R) * npts;
+    B.rhs_d.ensure(sizeof(double) * 2 * ndof);
+    double* coef = ptr<double>(B.rhs_d);
+    double* out = coef + ndof;
+    for (int which = 0; which < 2; ++which) {
+      const double* smp = which == 0 ? f_nodal_dev : g_nodal_dev;
+      if (!smp) continue;
+      if (o->ops[which == 0 ? 2 : 3].op.nterms == 0) continue;
+      nodal_to_coef(B, smp, nq, wts.data(), R, coef, s);
+      apply<double>(B, which == 0 ? K_DATAF : K_DATAG, coef, out, 1, s);
+      KernelsT<double>::axpby(ndof, 1.0, out, 1.0, b_dev, s);
+    }
+  }
+  API_END
+}
+
+static void check_solve_opts(const sgdg_solve_opts* so) {
+  require(so != nullptr, "null solver options");
+  require(so->rtol > 0 && so->restart >= 1 && so->restart <= 64 && so->maxit >= 1, "invalid solver options");
+}
+
+extern "C" sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
+                                        sgdg_solve_stats* st, hipStream_t s) {
+  API_BEGIN
+  require(o && b_dev && u_dev, "null argument");
+  check_solve_opts(so);
+  bool nan = false;
+  const sgdg_solve_stats stats = solve_batch(self_batch(o), b_dev, u_dev, *so, s, &nan);
+  if (st) *st = stats;
+  if (nan) throw Error{SGDG_E_NAN, "non-finite residual norm"};
+  if (stats.rel_residual > so->rtol) throw Error{SGDG_E_NOCONV, "iteration limit reached before the tolerance"};
+  API_END
+}
+
+// ------------------------------------------------------------ batch ABI ---
+extern "C" sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch* out) {
+  API_BEGIN
+  require(ops && out && n >= 1, "need n >= 1 ops handles");
+  for (int i = 0; i < n; ++i) require(ops[i] != nullptr, "null ops handle");
+  const int d = ops[0]->X.dom.d, r = ops[0]->grid->r, dev = ops[0]->device;
+  for (int i = 1; i < n; ++i) {
+    require(ops[i]->X.dom.d == d, "all problems of a batch must share the dimension");
+    require(ops[i]->grid->r == r, "all problems of a batch must share the time degree");
+    require(ops[i]->device == dev, "all problems of a batch must live on one device");
+  }
+  auto* b = new Batch;
+  b->P.assign(ops, ops + n);
+  b->d = d;
+  b->R = r + 1;
+  *out = b;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_batch_layout(sgdg_batch b, int64_t* offsets) {
+  API_BEGIN
+  require(b && offsets, "null argument");
+  int64_t off = 0;
+  for (size_t i = 0; i < b->P.size(); ++i) {
+    offsets[i] = off;
+    off += int64_t(b->R) * b->P[i]->grid->up_pts;
+  }
+  offsets[b->P.size()] = off;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_batch_apply(sgdg_batch b, const void* u_dev, void* y_dev, sgdg_dtype t, hipStream_t s) {
+  API_BEGIN
+  require(b && u_dev && y_dev && u_dev != y_dev, "null or aliased argument");
+  if (t == SGDG_F64) apply<double>(*b, K_FULL, static_cast<const double*>(u_dev), static_cast<double*>(y_dev), 1, s);
+  else apply<float>(*b, K_FULL, static_cast<const float*>(u_dev), static_cast<float*>(y_dev), 1, s);
+  API_END
+}
+
+extern "C" sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
+                                        sgdg_solve_stats* st, hipStream_t s) {
+  API_BEGIN
+  require(b && b_dev && u_dev, "null argument");
+  check_solve_opts(so);
+  bool nan = false;
+  const sgdg_solve_stats stats = solve_batch(*b, b_dev, u_dev, *so, s, &nan);
+  if (st) *st = stats;
+  if (nan) throw Error{SGDG_E_NAN, "non-finite residual norm"};
+  if (stats.rel_residual > so->rtol) throw Error{SGDG_E_NOCONV, "iteration limit reached before the tolerance"};
+  API_END
+}
+
+extern "C" void sgdg_batch_destroy(sgdg_batch b) { delete b; }
+
+// ---------------------------------------------------------- diagnostics ---
+extern "C" sgdg_status sgdg_profile(sgdg_ops o, int mode) {
+  API_BEGIN
+  require(o != nullptr, "null ops");
+  Batch& B = self_batch(o);
+  drain_events(B);
+  if (mode == 1)
+    for (int i = 0; i < 3; ++i) {
+      B.prof_ms[i] = 0;
+      B.prof_n[i] = 0;
+    }
+  B.prof = mode == 1;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launches) {
+  API_BEGIN
+  require(o != nullptr && slot >= 0 && slot < 3, "bad slot");
+  Batch& B = self_batch(o);
+  drain_events(B);
+  if (ms) *ms = B.prof_ms[slot];
+  if (launches) *launches = B.prof_n[slot];
+  API_END
+}
+
+extern "C" sgdg_status sgdg_op_info(sgdg_ops o, int kind_, int* nterms, int* nvg, int* nxg, int* Sx, int* Sv,
+                                    int* Rin, int* Rout) {
+  API_BEGIN
+  require(o != nullptr && kind_ >= SGDG_OP_FULL && kind_ <= SGDG_OP_DATA_G, "bad arguments");
+  const int idx = kind_ == SGDG_OP_FULL || kind_ == SGDG_OP_BLOCKDIAG ? 0 : kind_ - 1;
+  const DevOp& op = o->ops[idx].op;
+  if (nterms) *nterms = op.nterms;
+  if (nvg) *nvg = op.nvg;
+  if (nxg) *nxg = op.nxg;
+  if (Sx) *Sx = o->dx.d.S;
+  if (Sv) *Sv = o->dv.d.S;
+  if (Rin) *Rin = op.Rin;
+  if (Rout) *Rout = op.Rout;
+  API_END
+}

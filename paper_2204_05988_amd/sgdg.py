@@ -23,6 +23,7 @@ EXPORTS = [
     "sgdg_assemble_1d_factors", "sgdg_ops_destroy", "sgdg_apply_operator", "sgdg_combine",
     "sgdg_precondition", "sgdg_rhs", "sgdg_solve_strip", "sgdg_debug_dense_block",
     "sgdg_profile", "sgdg_profile_read", "sgdg_op_info",
+    "sgdg_batch_create", "sgdg_batch_layout", "sgdg_batch_apply", "sgdg_batch_solve", "sgdg_batch_destroy",
 ]
 
 
@@ -53,7 +54,7 @@ class PrecondOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("mixed_precision", C.c_int),
-                ("inner_outer_rtol", C.c_double), ("pc", PrecondOpts)]
+                ("inner_outer_rtol", C.c_double), ("pc", PrecondOpts), ("use_graph", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -91,8 +92,14 @@ def lib():
     L.sgdg_profile.argtypes = [vp, C.c_int]
     L.sgdg_profile_read.argtypes = [vp, C.c_int, dp, i64p]
     L.sgdg_op_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip, ip, ip]
+    L.sgdg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
+    L.sgdg_batch_layout.argtypes = [vp, i64p]
+    L.sgdg_batch_apply.argtypes = [vp, vp, vp, C.c_int, vp]
+    L.sgdg_batch_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+    L.sgdg_batch_destroy.argtypes = [vp]
+    L.sgdg_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy"):
+        if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy"):
             getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -163,8 +170,10 @@ def default_precond_opts(inner_rtol=1e-8, inner_maxit=200, inner_restart=30, mas
     return PrecondOpts(0, inner_rtol, inner_maxit, inner_restart, mass_sweeps)
 
 
-def default_solve_opts(rtol=1e-8, restart=50, maxit=400, mixed=False, inner_outer_rtol=1e-4, pc=None) -> SolveOpts:
-    return SolveOpts(rtol, restart, maxit, int(mixed), inner_outer_rtol, pc or default_precond_opts())
+def default_solve_opts(rtol=1e-8, restart=50, maxit=400, mixed=False, inner_outer_rtol=1e-4, pc=None,
+                       use_graph=False) -> SolveOpts:
+    return SolveOpts(rtol, restart, maxit, int(mixed), inner_outer_rtol, pc or default_precond_opts(),
+                     int(use_graph))
 
 
 class SparseGridOps:
@@ -269,6 +278,52 @@ class SparseGridOps:
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return u, st
+
+
+class SparseGridBatch:
+    """Independent strip problems applied and solved together (one launch per
+    kernel for the whole batch).  Vectors are the concatenation of the
+    problems' vectors, problem i at offsets[i]."""
+
+    def __init__(self, ops_list):
+        L = lib()
+        self.members = list(ops_list)  # keeps the ops handles alive
+        arr = (C.c_void_p * len(self.members))(*[m.ops.value for m in self.members])
+        h = C.c_void_p()
+        _check(L.sgdg_batch_create(arr, len(self.members), C.byref(h)))
+        self.h = h
+        off = (C.c_int64 * (len(self.members) + 1))()
+        _check(L.sgdg_batch_layout(h, off))
+        self.offsets = [int(off[i]) for i in range(len(self.members) + 1)]
+        self.ndof = self.offsets[-1]
+
+    def apply(self, u, y, stream=None):
+        import torch
+        dt = F64 if u.dtype == torch.float64 else F32
+        assert u.is_cuda and y.is_cuda and u.is_contiguous() and y.is_contiguous() and u.dtype == y.dtype
+        assert u.numel() == self.ndof and y.numel() == self.ndof, "shape mismatch"
+        _check(lib().sgdg_batch_apply(self.h, _ptr(u), _ptr(y), dt, _stream(stream)))
+        return y
+
+    def solve(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
+        assert b.numel() == self.ndof and u.numel() == self.ndof
+        o = opts or default_solve_opts()
+        st = SolveStats()
+        code = lib().sgdg_batch_solve(self.h, _ptr(b), _ptr(u), C.byref(o), C.byref(st), _stream(stream))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        return u, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sgdg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_dense_block(w, kind, row_grid, col_grid, fields=None):

@@ -1,0 +1,163 @@
+"""Batched problems and captured GMRES cycles on the GPU, against the oracle.
+
+A batch concatenates independent strip problems of different levels and
+coefficients (the uneven many-problem workload: 4D problems with
+beta = (v, a_i), sigma_i, Fourier forcing).  Each member of a batched
+apply must equal the oracle's operator to 1e-10 and the single-problem
+launch bit for bit; batched solves must reach the tolerance under the
+oracle's operator for every member.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import config_c2, config_c4_member, random_vector
+from oracle.operator import Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_05988_amd import sgdg
+    sgdg.lib()
+    return torch.device("cuda:0")
+
+
+_members = {}
+
+
+def _member(i, L):
+    key = (i, L)
+    if key not in _members:
+        from paper_2204_05988_amd import sgdg
+        w = config_c4_member(i, L=L)
+        _members[key] = (w, Problem(w), sgdg.SparseGridOps(w))
+    return _members[key]
+
+
+# uneven members: three levels, four different coefficient sets
+MEMBERS = [(0, 3), (1, 4), (2, 2), (3, 4)]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_batch_apply_matches_oracle_and_single(dev):
+    from paper_2204_05988_amd import sgdg
+    mem = [_member(i, L) for i, L in MEMBERS]
+    batch = sgdg.SparseGridBatch([m[2] for m in mem])
+    off = batch.offsets
+    assert off[-1] == sum(m[1].ndof for m in mem)
+    u = random_vector(batch.ndof, 11)[0]
+    _say(f"batched apply of {len(mem)} c4 members, n={batch.ndof}")
+    ut = torch.tensor(u, device=dev)
+    yt = torch.empty_like(ut)
+    batch.apply(ut, yt)
+    y32 = torch.empty(batch.ndof, dtype=torch.float32, device=dev)
+    batch.apply(ut.float(), y32)
+    torch.cuda.synchronize()
+    for k, (w, P, ops) in enumerate(mem):
+        a, b = off[k], off[k + 1]
+        ref = P.apply(u[a:b])
+        err = _rel(yt[a:b].cpu().numpy(), ref)
+        err32 = _rel(y32[a:b].double().cpu().numpy(), ref)
+        _say(f"  member {k} L={w.L}: fp64 rel err {err:.2e}, fp32 {err32:.2e}")
+        assert err <= 1e-10
+        assert err32 <= 2e-5
+        ys = torch.empty(b - a, dtype=torch.float64, device=dev)
+        ops.apply(ut[a:b].contiguous(), ys)
+        torch.cuda.synchronize()
+        assert torch.equal(ys, yt[a:b])
+
+
+def _fnorm(P, e):
+    tot = 0.0
+    blocks = P.split(e)
+    for s in range(P.R):
+        v = np.concatenate([blk[s].ravel() for blk in blocks])
+        tot += abs(v @ P.apply_mass(v))
+    return np.sqrt(tot)
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_batch_solve_reaches_tolerance(dev, mixed):
+    from paper_2204_05988_amd import sgdg
+    mem = [_member(i, L) for i, L in MEMBERS]
+    batch = sgdg.SparseGridBatch([m[2] for m in mem])
+    off = batch.offsets
+    # consistent right-hand sides b = A u* (the strip systems may be singular in coefficients)
+    bs = [P.apply(random_vector(P.ndof, 20 + k)[0]) for k, (_, P, _) in enumerate(mem)]
+    b = torch.tensor(np.concatenate(bs), device=dev)
+    x = torch.zeros_like(b)
+    tol = 1e-8 if mixed else 1e-10
+    _say(f"batched solve of {len(mem)} members ({'mixed' if mixed else 'fp64'})")
+    x, st = batch.solve(b, x, sgdg.default_solve_opts(rtol=tol, maxit=200, mixed=mixed))
+    _say(f"  outer {st.outer_iters}, inner {st.inner_iters_total}, max rel residual {st.rel_residual:.2e}, "
+         f"{st.seconds:.3f}s")
+    xs = x.cpu().numpy()
+    for k, (w, P, ops) in enumerate(mem):
+        xk = xs[off[k]:off[k + 1]]
+        res = np.linalg.norm(bs[k] - P.apply(xk)) / np.linalg.norm(bs[k])
+        _say(f"  member {k}: oracle residual {res:.2e}")
+        assert res <= 1.5 * tol
+        if not mixed:
+            # the same member solved alone reaches the same function
+            bk = torch.tensor(bs[k], device=dev)
+            xk1, _ = ops.solve_strip(bk, torch.zeros_like(bk), sgdg.default_solve_opts(rtol=tol, maxit=200))
+            dist = _fnorm(P, xk - xk1.cpu().numpy()) / max(_fnorm(P, xk1.cpu().numpy()), 1e-300)
+            _say(f"    L2 distance to the single solve {dist:.2e}")
+            assert dist <= 1e-7
+
+
+def test_batch_zero_rhs_member(dev):
+    """A member with b = 0 returns u = 0 while the others converge."""
+    from paper_2204_05988_amd import sgdg
+    mem = [_member(i, L) for i, L in MEMBERS[:2]]
+    batch = sgdg.SparseGridBatch([m[2] for m in mem])
+    off = batch.offsets
+    b0 = np.zeros(mem[0][1].ndof)
+    b1 = mem[1][1].apply(random_vector(mem[1][1].ndof, 3)[0])
+    b = torch.tensor(np.concatenate([b0, b1]), device=dev)
+    x = torch.ones_like(b)
+    _say("batched solve with a zero right-hand side member")
+    x, st = batch.solve(b, x, sgdg.default_solve_opts(rtol=1e-10, maxit=200))
+    xs = x.cpu().numpy()
+    assert np.all(xs[:off[1]] == 0.0)
+    res = np.linalg.norm(b1 - mem[1][1].apply(xs[off[1]:])) / np.linalg.norm(b1)
+    assert res <= 1.5e-10
+
+
+def test_graph_solve_matches_eager(dev):
+    """Grid-problem GMRES cycles replayed from a captured graph (twice) give the
+    same strip solution as eager launches."""
+    from paper_2204_05988_amd import sgdg
+    w = config_c2(L=5)
+    P = Problem(w)
+    ops = sgdg.SparseGridOps(w)
+    bref = P.apply(random_vector(P.ndof, 4)[0])
+    b = torch.tensor(bref, device=dev)
+    _say("graph vs eager strip solve c2_L5")
+    xe, ste = ops.solve_strip(b, torch.zeros_like(b), sgdg.default_solve_opts(rtol=1e-10, maxit=200))
+    for rep in range(2):
+        xg, stg = ops.solve_strip(b, torch.zeros_like(b),
+                                  sgdg.default_solve_opts(rtol=1e-10, maxit=200, use_graph=True))
+        torch.cuda.synchronize()
+        xgn = xg.cpu().numpy()
+        res = np.linalg.norm(bref - P.apply(xgn)) / np.linalg.norm(bref)
+        dist = _fnorm(P, xgn - xe.cpu().numpy()) / _fnorm(P, xe.cpu().numpy())
+        _say(f"  replay {rep}: outer {stg.outer_iters} (eager {ste.outer_iters}), {stg.seconds:.3f}s "
+             f"(eager {ste.seconds:.3f}s), oracle residual {res:.2e}, distance to eager {dist:.2e}")
+        assert res <= 2e-10
+        assert dist <= 1e-7
+    ops.close()

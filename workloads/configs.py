@@ -205,10 +205,12 @@ def config_c3(seed: int = 0, L: int = 6) -> Workload:
         sigma=[], xfields={}, vfields={f"v{i}": _coord(i) for i in range(3)}, seed=seed)
 
 
-def config_c4_member(i: int, seed: int = 0) -> Workload:
-    """One of the 64 batched 4D problems: beta=(v, a_i), sigma_i, Fourier forcing."""
+def config_c4_member(i: int, seed: int = 0, L: Optional[int] = None) -> Workload:
+    """One of the 64 batched 4D problems: beta=(v, a_i), sigma_i, Fourier forcing.
+    L overrides the drawn level (smaller members for parity tests)."""
     rng = np.random.default_rng([seed, i])
-    L = int(rng.integers(5, 8))
+    L_drawn = int(rng.integers(5, 8))
+    L = L_drawn if L is None else int(L)
     a = rng.uniform(-1.0, 1.0, size=2)
     sig = float(rng.uniform(0.0, 0.5))
     modes = []
