@@ -157,12 +157,21 @@ sgdg_status sgdg_combine(sgdg_ops o, const double* nodal_dev, double* coef_dev, 
 
 /* ------------------------------------------------------- preconditioners -- */
 
+/* A trained per-grid correction network standing in for the combination
+ * technique (see "learned preconditioner" below). */
+typedef struct sgdg_net_s* sgdg_net;
+
 typedef struct {
-  int kind;             /* 0 = combination technique (Algorithm 1's body) */
+  int kind;             /* 0 = combination technique (Algorithm 1's body); 1 = learned network,
+                           falling back to the combination technique */
   double inner_rtol;    /* relative residual of each grid problem (eq:Adeltall) */
   int inner_maxit;      /* iteration cap per grid problem */
   int inner_restart;    /* GMRES restart length of the grid problems */
-  int mass_sweeps;      /* Chebyshev-Jacobi steps approximating each mass inverse (0 = Jacobi) */
+  int mass_sweeps;      /* reserved, must be 0 (Jacobi mass inverse) */
+  sgdg_net net;         /* kind 1: the trained network of this problem */
+  int fallback_iters;   /* kind 1: if over any fallback_iters consecutive FGMRES iterations (default 10) ... */
+  double fallback_drop; /* ... the residual estimate drops by less than this factor (default 10), the
+                           remaining iterations use kind 0 */
 } sgdg_precond_opts;
 
 /* z_dev = P_CT r_dev (one vector, batch must be 1 in this version).
@@ -204,6 +213,8 @@ typedef struct {
   int inner_iters_total;  /* grid-problem GMRES iterations summed over all calls */
   double rel_residual;    /* final ||b - A u|| / ||b|| in FP64 */
   double seconds;         /* wall time of the call */
+  int fallback_used;      /* learned preconditioner: 1 if the solve switched to the combination technique */
+  int pc_applications;    /* preconditioner applications (learned + combination technique) */
 } sgdg_solve_stats;
 
 /* Solves A^(delta) u = b for one strip by flexible GMRES right-preconditioned
@@ -240,6 +251,70 @@ sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, double* u_dev, c
                              sgdg_solve_stats* st, hipStream_t s);
 void sgdg_batch_destroy(sgdg_batch b);
 
+/* ------------------------------------------------ learned preconditioner -- */
+
+/* The combination technique maps the residual of every upper grid l to a
+ * correction on the same grid (the lower partner (lx-1, lv) solves for the
+ * x-restriction of r_l; Algorithm 1's body).  The learned form replaces this
+ * per-grid map by a network N_l of its own per upper grid:
+ *     z_l = s_l * rms(r_l) * N_l(r_l / rms(r_l)),  rms(r) = ||r||_2 / sqrt(#entries),
+ * where N_l has 4 layers, each a 3x3 convolution over the x-plane followed by
+ * a 3x3 convolution over the v-plane (32 channels, biases, ReLU after layers
+ * 1-3; periodic padding along periodic domains, zeros otherwise), acting on
+ * the grid's coefficients with the time slices as channels.  Weights and
+ * activations are bfloat16 with FP32 accumulation (matrix cores); master
+ * weights and the Adam state are FP32.  The network is trained on pairs
+ * (r, P_CT r) that the solver records.  Only for d = 2 (4D phase space).
+ *
+ * Parameters: for each upper grid (in order), for each of the 8 convolutions
+ * (layer-major, x-plane then v-plane): W[9][32][32] (tap (a,b) -> 3(a+1)+(b+1),
+ * output channel, input channel) then the bias[32]; FP32. */
+typedef struct {
+  int steps;            /* Adam steps */
+  int batch;            /* samples per step */
+  double lr;            /* Adam learning rate (beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint64_t seed;        /* seed of the combination coefficients */
+  int mix;              /* 1: each sample is a random N(0,1/K) combination of the K stored pairs
+                           (valid because P_CT is linear); 0: the stored pairs in turn */
+} sgdg_train_opts;
+
+typedef struct {
+  double loss_first;    /* mean of the first min(10, steps) step losses */
+  double loss_last;     /* mean of the last min(10, steps) step losses */
+  double seconds;
+  int steps;
+} sgdg_train_stats;
+
+/* Creates the networks of o's upper grids, weights drawn from seed (scaled
+ * normal, zero biases, padding channels zero), output scales 1.  Device memory
+ * is owned by the handle.  SGDG_E_ARG unless d = 2. */
+sgdg_status sgdg_net_create(sgdg_ops o, uint64_t seed, sgdg_net* out);
+/* Number of FP32 parameters (grids x 8 x 9248) and of grids. */
+sgdg_status sgdg_net_shape(sgdg_net n, int64_t* n_params, int* n_grids);
+/* Host copies of the parameters (layout above) and the per-grid output scales. */
+sgdg_status sgdg_net_get_params(sgdg_net n, float* params, double* scales);
+sgdg_status sgdg_net_set_params(sgdg_net n, const float* params, const double* scales);
+/* Appends count pairs (r_i, z_i = P r_i), FP64 device vectors of n_dof each,
+ * contiguous, to the training store (converted to FP32).  SGDG_E_ARG beyond capacity. */
+sgdg_status sgdg_net_add_pairs(sgdg_net n, const double* r_dev, const double* z_dev, int count, hipStream_t s);
+/* capacity > 0: every combination-technique application inside solves of the
+ * network's problem appends its (r, z) pair until the store holds capacity
+ * pairs; 0 stops recording.  Resets nothing already stored. */
+sgdg_status sgdg_net_record(sgdg_net n, int capacity);
+sgdg_status sgdg_net_pair_count(sgdg_net n, int* count);
+/* Sets the output scales s_l from the stored pairs (mean of rms(z_l)/rms(r_l))
+ * and runs Adam on the mean squared error of the normalised outputs. */
+sgdg_status sgdg_net_train(sgdg_net n, const sgdg_train_opts* to, sgdg_train_stats* st, hipStream_t s);
+/* z_dev = P_learned r_dev (FP64 n_dof vectors). */
+sgdg_status sgdg_net_apply(sgdg_net n, const double* r_dev, double* z_dev, hipStream_t s);
+/* Raw network on the concatenated grid tensors: x_dev, y_dev FP32 [points][R]
+ * channels-last (points of grid l in the order x * n_v + v, grids in order;
+ * points = n_dof / R).  No normalisation, no scale. */
+sgdg_status sgdg_net_forward(sgdg_net n, const float* x_dev, float* y_dev, hipStream_t s);
+/* Gradient of sum(y * dy) for y = forward(x): grad_dev FP32 [n_params] (layout above). */
+sgdg_status sgdg_net_backward(sgdg_net n, const float* x_dev, const float* dy_dev, float* grad_dev, hipStream_t s);
+void sgdg_net_destroy(sgdg_net n);
+
 /* ------------------------------------------------------------ diagnostics -- */
 
 /* Event timing of the operator kernels (for roofline reports).  mode 1 resets
@@ -247,9 +322,9 @@ void sgdg_batch_destroy(sgdg_batch b);
  * subsequent launch group of the operator kernels; mode 0 stops recording. */
 sgdg_status sgdg_profile(sgdg_ops o, int mode);
 /* Accumulated time (ms) and launch-group count of one kernel class since the
- * last reset: slot 0 = Kronecker sweeps (k_sweeps), 1 = level scans (all
- * steps of one application, k_scan), 2 = term accumulation (k_final).
- * Waits for the recorded events. */
+ * last reset: slot 0 = level scans of the partner sums (all steps of one
+ * application, k_scan2), 1 = box-tiled accumulation (k_fused), 2 = grid-problem
+ * GMRES cycles of the preconditioner.  Waits for the recorded events. */
 sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launches);
 /* Shape of one operator: Kronecker terms, distinct v- and x-factors, stencil
  * sizes of the two domains and the time slices in/out. */

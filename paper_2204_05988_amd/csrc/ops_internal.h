@@ -119,7 +119,15 @@ struct sgdg_ops_s {
   double pinv[kMaxR * kMaxR] = {};  // (Tt + delta Ct + Gt)^-1
   int device = 0;
   std::unique_ptr<Batch, BatchDeleter> self;  // this problem as a batch of one
+  sgdg_net recorder = nullptr;                 // network recording (r, P_CT r) pairs of this problem
+  std::vector<sgdg_net> nets;                  // networks created for this problem
 };
+
+// The learned preconditioner (net.hip) as seen by the strip solver.
+void net_apply_dev(sgdg_net n, const double* r, double* z, hipStream_t s);
+sgdg_ops net_problem(sgdg_net n);
+void net_record_pair(sgdg_net n, const double* r, const double* z, hipStream_t s);
+void net_detach(sgdg_net n);  // the problem is being destroyed
 
 // the problem as a batch of one (created on first use)
 Batch& self_batch(sgdg_ops o);

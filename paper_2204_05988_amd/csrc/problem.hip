@@ -334,5 +334,9 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   API_END
 }
 
-extern "C" void sgdg_ops_destroy(sgdg_ops o) { delete o; }
+extern "C" void sgdg_ops_destroy(sgdg_ops o) {
+  if (!o) return;
+  for (sgdg_net n : o->nets) net_detach(n);  // networks outliving their problem become unusable, not dangling
+  delete o;
+}
 

@@ -648,7 +648,7 @@ static void ct_apply(Batch& B, const T* r, T* z, const sgdg_precond_opts& po, bo
 }
 
 static sgdg_precond_opts default_pc() {
-  sgdg_precond_opts p;
+  sgdg_precond_opts p{};
   p.kind = 0;
   p.inner_rtol = 1e-8;
   p.inner_maxit = 200;
@@ -682,9 +682,11 @@ static std::vector<double> seg_norms(Batch& B, const SegTab& ST, const double* v
 
 // Flexible GMRES on every problem of the batch in lockstep (one segment per
 // problem, FP64 Arnoldi), stopping per problem at ||b - A u|| <= tol ||b||.
+// monitor(iterations, largest relative residual estimate, largest relative residual at entry)
+using Monitor = std::function<void(int, double, double)>;
 static FgmresResult fgmres(Batch& B, const std::function<void(const double*, double*)>& A,
                            const std::function<void(const double*, double*)>& P, const double* b, double* x,
-                           double tol, int m, int maxit, hipStream_t s) {
+                           double tol, int m, int maxit, hipStream_t s, const Monitor* monitor = nullptr) {
   SegTab& ST = prob_tab(B, B.R);
   const SegTable& S = ST.t;
   const int nseg = S.nseg;
@@ -714,6 +716,7 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
     if (bn[i] == 0.0) KernelsT<double>::fill(ST.host[i].len, 0.0, x + ST.host[i].off, s);
   std::vector<int> act(nseg);
   std::vector<double> beta(nseg);
+  double rel0 = -1;
   for (;;) {
     A(x, w);
     KernelsT<double>::copy(n, b, V, s);
@@ -731,6 +734,7 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
       res.nan = true;
       return res;
     }
+    if (rel0 < 0) rel0 = res.rel;
     if (res.rel <= tol || res.iters >= maxit) return res;
     KernelsT<double>::seg_norm2(S, V, part, s);
     gmres_start(nseg, st, S.segs, part, tol, 0, s);  // converged problems start inactive
@@ -758,6 +762,7 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
         if (bn[i] > 0) est = std::max(est, beta[i] / bn[i]);
       }
       if (verbose) fprintf(stderr, "[sgdg fgmres] it %d  est %.3e\n", res.iters + j + 1, est);
+      if (monitor) (*monitor)(res.iters + j + 1, est, rel0);
       if (bad) {
         res.nan = true;
         return res;
@@ -778,14 +783,48 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = kind(B, K_FULL).total;
   sgdg_precond_opts pc = so.pc;
-  if (pc.inner_restart <= 0) pc = default_pc();
+  if (pc.inner_restart <= 0) {  // unset inner options: defaults, keeping the kind and network
+    const sgdg_precond_opts d = default_pc();
+    pc.inner_rtol = d.inner_rtol;
+    pc.inner_maxit = d.inner_maxit;
+    pc.inner_restart = d.inner_restart;
+  }
   const bool graph = so.use_graph != 0;
   B.inner_iters = 0;
+  // preconditioner: combination technique, or the learned network until it
+  // fails to reduce the residual estimate by fallback_drop within fallback_iters
+  // iterations (FGMRES admits a change of preconditioner between iterations)
+  const bool learned = pc.kind == 1;
+  bool use_ct = !learned, fell_back = false;
+  int pc_apps = 0;
+  const int fb_iters = pc.fallback_iters > 0 ? pc.fallback_iters : 10;
+  const double fb_drop = pc.fallback_drop > 1 ? pc.fallback_drop : 10.0;
+  sgdg_net rec = B.owned_by_ops ? B.P[0]->recorder : nullptr;
+  std::vector<double> est_hist;  // residual estimate after each learned iteration (index 0: at entry)
+  const Monitor monitor = [&](int it, double est, double rel0) {
+    if (use_ct) return;
+    if (est_hist.empty()) est_hist.push_back(rel0);
+    est_hist.push_back(est);
+    (void)it;
+    const size_t k = est_hist.size() - 1;  // learned iterations so far
+    if (k >= size_t(fb_iters) && est > est_hist[k - fb_iters] / fb_drop) {
+      use_ct = true;  // no drop by fb_drop over the last fb_iters iterations
+      fell_back = true;
+    }
+  };
   auto A64 = [&](const double* in, double* out) { apply<double>(B, K_FULL, in, out, 1, s); };
-  auto P64 = [&](const double* in, double* out) { ct_apply<double>(B, in, out, pc, graph, s, nan); };
+  auto P64 = [&](const double* in, double* out) {
+    ++pc_apps;
+    if (!use_ct) {
+      net_apply_dev(pc.net, in, out, s);
+      return;
+    }
+    ct_apply<double>(B, in, out, pc, graph, s, nan);
+    if (rec) net_record_pair(rec, in, out, s);
+  };
   sgdg_solve_stats st{};
   if (!so.mixed_precision) {
-    FgmresResult r = fgmres(B, A64, P64, b, u, so.rtol, so.restart, so.maxit, s);
+    FgmresResult r = fgmres(B, A64, P64, b, u, so.rtol, so.restart, so.maxit, s, learned ? &monitor : nullptr);
     st.outer_iters = r.iters;
     st.rel_residual = r.rel;
     *nan = *nan || r.nan;
@@ -807,9 +846,15 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
       convert_f32_to_f64(n, b32, out, s);
     };
     auto P32 = [&](const double* in, double* out) {
+      ++pc_apps;
+      if (!use_ct) {
+        net_apply_dev(pc.net, in, out, s);
+        return;
+      }
       convert_f64_to_f32(n, in, a32, s);
       ct_apply<float>(B, a32, b32, pc32, graph, s, nan);
       convert_f32_to_f64(n, b32, out, s);
+      if (rec) net_record_pair(rec, in, out, s);
     };
     double* rr = ptr<double>(B.fr);
     double* e = ptr<double>(B.fe);
@@ -832,7 +877,8 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
       }
       if (rel <= so.rtol || total >= so.maxit || steps >= 20) break;
       KernelsT<double>::fill(n, 0.0, e, s);
-      FgmresResult ri = fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s);
+      FgmresResult ri =
+          fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s, learned ? &monitor : nullptr);
       total += std::max(ri.iters, 1);
       ++steps;
       if (ri.nan) {
@@ -846,6 +892,8 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
     st.rel_residual = rel;
   }
   SGDG_CHECK_HIP(hipStreamSynchronize(s));
+  st.fallback_used = fell_back ? 1 : 0;
+  st.pc_applications = pc_apps;
   st.inner_iters_total = int(B.inner_iters);
   st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
@@ -956,7 +1004,7 @@ extern "C" sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_
   require(o && r_dev && z_dev && r_dev != z_dev, "null or aliased argument");
   require(batch == 1, "precondition supports batch == 1");
   const sgdg_precond_opts po = po_in ? *po_in : default_pc();
-  require(po.kind == 0, "only the combination-technique preconditioner (kind 0) is available");
+  require(po.kind == 0, "sgdg_precondition applies the combination technique (kind 0); see sgdg_net_apply");
   require(po.inner_rtol > 0 && po.inner_maxit >= 1 && po.inner_restart >= 1, "invalid inner solver options");
   Batch& B = self_batch(o);
   bool nan = false;
@@ -1020,16 +1068,21 @@ extern "C" sgdg_status sgdg_rhs(sgdg_ops o, const double* u_prev_dev, int prev_s
   API_END
 }
 
-static void check_solve_opts(const sgdg_solve_opts* so) {
+static void check_solve_opts(const sgdg_solve_opts* so, const Batch& B) {
   require(so != nullptr, "null solver options");
   require(so->rtol > 0 && so->restart >= 1 && so->restart <= 64 && so->maxit >= 1, "invalid solver options");
+  require(so->pc.kind == 0 || so->pc.kind == 1, "unknown preconditioner kind");
+  require(so->pc.mass_sweeps == 0, "mass_sweeps must be 0");
+  if (so->pc.kind == 1)
+    require(so->pc.net != nullptr && B.P.size() == 1 && net_problem(so->pc.net) == B.P[0],
+            "the learned preconditioner needs the network of this problem");
 }
 
 extern "C" sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
                                         sgdg_solve_stats* st, hipStream_t s) {
   API_BEGIN
   require(o && b_dev && u_dev, "null argument");
-  check_solve_opts(so);
+  check_solve_opts(so, self_batch(o));
   bool nan = false;
   const sgdg_solve_stats stats = solve_batch(self_batch(o), b_dev, u_dev, *so, s, &nan);
   if (st) *st = stats;
@@ -1081,7 +1134,7 @@ extern "C" sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, doubl
                                         sgdg_solve_stats* st, hipStream_t s) {
   API_BEGIN
   require(b && b_dev && u_dev, "null argument");
-  check_solve_opts(so);
+  check_solve_opts(so, *b);
   bool nan = false;
   const sgdg_solve_stats stats = solve_batch(*b, b_dev, u_dev, *so, s, &nan);
   if (st) *st = stats;

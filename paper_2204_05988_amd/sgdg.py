@@ -24,6 +24,9 @@ EXPORTS = [
     "sgdg_precondition", "sgdg_rhs", "sgdg_solve_strip", "sgdg_debug_dense_block",
     "sgdg_profile", "sgdg_profile_read", "sgdg_op_info",
     "sgdg_batch_create", "sgdg_batch_layout", "sgdg_batch_apply", "sgdg_batch_solve", "sgdg_batch_destroy",
+    "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
+    "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
+    "sgdg_net_backward", "sgdg_net_destroy",
 ]
 
 
@@ -49,7 +52,8 @@ class Problem(C.Structure):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("inner_rtol", C.c_double), ("inner_maxit", C.c_int),
-                ("inner_restart", C.c_int), ("mass_sweeps", C.c_int)]
+                ("inner_restart", C.c_int), ("mass_sweeps", C.c_int), ("net", C.c_void_p),
+                ("fallback_iters", C.c_int), ("fallback_drop", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -59,7 +63,16 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("refinement_steps", C.c_int), ("inner_iters_total", C.c_int),
-                ("rel_residual", C.c_double), ("seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("fallback_used", C.c_int),
+                ("pc_applications", C.c_int)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("seed", C.c_uint64), ("mix", C.c_int)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("seconds", C.c_double), ("steps", C.c_int)]
 
 
 _LIB = None
@@ -98,8 +111,23 @@ def lib():
     L.sgdg_batch_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
     L.sgdg_batch_destroy.argtypes = [vp]
     L.sgdg_batch_destroy.restype = None
+    fp = C.POINTER(C.c_float)
+    L.sgdg_net_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.sgdg_net_shape.argtypes = [vp, i64p, ip]
+    L.sgdg_net_get_params.argtypes = [vp, fp, dp]
+    L.sgdg_net_set_params.argtypes = [vp, fp, dp]
+    L.sgdg_net_add_pairs.argtypes = [vp, vp, vp, C.c_int, vp]
+    L.sgdg_net_record.argtypes = [vp, C.c_int]
+    L.sgdg_net_pair_count.argtypes = [vp, ip]
+    L.sgdg_net_train.argtypes = [vp, C.POINTER(TrainOpts), C.POINTER(TrainStats), vp]
+    L.sgdg_net_apply.argtypes = [vp, vp, vp, vp]
+    L.sgdg_net_forward.argtypes = [vp, vp, vp, vp]
+    L.sgdg_net_backward.argtypes = [vp, vp, vp, vp, vp]
+    L.sgdg_net_destroy.argtypes = [vp]
+    L.sgdg_net_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy"):
+        if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy",
+                        "sgdg_net_destroy"):
             getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -166,8 +194,11 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def default_precond_opts(inner_rtol=1e-8, inner_maxit=200, inner_restart=30, mass_sweeps=0) -> PrecondOpts:
-    return PrecondOpts(0, inner_rtol, inner_maxit, inner_restart, mass_sweeps)
+def default_precond_opts(inner_rtol=1e-8, inner_maxit=200, inner_restart=30, mass_sweeps=0, net=None,
+                         fallback_iters=10, fallback_drop=10.0) -> PrecondOpts:
+    """kind 0 (combination technique), or kind 1 (learned) when a LearnedPreconditioner is given."""
+    return PrecondOpts(1 if net is not None else 0, inner_rtol, inner_maxit, inner_restart, mass_sweeps,
+                       net.h if net is not None else None, fallback_iters, fallback_drop)
 
 
 def default_solve_opts(rtol=1e-8, restart=50, maxit=400, mixed=False, inner_outer_rtol=1e-4, pc=None,
@@ -317,6 +348,77 @@ class SparseGridBatch:
     def close(self):
         if getattr(self, "h", None):
             lib().sgdg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LearnedPreconditioner:
+    """The per-grid correction networks of one problem (d = 2)."""
+
+    def __init__(self, ops: SparseGridOps, seed=0):
+        L = lib()
+        self.ops = ops  # keeps the problem alive
+        h = C.c_void_p()
+        _check(L.sgdg_net_create(ops.ops, seed, C.byref(h)))
+        self.h = h
+        n, g = C.c_int64(), C.c_int()
+        _check(L.sgdg_net_shape(h, C.byref(n), C.byref(g)))
+        self.n_params, self.n_grids = n.value, g.value
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        sc = np.zeros(self.n_grids)
+        _check(lib().sgdg_net_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                         sc.ctypes.data_as(C.POINTER(C.c_double))))
+        return p, sc
+
+    def set_params(self, params=None, scales=None):
+        pp = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        ss = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
+        _check(lib().sgdg_net_set_params(self.h, None if pp is None else pp.ctypes.data_as(C.POINTER(C.c_float)),
+                                         None if ss is None else ss.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def add_pairs(self, r, z, stream=None):
+        assert r.numel() == z.numel() and r.numel() % self.ops.ndof == 0
+        _check(lib().sgdg_net_add_pairs(self.h, _ptr(r), _ptr(z), r.numel() // self.ops.ndof, _stream(stream)))
+
+    def record(self, capacity):
+        _check(lib().sgdg_net_record(self.h, capacity))
+
+    def pair_count(self):
+        c = C.c_int()
+        _check(lib().sgdg_net_pair_count(self.h, C.byref(c)))
+        return c.value
+
+    def train(self, steps, batch=8, lr=1e-3, seed=0, mix=True, stream=None):
+        o = TrainOpts(steps, batch, lr, seed, int(mix))
+        st = TrainStats()
+        _check(lib().sgdg_net_train(self.h, C.byref(o), C.byref(st), _stream(stream)))
+        return st
+
+    def apply(self, r, z, stream=None):
+        assert r.numel() == self.ops.ndof and z.numel() == self.ops.ndof
+        _check(lib().sgdg_net_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def forward(self, x, y, stream=None):
+        assert x.numel() == self.ops.ndof and y.numel() == self.ops.ndof
+        _check(lib().sgdg_net_forward(self.h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def backward(self, x, dy, grad, stream=None):
+        assert grad.numel() == self.n_params
+        _check(lib().sgdg_net_backward(self.h, _ptr(x), _ptr(dy), _ptr(grad), _stream(stream)))
+        return grad
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sgdg_net_destroy(self.h)
             self.h = None
 
     def __del__(self):
