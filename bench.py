@@ -6,9 +6,17 @@ level scans with the embedding matrices, term accumulation) to a batch of
 synthetic input vectors already resident in HBM.  Workload: the 4D phase-space
 problem (d=2, r=1, sparse-grid level 7, 620 892 space-time DOFs per vector).
 
-Prints one JSON line (rank 0).  Also reports, beside the headline number, the
-strip-solve time to 1e-8 in FP64 and in mixed precision, and the CPU oracle
-timed on a bounded sample.
+Prints one JSON line (rank 0).  Also reports, beside the headline number:
+  * strip_solve: the first strip of that problem solved to 1e-8 in FP64 and in
+    mixed precision (FP32 inner, FP64 refinement);
+  * learned: the 4D Vlasov-type step (x periodic, frozen random E(x), L=7,
+    r=0): (r, P_CT r) pairs recorded from CT-preconditioned solves of strips
+    1-8, the per-grid networks trained on them, then strips 9-10 solved to 1e-8
+    with CT, with the learned preconditioner, and learned + mixed precision;
+  * batched: independent 4D problems with levels drawn from {5,6,7}, applied
+    and solved in lockstep (FP32 applies inside FP64 refinement) against the
+    same problems solved one at a time in plain FP64;
+  * cpu_baseline: the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -35,6 +43,9 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
+    ap.add_argument("--train-steps", type=int, default=300)
     return ap.parse_args()
 
 
@@ -133,11 +144,21 @@ def main():
         "roofline": roof,
         "wall_s": round(wall, 3),
     }
+    _log(f"apply: {value:.3e} DOF-applies/s")
     if not a.no_solve:
         out["strip_solve"] = solve_times(ops, w, dev)
+        _log(f"strip solves: {out['strip_solve']}")
+    if not a.no_learned:
+        out["learned"] = learned_leg(dev, a.train_steps)
+    if a.batched > 0:
+        out["batched"] = batched_leg(dev, a.batched)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, value)
     print(json.dumps(out), flush=True)
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def solve_times(ops, w, dev):
@@ -170,6 +191,133 @@ def solve_times(ops, w, dev):
                      "inner_iters": st.inner_iters_total, "rel_residual": st.rel_residual,
                      "refinements": st.refinement_steps}
     return res
+
+
+def _interp_u0(ops, w, dev):
+    """Spanning coefficients of the sparse-grid interpolant of u0 (combination on the device)."""
+    import torch
+    from workloads import sample_on_grids
+    nodal0 = np.concatenate([sample_on_grids(w, _grids(ops.upper), w.u0), sample_on_grids(w, _grids(ops.lower), w.u0)])
+    u0 = torch.empty(ops.npts_up, dtype=torch.float64, device=dev)
+    ops.combine(torch.tensor(nodal0, device=dev), u0, 1)
+    return u0
+
+
+def _timed_solve(ops, b, opts):
+    import torch
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = ops.solve_strip(b, x, opts, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    return x, {"seconds": round(time.perf_counter() - t0, 4), "outer_iters": st.outer_iters,
+               "inner_iters": st.inner_iters_total, "rel_residual": st.rel_residual,
+               "pc_applications": st.pc_applications, "fallback": st.fallback_used}
+
+
+def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c5
+    w = config_c5(L=L)
+    t0 = time.perf_counter()
+    ops = sgdg.SparseGridOps(w)
+    setup = time.perf_counter() - t0
+    net = sgdg.LearnedPreconditioner(ops, seed=0)
+    u = _interp_u0(ops, w, dev)
+    prev = 1
+    ct = sgdg.default_solve_opts(rtol=1e-8, maxit=400)
+    net.record(4096)
+    rec_time = 0.0
+    for j in range(1, record_strips + 1):
+        b = ops.rhs(u, prev)
+        u, st = _timed_solve(ops, b, ct)
+        rec_time += st["seconds"]
+        prev = 1
+        _log(f"learned leg: CT strip {j} {st}")
+    net.record(0)
+    ts = net.train(train_steps, batch=8, lr=1e-3, seed=1)
+    _log(f"learned leg: trained {ts.steps} steps in {ts.seconds:.2f}s, loss {ts.loss_first:.3e} -> {ts.loss_last:.3e}")
+    out = {"workload": f"4D Vlasov-type step, x periodic, E(x) 16 modes, L={L}, r=0 (c5)", "dofs": ops.ndof,
+           "setup_s": round(setup, 3), "pairs": net.pair_count(), "record_strips": record_strips,
+           "record_solve_s": round(rec_time, 3),
+           "train": {"steps": ts.steps, "batch": 8, "seconds": round(ts.seconds, 3),
+                     "loss_first": ts.loss_first, "loss_last": ts.loss_last}, "strips": []}
+    learned = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(net=net))
+    learned_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True, pc=sgdg.default_precond_opts(net=net))
+    for j in range(record_strips + 1, record_strips + test_strips + 1):
+        b = ops.rhs(u, prev)
+        row = {"strip": j}
+        x, row["ct_fp64"] = _timed_solve(ops, b, ct)
+        _, row["learned_fp64"] = _timed_solve(ops, b, learned)
+        _, row["learned_mixed"] = _timed_solve(ops, b, learned_mixed)
+        row["gain_learned_fp64"] = round(row["ct_fp64"]["seconds"] / row["learned_fp64"]["seconds"], 3)
+        row["gain_learned_mixed"] = round(row["ct_fp64"]["seconds"] / row["learned_mixed"]["seconds"], 3)
+        out["strips"].append(row)
+        _log(f"learned leg: {row}")
+        u = x
+    net.close()
+    ops.close()
+    return out
+
+
+def batched_leg(dev, n):
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c4, gauss_legendre_times, sample_on_grids
+    members = config_c4(seed=0, n=n)
+    t0 = time.perf_counter()
+    ops_list = [sgdg.SparseGridOps(w) for w in members]
+    setup = time.perf_counter() - t0
+    _log(f"batched leg: {n} problems assembled in {setup:.1f}s")
+    batch = sgdg.SparseGridBatch(ops_list)
+    # strip 1 right-hand sides: u0 = 0, forcing f at the Gauss points of the strip
+    bs = []
+    for w, ops in zip(members, ops_list):
+        tq, _ = gauss_legendre_times(0.0, w.dt, w.r + 2)
+        f = torch.tensor(np.stack([np.concatenate([sample_on_grids(w, _grids(ops.upper), w.f, t),
+                                                   sample_on_grids(w, _grids(ops.lower), w.f, t)]) for t in tq]),
+                         device=dev)
+        zero = torch.zeros(ops.npts_up, dtype=torch.float64, device=dev)
+        bs.append(ops.rhs(zero, 1, f, None))
+    b = torch.cat(bs)
+    out = {"workload": f"{n} independent 4D problems, levels {{5,6,7}}, beta=(v,a_i), sigma_i, Fourier forcing (c4)",
+           "problems": n, "levels": [w.L for w in members], "dofs_total": batch.ndof, "setup_s": round(setup, 3)}
+    # batched apply throughput
+    for name, dt in (("apply_f64", torch.float64), ("apply_f32", torch.float32)):
+        u = torch.randn(batch.ndof, dtype=dt, device=dev)
+        y = torch.empty_like(u)
+        for _ in range(3):
+            batch.apply(u, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            batch.apply(u, y)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": round(el * 1e3, 3), "dof_applies_per_s": batch.ndof / el}
+    # lockstep mixed-precision solve vs one-at-a-time FP64
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = batch.solve(b, x, sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True), raise_on_noconv=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    out["batched_mixed_solve"] = {"seconds": round(tb, 3), "outer_iters": st.outer_iters,
+                                  "refinements": st.refinement_steps, "max_rel_residual": st.rel_residual}
+    _log(f"batched leg: {out['batched_mixed_solve']}")
+    seq, worst = 0.0, 0.0
+    for ops, bb in zip(ops_list, bs):
+        _, r = _timed_solve(ops, bb, sgdg.default_solve_opts(rtol=1e-8, maxit=400))
+        seq += r["seconds"]
+        worst = max(worst, r["rel_residual"])
+    out["sequential_fp64_solve"] = {"seconds": round(seq, 3), "max_rel_residual": worst}
+    out["speedup_batched_mixed_vs_sequential_fp64"] = round(seq / tb, 3)
+    batch.close()
+    for o in ops_list:
+        o.close()
+    return out
 
 
 def _grids(shapes):
