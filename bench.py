@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed loop, copy a 512 MiB buffer once (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -145,6 +147,13 @@ def main():
         "wall_s": round(wall, 3),
     }
     _log(f"apply: {value:.3e} DOF-applies/s")
+    if a.calib_copy:
+        src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("calibration copy: 512 MiB read + 512 MiB written")
     if not a.no_solve:
         out["strip_solve"] = solve_times(ops, w, dev)
         _log(f"strip solves: {out['strip_solve']}")

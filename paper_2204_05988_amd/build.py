@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libsgdg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "assembly.cpp", "terms.cpp", "debug.cpp", "kernels.hip", "fused.hip", "problem.hip", "solver.hip", "net.hip"]
+SOURCES = ["mesh.cpp", "assembly.cpp", "terms.cpp", "debug.cpp", "kernels.hip", "fused.hip", "problem.hip", "solver.hip", "net.hip", "split.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SGDG_ARCH", "gfx950")
@@ -39,7 +39,7 @@ def _compile(src):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 9)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 10)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-fopenmp", *objs, "-o", tmp,

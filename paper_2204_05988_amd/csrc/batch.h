@@ -26,6 +26,7 @@ struct ProbDesc {
   int64_t u_off;       // start of this problem's vector in the concatenated layout
   int64_t y_off;       // start of its output vector
   int64_t pt_off, qt_off;  // start of its scan arrays
+  int64_t z_off;           // start of its staged v-stencil values (split application)
 };
 
 // A box of x-nodes times a box of v-nodes of one grid of one problem.
@@ -39,6 +40,7 @@ struct FusedItem {
 struct ScanItem {
   int prob, side;      // side 0: lower partners (Pt), 1: upper partners (Qt)
   int lg;              // target lower grid
+  int grp;             // unused (0)
   int64_t start;       // first element of the block in the target
 };
 
@@ -55,6 +57,26 @@ struct FusedCall {
   T* y;
   T* Pt;
   T* Qt;
+};
+
+// Split application: one block of points of one grid of one problem.
+struct SplitItem {
+  int prob, grid;
+  int64_t p0;  // first point (x * nv + v) of the block
+};
+
+template <class T>
+struct SplitCall {
+  const ProbDesc* descs;
+  const SplitItem* items;
+  int nitems;
+  int B;                   // vectors per problem
+  int64_t u_bstride, y_bstride, pt_bstride, qt_bstride, z_bstride;
+  const T* u;
+  T* y;
+  const T* Pt;
+  const T* Qt;
+  T* Z;                    // [b][problem: V-group][grid layout] staged (I (x) V_j) u + (E^x (x) I) Pt_j
 };
 
 // A contiguous segment of a concatenated vector: one component grid of one

@@ -325,14 +325,16 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
 // nlow-1-t.  The restricted stencils E^T V (resp. E^T X) of width W couple a
 // coarse node with the fine nodes 2P + o; the u values at those nodes are
 // loaded once and reused by every group.
+// slot-major restricted stencils: entry o of the coarse nodes of one level is contiguous
 template <class T> __device__ __forceinline__ const T* rv(const DevDomain& D);
-template <> __device__ __forceinline__ const double* rv<double>(const DevDomain& D) { return D.rvals; }
-template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.rvals32; }
+template <> __device__ __forceinline__ const double* rv<double>(const DevDomain& D) { return D.trvals; }
+template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.trvals32; }
 
-template <class T, int D>
+template <class T, int D, int R>
 __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   constexpr int W = D == 1 ? 5 : (D == 2 ? 19 : 65);
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  constexpr int RS = R * W <= 48 ? R : 1;  // slices gathered per pass (registers)
   const ScanItem si = C.sitems[blockIdx.x];
   const ProbDesc& A = C.descs[si.prob];
   const DevGrids& G = A.G;
@@ -343,25 +345,22 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   const int lg = si.lg;
   const int nxl = L.nx[lg], nvl = L.nv[lg];
   const int64_t lplane = int64_t(nxl) * nvl;
-  const int64_t loc = si.start + threadIdx.x;
-  if (loc >= int64_t(op.Rin) * lplane) return;
-  const int s = int(loc / lplane);
-  const int64_t rem = loc - int64_t(s) * lplane;
-  const int x = int(rem / nvl), v = int(rem - int64_t(x) * nvl);
+  const int64_t pt = si.start + threadIdx.x;  // target point x * nvl + v
+  if (pt >= lplane) return;
+  const int x = int(pt / nvl), v = int(pt - int64_t(pt / nvl) * nvl);
   const int64_t ltotal = L.off[L.n];
   const T* ub = C.u + int64_t(b) * C.u_bstride + A.u_off;
   T* Ptb = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off;
   T* Qtb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off;
-  T un[W];
   if (lower) {
     // source grid t (lx, lv); target (lx, lv-1); previous Pt_t on lower grid t-1 (lx-1, lv)
     const int src = lg;
     const int nv = G.nv[src];
-    const int lvc = G.lv[src] - 1 - A.DV.lmin;  // level of v (coarse)
-    const T* us = ub + G.off[src] + int64_t(s) * G.nx[src] * nv + int64_t(x) * nv;
-    const int32_t* wi = A.DV.wide + A.DV.wlev_off[lvc] + int64_t(v) * W;
+    const int lvc = G.lv[src] - 1 - A.DV.lmin;  // level of v (coarse) = the target's
+    const int64_t splane = int64_t(G.nx[src]) * nv;
+    int32_t wi[W];
 #pragma unroll
-    for (int o = 0; o < W; ++o) un[o] = us[wi[o]];
+    for (int o = 0; o < W; ++o) wi[o] = A.DV.twide[A.DV.wlev_off[lvc] + int64_t(o) * nvl + v];
     const bool has_p = src > 0;
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
@@ -373,37 +372,53 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       p1 = A.DX.par[po + 1];
       w0 = T(A.DX.parw[po]);
       w1 = T(A.DX.parw[po + 1]);
-      const int64_t co = A.DV.lev_off[lvc] + int64_t(v) * SS;
+      const int64_t co = A.DV.lev_off[lvc] + v;
 #pragma unroll
       for (int c = 0; c < SS; ++c) {
-        ch[c] = A.DV.chi[co + c];
-        cw[c] = T(A.DV.chiw[co + c]);
+        ch[c] = A.DV.tchi[co + int64_t(c) * nvl];
+        cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvl]);
       }
     }
     const int64_t pl = has_p ? int64_t(L.nx[src - 1]) * nv : 0;
-    for (int j = 0; j < op.nvg; ++j) {
-      const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + int64_t(v) * W;
-      T acc = T(0);
+    for (int s0 = 0; s0 < R; s0 += RS) {
+      T un[RS][W];
 #pragma unroll
-      for (int o = 0; o < W; ++o) acc += r[o] * un[o];
-      if (has_p) {
-        const T* pp = Ptb + int64_t(j) * ltotal + L.off[src - 1] + int64_t(s) * pl;
-        const T* r0 = pp + int64_t(p0) * nv;
-        const T* r1 = pp + int64_t(p1) * nv;
+      for (int q = 0; q < RS; ++q) {
+        const T* us = ub + G.off[src] + int64_t(s0 + q) * splane + int64_t(x) * nv;
 #pragma unroll
-        for (int c = 0; c < SS; ++c) acc += cw[c] * (w0 * r0[ch[c]] + w1 * r1[ch[c]]);
+        for (int o = 0; o < W; ++o) un[q][o] = us[wi[o]];
       }
-      Ptb[int64_t(j) * ltotal + L.off[lg] + loc] = acc;
+      for (int j = 0; j < op.nvg; ++j) {
+        const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + v;
+        T rr[W];
+#pragma unroll
+        for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nvl];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+          const int s = s0 + q;
+          T acc = T(0);
+#pragma unroll
+          for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
+          if (has_p) {
+            const T* pp = Ptb + int64_t(j) * ltotal + L.off[src - 1] + int64_t(s) * pl;
+            const T* r0 = pp + int64_t(p0) * nv;
+            const T* r1 = pp + int64_t(p1) * nv;
+#pragma unroll
+            for (int c = 0; c < SS; ++c) acc += cw[c] * (w0 * r0[ch[c]] + w1 * r1[ch[c]]);
+          }
+          Ptb[int64_t(j) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
+        }
+      }
     }
   } else {
     // source grid lg+1 (lx+1, lv-1); target lower lg (lx, lv-1); previous Qt on lower grid lg+1 (lx+1, lv-2)
     const int src = lg + 1;
     const int nv = G.nv[src];
-    const int lxc = G.lx[src] - 1 - A.DX.lmin;  // level of x (coarse)
-    const T* us = ub + G.off[src] + int64_t(s) * G.nx[src] * nv + v;
-    const int32_t* wi = A.DX.wide + A.DX.wlev_off[lxc] + int64_t(x) * W;
+    const int lxc = G.lx[src] - 1 - A.DX.lmin;  // level of x (coarse) = the target's
+    const int64_t splane = int64_t(G.nx[src]) * nv;
+    int32_t wi[W];
 #pragma unroll
-    for (int o = 0; o < W; ++o) un[o] = us[int64_t(wi[o]) * nv];
+    for (int o = 0; o < W; ++o) wi[o] = A.DX.twide[A.DX.wlev_off[lxc] + int64_t(o) * nxl + x];
     const bool has_q = src + 1 < G.n;
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
@@ -416,41 +431,60 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       p1 = A.DV.par[po + 1];
       w0 = T(A.DV.parw[po]);
       w1 = T(A.DV.parw[po + 1]);
-      const int64_t co = A.DX.lev_off[lxc] + int64_t(x) * SS;
+      const int64_t co = A.DX.lev_off[lxc] + x;
 #pragma unroll
       for (int c = 0; c < SS; ++c) {
-        ch[c] = A.DX.chi[co + c];
-        cw[c] = T(A.DX.chiw[co + c]);
+        ch[c] = A.DX.tchi[co + int64_t(c) * nxl];
+        cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxl]);
       }
       nvq = L.nv[src];
     }
     const int64_t ql = has_q ? int64_t(L.nx[src]) * nvq : 0;
-    for (int m = 0; m < op.nxg; ++m) {
-      const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + int64_t(x) * W;
-      T acc = T(0);
+    for (int s0 = 0; s0 < R; s0 += RS) {
+      T un[RS][W];
 #pragma unroll
-      for (int o = 0; o < W; ++o) acc += r[o] * un[o];
-      if (has_q) {
-        const T* qq = Qtb + int64_t(m) * ltotal + L.off[src] + int64_t(s) * ql;
+      for (int q = 0; q < RS; ++q) {
+        const T* us = ub + G.off[src] + int64_t(s0 + q) * splane + v;
 #pragma unroll
-        for (int c = 0; c < SS; ++c) {
-          const T* row = qq + int64_t(ch[c]) * nvq;
-          acc += cw[c] * (w0 * row[p0] + w1 * row[p1]);
+        for (int o = 0; o < W; ++o) un[q][o] = us[int64_t(wi[o]) * nv];
+      }
+      for (int m = 0; m < op.nxg; ++m) {
+        const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + x;
+        T rr[W];
+#pragma unroll
+        for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nxl];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+          const int s = s0 + q;
+          T acc = T(0);
+#pragma unroll
+          for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
+          if (has_q) {
+            const T* qq = Qtb + int64_t(m) * ltotal + L.off[src] + int64_t(s) * ql;
+#pragma unroll
+            for (int c = 0; c < SS; ++c) {
+              const T* row = qq + int64_t(ch[c]) * nvq;
+              acc += cw[c] * (w0 * row[p0] + w1 * row[p1]);
+            }
+          }
+          Qtb[int64_t(m) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
         }
       }
-      Qtb[int64_t(m) * ltotal + L.off[lg] + loc] = acc;
     }
   }
 }
 
 // ------------------------------------------------------------- launchers --
 template <class T>
-void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, hipStream_t s) {
+void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, hipStream_t s) {
   if (nsitems == 0) return;
   dim3 grid(unsigned(nsitems), C.B);
-  if (d == 1) hipLaunchKernelGGL((k_scan2<T, 1>), grid, dim3(kFB), 0, s, C);
-  else if (d == 2) hipLaunchKernelGGL((k_scan2<T, 2>), grid, dim3(kFB), 0, s, C);
-  else hipLaunchKernelGGL((k_scan2<T, 3>), grid, dim3(kFB), 0, s, C);
+#define SGDG_SCAN_CASE(DD, RR) \
+  if (d == DD && R == RR) hipLaunchKernelGGL((k_scan2<T, DD, RR>), grid, dim3(kFB), 0, s, C);
+  SGDG_SCAN_CASE(1, 1) SGDG_SCAN_CASE(1, 2) SGDG_SCAN_CASE(1, 3)
+  SGDG_SCAN_CASE(2, 1) SGDG_SCAN_CASE(2, 2) SGDG_SCAN_CASE(2, 3)
+  SGDG_SCAN_CASE(3, 1) SGDG_SCAN_CASE(3, 2) SGDG_SCAN_CASE(3, 3)
+#undef SGDG_SCAN_CASE
   SGDG_CHECK_HIP(hipGetLastError());
 }
 
@@ -467,8 +501,8 @@ void fused_tiles(const FusedCall<T>& C, int d, int R, hipStream_t s) {
   SGDG_CHECK_HIP(hipGetLastError());
 }
 
-template void fused_scan_step<double>(const FusedCall<double>&, int, int, hipStream_t);
-template void fused_scan_step<float>(const FusedCall<float>&, int, int, hipStream_t);
+template void fused_scan_step<double>(const FusedCall<double>&, int, int, int, hipStream_t);
+template void fused_scan_step<float>(const FusedCall<float>&, int, int, int, hipStream_t);
 template void fused_tiles<double>(const FusedCall<double>&, int, int, hipStream_t);
 template void fused_tiles<float>(const FusedCall<float>&, int, int, hipStream_t);
 

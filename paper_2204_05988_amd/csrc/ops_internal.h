@@ -93,7 +93,8 @@ struct sgdg_grid_s {
 };
 
 struct DomDev {
-  DevBuf nbr, par, parw, chi, chiw, vals, vals32, wide, rvals, rvals32;
+  DevBuf nbr, tnbr, par, parw, chi, chiw, tchi, tchiw, vals, vals32, tvals, tvals32, wide, rvals, rvals32, twide,
+      trvals, trvals32;
   DevDomain d;
 };
 

@@ -136,10 +136,34 @@ static void upload_domain(DomainData& D, DomDev& dd) {
       par.insert(par.end(), size_t(T.n) * 2, 0);
       parw.insert(parw.end(), size_t(T.n) * 2, 0.0);
     }
+    d.lev_n[l - D.lmin] = T.n;
     o += T.n * S;
     po += T.n * 2;
   }
   d.nbr = upload(dd.nbr, nbr);
+  // slot-major copies: entry e of consecutive nodes is contiguous.  off(l) is
+  // the start of level l in a block of `stride` elements; K entries per node.
+  auto slot_major = [&](auto& dst, const auto& src, size_t nblocks, int64_t stride, int K, auto off) {
+    dst.resize(src.size());
+    for (size_t bk = 0; bk < nblocks; ++bk)
+      for (int l = D.lmin; l <= D.lmax; ++l) {
+        const int64_t n = D.L(l).n, base = int64_t(bk) * stride + off(l);
+        for (int64_t i = 0; i < n; ++i)
+          for (int e = 0; e < K; ++e) dst[base + int64_t(e) * n + i] = src[base + i * K + e];
+      }
+  };
+  auto loff = [&](int l) { return d.lev_off[l - D.lmin]; };
+  {
+    std::vector<int32_t> t;
+    slot_major(t, nbr, 1, o, S, loff);
+    d.tnbr = upload(dd.tnbr, t);
+    std::vector<int32_t> tc;
+    slot_major(tc, chi, 1, o, S, loff);
+    d.tchi = upload(dd.tchi, tc);
+    std::vector<double> tw;
+    slot_major(tw, chiw, 1, o, S, loff);
+    d.tchiw = upload(dd.tchiw, tw);
+  }
   d.chi = upload(dd.chi, chi);
   d.chiw = upload(dd.chiw, chiw);
   d.par = upload(dd.par, par);
@@ -156,6 +180,14 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   for (size_t i = 0; i < vals.size(); ++i) v32[i] = float(vals[i]);
   d.vals = upload(dd.vals, vals);
   d.vals32 = upload(dd.vals32, v32);
+  {
+    std::vector<double> t;
+    slot_major(t, vals, nf, o, S, loff);
+    std::vector<float> t32(t.size());
+    for (size_t i = 0; i < t.size(); ++i) t32[i] = float(t[i]);
+    d.tvals = upload(dd.tvals, t);
+    d.tvals32 = upload(dd.tvals32, t32);
+  }
   // restricted stencils
   const int W = int(D.woff.size());
   d.W = W;
@@ -180,6 +212,16 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   for (size_t i = 0; i < rv.size(); ++i) rv32[i] = float(rv[i]);
   d.rvals = upload(dd.rvals, rv);
   d.rvals32 = upload(dd.rvals32, rv32);
+  auto woff = [&](int l) { return d.wlev_off[l - D.lmin]; };
+  std::vector<int32_t> tw;
+  slot_major(tw, wide, 1, wo, W, woff);
+  d.twide = upload(dd.twide, tw);
+  std::vector<double> trv;
+  slot_major(trv, rv, nf, wo, W, woff);
+  std::vector<float> trv32(trv.size());
+  for (size_t i = 0; i < trv.size(); ++i) trv32[i] = float(trv[i]);
+  d.trvals = upload(dd.trvals, trv);
+  d.trvals32 = upload(dd.trvals32, trv32);
 }
 
 static void upload_op(OpDev& od) {

@@ -135,13 +135,17 @@ struct DevDomain {
   int S = 0, lmin = 0, lmax = 0;
   int64_t lev_off[kMaxLevels] = {};   // start of level l in the [n][S] tables (l - lmin)
   int64_t par_off[kMaxLevels] = {};   // start of level l in the [n][2] parent tables
-  const int32_t* nbr = nullptr;
+  int64_t lev_n[kMaxLevels] = {};     // nodes of level l (l - lmin)
+  const int32_t* nbr = nullptr;       // [n][S] per level
+  const int32_t* tnbr = nullptr;      // the same, slot-major [S][n] per level (coalesced by node)
   const int32_t* par = nullptr;
   const double* parw = nullptr;
   const int32_t* chi = nullptr;
   const double* chiw = nullptr;
   const double* vals = nullptr;       // [factor][level-major [n][S]] FP64
   const float* vals32 = nullptr;      // same, FP32
+  const double* tvals = nullptr;      // [factor][level-major [S][n]] FP64 (slot-major)
+  const float* tvals32 = nullptr;     // same, FP32
   int64_t fac_stride = 0;             // elements per factor
   int mass_fac = -1;                  // plain mass factor (Jacobi / Chebyshev preconditioner)
   int W = 0;                          // restricted-stencil width
@@ -149,6 +153,11 @@ struct DevDomain {
   const int32_t* wide = nullptr;      // fine node of each restricted slot
   const double* rvals = nullptr;      // [factor][levels [n][W]] FP64
   const float* rvals32 = nullptr;
+  const int32_t* twide = nullptr;     // slot-major copies [W][n] per level (coalesced by node)
+  const double* trvals = nullptr;
+  const float* trvals32 = nullptr;
+  const int32_t* tchi = nullptr;      // slot-major children [S][n] per level
+  const double* tchiw = nullptr;
   int64_t rstride = 0;                // elements per factor
 };
 

@@ -7,6 +7,7 @@
 #include <sstream>
 
 #include "ops_internal.h"
+#include "split.h"
 
 // ----------------------------------------------------------------- batch ---
 namespace {
@@ -33,15 +34,17 @@ struct Items {
 struct KindData {
   DevBuf desc;
   std::vector<ProbDesc> host;
-  int64_t pt_bstride = 0, qt_bstride = 0, total = 0;
+  int64_t pt_bstride = 0, qt_bstride = 0, z_bstride = 0, total = 0;
   int R = 1;
   bool any_scan = false;
   Items it[2];  // FP64, FP32
+  DevBuf split_items;
+  int n_split = 0;
 };
 
 template <class T>
 struct BWork {
-  DevBuf Pt, Qt, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
+  DevBuf Pt, Qt, Z, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
 };
 
 }  // namespace
@@ -61,6 +64,9 @@ struct sgdg_batch_s {
   bool owned_by_ops = false;
   // box-shape choice of the fused kernel per element size (tuned or default)
   int xbox[2] = {0, 0};
+  // operator application variant: 0 split (two streaming passes), 1 fused box tiles
+  int variant = 0;
+  int split_bc = 0;  // vectors per thread of the split passes (0: default for d)
   // graphs of grid-problem GMRES cycles
   std::map<std::string, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
@@ -92,6 +98,8 @@ Batch& self_batch(sgdg_ops o) {
     b->d = o->X.dom.d;
     b->R = o->grid->R;
     b->owned_by_ops = true;
+    if (const char* v = getenv("SGDG_APPLY_VARIANT")) b->variant = std::string(v) == "fused" ? 1 : 0;
+    if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
     o->self.reset(b);
   }
   return *o->self;
@@ -143,7 +151,8 @@ static KindData& kind(Batch& B, int k) {
   const int opidx = (k == K_FULL || k == K_DIAG || k == K_CT) ? 0 : (k == K_MASS ? 1 : (k == K_DATAF ? 2 : 3));
   const int R = B.P[0]->ops[opidx].op.Rin;
   K.R = R;
-  int64_t off = 0, pt = 0, qt = 0;
+  int64_t off = 0, pt = 0, qt = 0, zo = 0;
+  std::vector<SplitItem> sitems;
   for (size_t p = 0; p < B.P.size(); ++p) {
     sgdg_ops o = B.P[p];
     sgdg_grid g = o->grid;
@@ -174,6 +183,12 @@ static KindData& kind(Batch& B, int k) {
     off += D.G.off[D.G.n];
     D.pt_off = pt;
     D.qt_off = qt;
+    D.z_off = zo;
+    zo += int64_t(std::max(1, D.op.nvg)) * D.G.off[D.G.n];
+    for (int gi = 0; gi < D.G.n; ++gi) {
+      const int64_t plane = int64_t(D.G.nx[gi]) * D.G.nv[gi];
+      for (int64_t p0 = 0; p0 < plane; p0 += split_points_per_item()) sitems.push_back(SplitItem{int(p), gi, p0});
+    }
     if (!D.diag_only) {
       K.any_scan = true;
       const int64_t lt = D.Gl.off[D.Gl.n];
@@ -185,7 +200,10 @@ static KindData& kind(Batch& B, int k) {
   K.total = off;
   K.pt_bstride = pt;
   K.qt_bstride = qt;
+  K.z_bstride = zo;
   upload(K.desc, K.host);
+  upload(K.split_items, sitems);
+  K.n_split = int(sitems.size());
   return K;
 }
 
@@ -293,8 +311,8 @@ static Items& items(Batch& B, int k, int elem) {
         if (D.diag_only || t + 1 >= D.G.n) continue;
         for (int side = 0; side < 2; ++side) {
           const int lg = side == 0 ? t : D.Gl.n - 1 - t;
-          const int64_t len = int64_t(K.R) * D.Gl.nx[lg] * D.Gl.nv[lg];
-          for (int64_t st = 0; st < len; st += fused_threads()) sits.push_back(ScanItem{int(p), side, lg, st});
+          const int64_t len = int64_t(D.Gl.nx[lg]) * D.Gl.nv[lg];  // points; slices loop in the kernel
+          for (int64_t st = 0; st < len; st += fused_threads()) sits.push_back(ScanItem{int(p), side, lg, 0, st});
         }
       }
       I.step_count.push_back(int(sits.size()) - I.step_first.back());
@@ -332,11 +350,31 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
       for (size_t t = 0; t < I.step_first.size(); ++t) {
         FusedCall<T> Cs = C;
         Cs.sitems = C.sitems + I.step_first[t];
-        fused_scan_step<T>(Cs, I.step_count[t], B.d, s);
+        fused_scan_step<T>(Cs, I.step_count[t], B.d, K.R, s);
       }
     });
   }
-  timed(B, 1, s, [&] { fused_tiles<T>(C, B.d, K.R, s); });
+  if (B.variant == 1) {
+    timed(B, 1, s, [&] { fused_tiles<T>(C, B.d, K.R, s); });
+    return;
+  }
+  SplitCall<T> S{};
+  S.descs = C.descs;
+  S.items = ptr<SplitItem>(K.split_items);
+  S.nitems = K.n_split;
+  S.B = nb;
+  S.u_bstride = S.y_bstride = K.total;
+  S.pt_bstride = K.pt_bstride;
+  S.qt_bstride = K.qt_bstride;
+  S.z_bstride = K.z_bstride;
+  S.u = u;
+  S.y = y;
+  S.Pt = C.Pt;
+  S.Qt = C.Qt;
+  w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
+  S.Z = ptr<T>(w.Z);
+  const int bc = B.split_bc > 0 ? B.split_bc : split_default_bc(B.d);
+  timed(B, 1, s, [&] { split_apply<T>(S, B.d, K.R, bc, s); });
 }
 
 // ---------------------------------------------------------- segments -----
@@ -1106,6 +1144,8 @@ extern "C" sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch*
   b->P.assign(ops, ops + n);
   b->d = d;
   b->R = r + 1;
+  if (const char* v = getenv("SGDG_APPLY_VARIANT")) b->variant = std::string(v) == "fused" ? 1 : 0;
+  if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
   *out = b;
   API_END
 }

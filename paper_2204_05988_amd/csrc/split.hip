@@ -1,0 +1,256 @@
+// Split operator application for gfx950: two streaming passes over the points
+// of every upper grid, with the v-stencil stage kept in HBM between them.
+//
+// With V-groups j (terms sharing a v-factor) and X-groups m (terms sharing an
+// x-factor), the block row of upper grid i is (Sect. 4.2, with the embedding
+// identities X_{l,l'} = X_l E_{l<-l'} below and E_{l'<-l}^T X_{l'} above):
+//
+//   y_i = sum_k Tm_k (X_k (x) I) Z_i^{j(k)} + sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt_i^{m(k)}
+//   Z_i^j = (I (x) V_j) u_i + (E^x (x) I) Pt_i^j
+//
+// Pass 1 (k_vstage) computes Z for every group: the v-stencil of u (v is the
+// fastest axis, so the 2^d-neighbour gathers stay in L1/L2) plus the x-prolonged
+// lower-partner scan array.  Pass 2 (k_xstage) applies the x-stencils of the
+// terms to Z (rows x +- 1 are nv apart: one coalesced row per neighbour) and
+// adds the upper-partner part, prolonging Qt in v on the fly.  One thread owns
+// one point and BC vectors of the batch; the stencil indices, parent tables
+// and factor values of its point are loaded once and reused across them.
+#include <hip/hip_runtime.h>
+
+#include "split.h"
+
+namespace sgdg {
+
+namespace {
+
+constexpr int kSB = 256;  // threads (points) per block
+// slot-major factor tables: entry e of the nodes of one level is contiguous
+template <class T> __device__ __forceinline__ const T* vals(const DevDomain& D);
+template <> __device__ __forceinline__ const double* vals<double>(const DevDomain& D) { return D.tvals; }
+template <> __device__ __forceinline__ const float* vals<float>(const DevDomain& D) { return D.tvals32; }
+template <class T> __device__ __forceinline__ const T* tmat(const DevOp& op);
+template <> __device__ __forceinline__ const double* tmat<double>(const DevOp& op) { return op.term_tm; }
+template <> __device__ __forceinline__ const float* tmat<float>(const DevOp& op) { return op.term_tm32; }
+
+template <class T, int D, int R, int BC>
+__global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  const SplitItem it = C.items[blockIdx.x];
+  const int b0 = int(blockIdx.y) * BC;
+  const ProbDesc& A = C.descs[it.prob];
+  const int g = it.grid;
+  const int nx = A.G.nx[g], nv = A.G.nv[g];
+  const int64_t plane = int64_t(nx) * nv;
+  const int64_t p = it.p0 + threadIdx.x;
+  if (p >= plane) return;
+  const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
+  const int lx = A.G.lx[g], lv = A.G.lv[g];
+  const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
+  int32_t nbv[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) nbv[e] = A.DV.tnbr[vlo + int64_t(e) * nv + v];
+  const bool has_p = !A.diag_only && g > 0;
+  int32_t px0 = 0, px1 = 0;
+  T wx0 = 0, wx1 = 0;
+  int64_t lo = 0, lplane = 0;
+  if (has_p) {
+    const int64_t pp = A.DX.par_off[lx - A.DX.lmin] + 2 * int64_t(x);
+    px0 = A.DX.par[pp];
+    px1 = A.DX.par[pp + 1];
+    wx0 = T(A.DX.parw[pp]);
+    wx1 = T(A.DX.parw[pp + 1]);
+    lo = A.Gl.off[g - 1];
+    lplane = int64_t(A.Gl.nx[g - 1]) * nv;
+  }
+  const int64_t total = A.G.off[A.G.n];
+  const int64_t ltotal = A.Gl.off[A.Gl.n];
+  const T* vv = vals<T>(A.DV);
+  T un[BC][R][SS];
+#pragma unroll
+  for (int q = 0; q < BC; ++q) {
+    const int b = b0 + q < C.B ? b0 + q : b0;
+    const T* ub = C.u + int64_t(b) * C.u_bstride + A.u_off + A.G.off[g] + int64_t(x) * nv;
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int e = 0; e < SS; ++e) un[q][s][e] = ub[int64_t(s) * plane + nbv[e]];
+  }
+  for (int j = 0; j < A.op.nvg; ++j) {
+    const T* f = vv + int64_t(A.op.vg_fac[j]) * A.DV.fac_stride + vlo + v;
+    T fv[SS];
+#pragma unroll
+    for (int e = 0; e < SS; ++e) fv[e] = f[int64_t(e) * nv];
+#pragma unroll
+    for (int q = 0; q < BC; ++q) {
+      const int b = b0 + q;
+      if (b >= C.B) break;
+      T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(j) * total + A.G.off[g] + p;
+      const T* pt = has_p ? C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v : nullptr;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        T z = T(0);
+#pragma unroll
+        for (int e = 0; e < SS; ++e) z += fv[e] * un[q][s][e];
+        if (has_p) z += wx0 * pt[int64_t(s) * lplane + int64_t(px0) * nv] + wx1 * pt[int64_t(s) * lplane + int64_t(px1) * nv];
+        zb[int64_t(s) * plane] = z;
+      }
+    }
+  }
+}
+
+template <class T, int D, int R, int BC>
+__global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  const SplitItem it = C.items[blockIdx.x];
+  const int b0 = int(blockIdx.y) * BC;
+  const ProbDesc& A = C.descs[it.prob];
+  const int g = it.grid;
+  const int nx = A.G.nx[g], nv = A.G.nv[g];
+  const int64_t plane = int64_t(nx) * nv;
+  const int64_t p = it.p0 + threadIdx.x;
+  if (p >= plane) return;
+  const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
+  const int lx = A.G.lx[g], lv = A.G.lv[g];
+  const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
+  const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
+  const DevOp& op = A.op;
+  const T* xv = vals<T>(A.DX);
+  const T* vv = vals<T>(A.DV);
+  const T* tm = tmat<T>(op);
+  const int64_t total = A.G.off[A.G.n];
+  int32_t nbx[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) nbx[e] = A.DX.tnbr[xlo + int64_t(e) * nx + x];
+  T acc[BC][R];
+#pragma unroll
+  for (int q = 0; q < BC; ++q)
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[q][s] = T(0);
+  // diagonal + lower partners: x-stencils of the staged Z
+  for (int j = 0; j < op.nvg; ++j) {
+    T z[BC][R][SS];
+#pragma unroll
+    for (int q = 0; q < BC; ++q) {
+      const int b = b0 + q < C.B ? b0 + q : b0;
+      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(j) * total + A.G.off[g] + v;
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int e = 0; e < SS; ++e) z[q][s][e] = zb[int64_t(s) * plane + int64_t(nbx[e]) * nv];
+    }
+    for (int kk = op.vg_start[j]; kk < op.vg_start[j + 1]; ++kk) {
+      const int k = op.vg_terms[kk];
+      const T* f = xv + int64_t(op.term_xf[k]) * A.DX.fac_stride + xlo + x;
+      T xf[SS];
+#pragma unroll
+      for (int e = 0; e < SS; ++e) xf[e] = f[int64_t(e) * nx];
+      const T* tk = tm + int64_t(k) * R * R;
+      T tkv[R * R];
+#pragma unroll
+      for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) {
+          T t = T(0);
+#pragma unroll
+          for (int e = 0; e < SS; ++e) t += xf[e] * z[q][s2][e];
+#pragma unroll
+          for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
+        }
+    }
+  }
+  // upper partners: v-stencils of the v-prolonged Qt
+  const bool has_q = !A.diag_only && g + 1 < A.G.n;
+  if (has_q) {
+    const int nvl = A.Gl.nv[g];  // lower grid g: (lx, lv - 1)
+    const int64_t qplane = int64_t(nx) * nvl;
+    const int64_t ltotal = A.Gl.off[A.Gl.n];
+    const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
+    int32_t vp0[SS], vp1[SS];
+    T vw0[SS], vw1[SS];
+#pragma unroll
+    for (int e = 0; e < SS; ++e) {
+      const int32_t vn = A.DV.tnbr[vlo + int64_t(e) * nv + v];
+      vp0[e] = A.DV.par[vpo + 2 * int64_t(vn)];
+      vp1[e] = A.DV.par[vpo + 2 * int64_t(vn) + 1];
+      vw0[e] = T(A.DV.parw[vpo + 2 * int64_t(vn)]);
+      vw1[e] = T(A.DV.parw[vpo + 2 * int64_t(vn) + 1]);
+    }
+    for (int m = 0; m < op.nxg; ++m) {
+      T qv[BC][R][SS];
+#pragma unroll
+      for (int q = 0; q < BC; ++q) {
+        const int b = b0 + q < C.B ? b0 + q : b0;
+        const T* qb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g] +
+                      int64_t(x) * nvl;
+#pragma unroll
+        for (int s = 0; s < R; ++s)
+#pragma unroll
+          for (int e = 0; e < SS; ++e)
+            qv[q][s][e] = vw0[e] * qb[int64_t(s) * qplane + vp0[e]] + vw1[e] * qb[int64_t(s) * qplane + vp1[e]];
+      }
+      for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
+        const int k = op.xg_terms[kk];
+        const T* f = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
+        T vf[SS];
+#pragma unroll
+        for (int e = 0; e < SS; ++e) vf[e] = f[int64_t(e) * nv];
+        const T* tk = tm + int64_t(k) * R * R;
+        T tkv[R * R];
+#pragma unroll
+        for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
+#pragma unroll
+        for (int q = 0; q < BC; ++q)
+#pragma unroll
+          for (int s2 = 0; s2 < R; ++s2) {
+            T t = T(0);
+#pragma unroll
+            for (int e = 0; e < SS; ++e) t += vf[e] * qv[q][s2][e];
+#pragma unroll
+            for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < BC; ++q) {
+    const int b = b0 + q;
+    if (b >= C.B) break;
+    T* yb = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(R) * A.poff[g] + p;
+#pragma unroll
+    for (int s = 0; s < R; ++s) yb[int64_t(s) * plane] = acc[q][s];
+  }
+}
+
+}  // namespace
+
+int split_points_per_item() { return kSB; }
+int split_default_bc(int d) { return d == 3 ? 1 : 2; }
+
+template <class T>
+void split_apply(const SplitCall<T>& C, int d, int R, int bc, hipStream_t s) {
+  if (C.nitems == 0) return;
+  if (d == 3 || (bc != 1 && bc != 2 && bc != 4)) bc = d == 3 ? 1 : 2;
+  dim3 grid(unsigned(C.nitems), unsigned((C.B + bc - 1) / bc));
+#define SGDG_SPLIT_CASE(DD, RR, BB)                                                   \
+  if (d == DD && R == RR && bc == BB) {                                               \
+    hipLaunchKernelGGL((k_vstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);          \
+    SGDG_CHECK_HIP(hipGetLastError());                                                \
+    hipLaunchKernelGGL((k_xstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);          \
+    SGDG_CHECK_HIP(hipGetLastError());                                                \
+    return;                                                                           \
+  }
+#define SGDG_SPLIT_R(DD, BB) SGDG_SPLIT_CASE(DD, 1, BB) SGDG_SPLIT_CASE(DD, 2, BB) SGDG_SPLIT_CASE(DD, 3, BB)
+  SGDG_SPLIT_R(1, 1) SGDG_SPLIT_R(1, 2) SGDG_SPLIT_R(1, 4)
+  SGDG_SPLIT_R(2, 1) SGDG_SPLIT_R(2, 2) SGDG_SPLIT_R(2, 4)
+  SGDG_SPLIT_R(3, 1)
+#undef SGDG_SPLIT_R
+#undef SGDG_SPLIT_CASE
+  throw Error{SGDG_E_ARG, "unsupported dimension or time degree"};
+}
+
+template void split_apply<double>(const SplitCall<double>&, int, int, int, hipStream_t);
+template void split_apply<float>(const SplitCall<float>&, int, int, int, hipStream_t);
+
+}  // namespace sgdg
