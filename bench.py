@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 157.3  # non-packed FP32: twice the FP64 lane rate
 
 
 def parse():
@@ -46,41 +47,84 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed loop, copy a 512 MiB buffer once (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def kernel_roofline(ops, shapes, B, R, elem_bytes):
-    """Algorithmic flops and bytes per launch of the fused accumulation kernel (k_fused).
+def kernel_work(ops, B, R, elem_bytes):
+    """Algorithmic flops and HBM bytes per launch of each operator kernel.
 
-    Per output point of upper grid i and per vector:
-      diagonal+lower part: for every V-group j, Z_j = V_j u + E^x Pt_j   (Rin (2 Sv + 4) flops)
-                           for every term k, Rin x-stencil sums of Sx entries and an Rout x Rin mix
-      upper part (i < n-1): for every X-group m, E^v Qt_m                  (Rin 4 flops)
-                           for every term k, Rin v-stencil sums of Sv entries and the mix
-    Bytes: u read once (Rin), y written once (Rout), the lower-diagonal scan
-    arrays read once per group (they are 2^d times smaller than the grid).
-    Box halos are not counted (they are implementation overhead, not algorithm).
+    Per point of upper grid i (of n) and per vector, with nt Kronecker terms,
+    nvg / nxg distinct v- / x-factors, S-point stencils (S = 3, 7, 15 for
+    d = 1, 2, 3) and R time slices:
+      k_vstage  W^m = sum_{k in m} Tm_k [V_k u + E^x Pt^{j(k)}]:
+                flops nt R 2S + nt 2R^2 (+ nt R 4 if i > 0);
+                bytes u (R) + W (nxg R) [+ Pt (nt R / 2^d) if i > 0]
+      k_ustage  sum_k Tm_k V_k E^v Qt^{m(k)}, i < n-1 (zero fill otherwise):
+                flops nxg S R 4 + nt (R 2S + 2R^2); bytes Qt (nxg R / 2^d) + y (R)
+      k_xstage  y += sum_m X_m W^m:  flops nxg R 2S; bytes W (nxg R) + y (2R)
+      k_fused   the whole block row from LDS-staged boxes:
+                flops nvg R (2S + 4) + nt R (2S + 2R) [+ nxg R 4 + nt R (2S + 2R) if i < n-1];
+                bytes u (R) + y (R) + Pt, Qt (nvg R / 2^d, nxg R / 2^d)
+    The partner scan arrays live on the lower diagonal, 2^d times smaller.
     """
     info = ops.op_info()
-    nt, nvg, nxg, Sx, Sv = info["nterms"], info["nvg"], info["nxg"], info["Sx"], info["Sv"]
+    nt, nvg, nxg = info["nterms"], info["nvg"], info["nxg"]
     d = ops.w.d
-    flops = 0.0
-    bytes_ = 0.0
-    n = len(shapes)
-    for gi, (_, _, nx, nv) in enumerate(shapes):
-        pts = nx * nv
-        per = nvg * R * (2 * Sv + 4) + nt * R * (2 * Sx + 2 * R)
-        by = R + R
-        if gi > 0:
-            by += nvg * R / 2 ** d
-        if gi + 1 < n:
-            per += nxg * R * 4 + nt * R * (2 * Sv + 2 * R)
-            by += nxg * R / 2 ** d
-        flops += pts * per
-        bytes_ += pts * by * elem_bytes
-    return flops * B, bytes_ * B
+    S = {1: 3, 2: 7, 3: 15}[d]
+    n = len(ops.upper)
+    work = {k: [0.0, 0.0] for k in ("vstage", "ustage", "xstage", "fused")}
+    for gi, (_, _, nx, nv) in enumerate(ops.upper):
+        pts = nx * nv * B
+        hp, hq = gi > 0, gi + 1 < n
+
+        def add(k, fl, by):
+            work[k][0] += pts * fl
+            work[k][1] += pts * by * elem_bytes
+        add("vstage", nt * R * 2 * S + nt * 2 * R * R + (nt * R * 4 if hp else 0),
+            R + nxg * R + (nt * R / 2 ** d if hp else 0))
+        add("ustage", (nxg * S * R * 4 + nt * (R * 2 * S + 2 * R * R)) if hq else 0,
+            (nxg * R / 2 ** d if hq else 0) + R)
+        add("xstage", nxg * R * 2 * S, nxg * R + 2 * R)
+        add("fused", nvg * R * (2 * S + 4) + nt * R * (2 * S + 2 * R) + ((nxg * R * 4 + nt * R * (2 * S + 2 * R)) if hq else 0),
+            2 * R + (nvg * R / 2 ** d if hp else 0) + (nxg * R / 2 ** d if hq else 0))
+    return work
+
+
+def recorded_traffic(kernel, workload_tag):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary of this workload, or None if there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"apply_{workload_tag}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = {"k_vstage": "split.hip", "k_ustage": "split.hip", "k_xstage": "split.hip",
+           "k_scan2": "fused.hip", "k_fused": "fused.hip"}.get(kernel)
+    if src is None:
+        return None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2204_05988_amd", "csrc", src), "rb").read()).hexdigest()[:16]
+    text = open(path).read()
+    if f"{src} sha256/16 {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if f and f[0] == kernel:
+            return float(f[4])
+    return None
+
+
+def roofline(fl, by, ms, valu_peak):
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    t_alu = fl / (valu_peak * 1e12)
+    if t_alu > t_hbm:
+        ach = fl / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": valu_peak, "unit": "TFLOP/s",
+                "frac": round(ach / valu_peak, 4)}
+    ach = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -102,6 +146,9 @@ def main():
     u = torch.tensor(random_vector(ops.ndof, 0, batch=B), device=dev, dtype=dt)
     y = torch.empty_like(u)
     stream = torch.cuda.current_stream()
+    tuned = None if a.no_tune else ops.tune(a.dtype, batch=B, reps=3)
+    if tuned is not None:
+        _log(f"launch configuration: {tuned}")
     for _ in range(a.warmup):
         ops.apply(u, y, batch=B)
     torch.cuda.synchronize()
@@ -115,26 +162,25 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    prof = {name: ops.profile_read(slot) for slot, name in enumerate(["scan", "fused"])}
+    slots = {"scan": 0, "fused": 1, "vstage": 3, "ustage": 4, "xstage": 5}
+    prof = {name: ops.profile_read(slot) for name, slot in slots.items()}
+    prof = {k: v for k, v in prof.items() if v[1] > 0}
     ops.profile(False)
     ms_step = ms / a.steps
     value = B * ops.ndof / (ms_step * 1e-3)
-    # dominant kernel
-    dom = max(prof, key=lambda k: prof[k][0])
-    fl, by = kernel_roofline(ops, ops.upper, B, R, 8 if a.dtype == "f64" else 4)
-    fin_ms = prof["fused"][0] / max(prof["fused"][1], 1)
-    ach_gbs = by / (fin_ms * 1e-3) / 1e9
-    ach_tf = fl / (fin_ms * 1e-3) / 1e12
-    t_hbm = by / (HBM_PEAK_GBS * 1e9)
-    t_alu = fl / (FP64_VALU_PEAK_TFLOPS * 1e12)
-    if t_alu > t_hbm:
-        roof = {"bound": "alu", "achieved": round(ach_tf, 3), "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach_tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None}
-    else:
-        roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    roof["kernel"] = "k_fused"
-    roof["kernel_ms"] = round(fin_ms, 4)
+    valu_peak = FP64_VALU_PEAK_TFLOPS if a.dtype == "f64" else FP32_VALU_PEAK_TFLOPS
+    work = kernel_work(ops, B, R, 8 if a.dtype == "f64" else 4)
+    per_kernel = {}
+    for k, (tot, cnt) in prof.items():
+        if k in work and cnt > 0:
+            kms = tot / cnt
+            per_kernel[k] = dict(roofline(work[k][0], work[k][1], kms, valu_peak), kernel_ms=round(kms, 4),
+                                 flops=work[k][0], bytes=work[k][1])
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["kernel_ms"])
+    roof = dict(per_kernel[dom])
+    roof["kernel"] = "k_" + dom
+    tag = f"c2_L{a.level}_B{B}_{a.dtype}"
+    roof["traffic"] = recorded_traffic("k_" + dom, tag)
     out = {
         "metric": "DOF-applies/s", "value": value, "unit": "DOF-applies/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -142,8 +188,10 @@ def main():
         "config": {"workload": f"4D phase space d=2, r=1, sparse grid L={a.level} (c2), full SD-DG operator",
                    "dofs_per_vector": ops.ndof, "batch": B, "grids": len(ops.upper)},
         "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items()},
-        "dominant_kernel": dom,
+        "launch_config": tuned,
+        "dominant_kernel": "k_" + dom,
         "roofline": roof,
+        "kernels": per_kernel,
         "wall_s": round(wall, 3),
     }
     _log(f"apply: {value:.3e} DOF-applies/s")

@@ -315,6 +315,32 @@ sgdg_status sgdg_net_forward(sgdg_net n, const float* x_dev, float* y_dev, hipSt
 sgdg_status sgdg_net_backward(sgdg_net n, const float* x_dev, const float* dy_dev, float* grad_dev, hipStream_t s);
 void sgdg_net_destroy(sgdg_net n);
 
+/* ------------------------------------------------------------- autotuner -- */
+
+/* Launch configuration of the operator application.  variant 0: split
+ * application (v-stage, upper-partner and x-stage passes) with
+ * vectors_per_thread vectors per thread; variant 1: fused box tiles with
+ * x-boxes of xbox nodes per axis. */
+typedef struct {
+  int variant;
+  int vectors_per_thread;
+  int xbox;
+  double ms;        /* measured time of one full application with this configuration */
+  int from_cache;   /* 1 if taken from the tuning cache without measuring */
+} sgdg_tune_result;
+
+/* Times every candidate configuration of the full operator application for
+ * `batch` vectors of dtype t on stream s (reps timed applications each, after
+ * one warm-up), keeps the fastest for this handle, and records it in the
+ * tuning cache, a text file keyed by dimension, slices, dtype, batch and the
+ * levels of every grid: $SGDG_TUNE_CACHE, else $HOME/.cache/sgdg_tune.txt.
+ * A cached entry is used without measuring unless force is 1.  Allocates and
+ * frees two work vectors; synchronises s. */
+sgdg_status sgdg_tune(sgdg_ops o, sgdg_dtype t, int batch, int reps, int force, sgdg_tune_result* out,
+                      hipStream_t s);
+/* The same for a multi-problem batch (one vector per problem). */
+sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int force, sgdg_tune_result* out, hipStream_t s);
+
 /* ------------------------------------------------------------ diagnostics -- */
 
 /* Event timing of the operator kernels (for roofline reports).  mode 1 resets
@@ -324,7 +350,9 @@ sgdg_status sgdg_profile(sgdg_ops o, int mode);
 /* Accumulated time (ms) and launch-group count of one kernel class since the
  * last reset: slot 0 = level scans of the partner sums (all steps of one
  * application, k_scan2), 1 = box-tiled accumulation (k_fused), 2 = grid-problem
- * GMRES cycles of the preconditioner.  Waits for the recorded events. */
+ * GMRES cycles of the preconditioner, 3 = v-stage (k_vstage), 4 =
+ * upper-partner pass (k_ustage), 5 = x-stage (k_xstage).  Waits for the
+ * recorded events. */
 sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launches);
 /* Shape of one operator: Kronecker terms, distinct v- and x-factors, stencil
  * sizes of the two domains and the time slices in/out. */

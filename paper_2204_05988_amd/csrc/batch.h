@@ -26,7 +26,7 @@ struct ProbDesc {
   int64_t u_off;       // start of this problem's vector in the concatenated layout
   int64_t y_off;       // start of its output vector
   int64_t pt_off, qt_off;  // start of its scan arrays
-  int64_t z_off;           // start of its staged v-stencil values (split application)
+  int64_t z_off;           // start of its staged v-stage arrays (split application)
 };
 
 // A box of x-nodes times a box of v-nodes of one grid of one problem.
@@ -76,7 +76,7 @@ struct SplitCall {
   T* y;
   const T* Pt;
   const T* Qt;
-  T* Z;                    // [b][problem: V-group][grid layout] staged (I (x) V_j) u + (E^x (x) I) Pt_j
+  T* Z;                    // [b][problem: X-group m][grid layout] staged v-stage W^m
 };
 
 // A contiguous segment of a concatenated vector: one component grid of one

@@ -2,6 +2,8 @@
 // (Algorithm 1's body, Sect. 4.3), the strip right-hand side
 // (eq:weak_form_j) and the flexible-GMRES strip solves, for a batch of
 // independent problems.  The single-problem entry points use a batch of one.
+#include <sys/stat.h>
+
 #include <chrono>
 #include <fstream>
 #include <sstream>
@@ -70,15 +72,17 @@ struct sgdg_batch_s {
   // graphs of grid-problem GMRES cycles
   std::map<std::string, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
-  // event timing: slot 0 level scans, 1 fused tiles, 2 grid-problem cycles
+  // event timing: slot 0 level scans, 1 fused tiles, 2 grid-problem cycles,
+  // 3/4/5 split v-stage, upper-partner and x-stage passes
+  static constexpr int kSlots = 6;
   bool prof = false;
   struct Ev {
     hipEvent_t a, b;
     int slot;
   };
   std::vector<Ev> events;
-  double prof_ms[3] = {0, 0, 0};
-  int64_t prof_n[3] = {0, 0, 0};
+  double prof_ms[kSlots] = {};
+  int64_t prof_n[kSlots] = {};
   ~sgdg_batch_s() {
     for (auto& e : events) {
       (void)hipEventDestroy(e.a);
@@ -184,7 +188,7 @@ static KindData& kind(Batch& B, int k) {
     D.pt_off = pt;
     D.qt_off = qt;
     D.z_off = zo;
-    zo += int64_t(std::max(1, D.op.nvg)) * D.G.off[D.G.n];
+    zo += int64_t(std::max(1, D.op.nxg)) * D.G.off[D.G.n];  // one staged array per X-group
     for (int gi = 0; gi < D.G.n; ++gi) {
       const int64_t plane = int64_t(D.G.nx[gi]) * D.G.nv[gi];
       for (int64_t p0 = 0; p0 < plane; p0 += split_points_per_item()) sitems.push_back(SplitItem{int(p), gi, p0});
@@ -374,7 +378,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
   S.Z = ptr<T>(w.Z);
   const int bc = B.split_bc > 0 ? B.split_bc : split_default_bc(B.d);
-  timed(B, 1, s, [&] { split_apply<T>(S, B.d, K.R, bc, s); });
+  for (int stage = 0; stage < 3; ++stage) timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
 }
 
 // ---------------------------------------------------------- segments -----
@@ -1020,6 +1024,128 @@ static void nodal_to_coef(Batch& B, const double* samples, int nq, const double*
   KernelsT<double>::ct_combine(ct_tab(B, Rs).t, blk, coef, s);
 }
 
+// ------------------------------------------------------------ autotuner --
+struct TuneCfg {
+  int variant, bc, xbox;
+};
+
+static std::vector<TuneCfg> tune_candidates(int d) {
+  std::vector<TuneCfg> c;
+  if (d == 3) {
+    c.push_back({0, 1, 0});
+  } else {
+    for (int bc : {1, 2, 4}) c.push_back({0, bc, 0});
+  }
+  const int base = d == 1 ? 32 : (d == 2 ? 8 : 4);
+  for (int xb : {base / 2, base, base * 2}) c.push_back({1, 0, xb});
+  return c;
+}
+
+static std::string tune_key(const Batch& B, int elem, int nb) {
+  std::ostringstream k;
+  k << "d" << B.d << "_R" << B.R << "_e" << elem << "_b" << nb << "_p" << B.P.size() << "_g";
+  for (sgdg_ops o : B.P) {
+    for (const auto& gd : o->grid->up) k << gd.lx << "." << gd.lv << ",";
+    k << (o->grid->x.periodic ? "P" : "N") << (o->grid->v.periodic ? "P" : "N") << ";";
+  }
+  return k.str();
+}
+
+static std::string tune_cache_path() {
+  if (const char* p = getenv("SGDG_TUNE_CACHE")) return p;
+  const char* h = getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/sgdg_tune.txt";
+}
+
+static bool tune_lookup(const std::string& key, TuneCfg& cfg, double& ms) {
+  std::ifstream f(tune_cache_path());
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {  // last entry of a key wins
+    std::istringstream in(line);
+    std::string k;
+    TuneCfg c{};
+    double t = 0;
+    if (in >> k >> c.variant >> c.bc >> c.xbox >> t && k == key) {
+      cfg = c;
+      ms = t;
+      found = true;
+    }
+  }
+  return found;
+}
+
+static void tune_store(const std::string& key, const TuneCfg& c, double ms) {
+  const std::string path = tune_cache_path();
+  const size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << " " << c.variant << " " << c.bc << " " << c.xbox << " " << ms << "\n";
+}
+
+static void set_cfg(Batch& B, const TuneCfg& c) {
+  B.variant = c.variant;
+  B.split_bc = c.bc;
+  if (c.variant == 1 && (B.xbox[0] != c.xbox || B.xbox[1] != c.xbox)) {
+    SGDG_CHECK_HIP(hipDeviceSynchronize());
+    B.xbox[0] = B.xbox[1] = c.xbox;
+    for (auto& K : B.kinds)
+      for (auto& I : K.it) I.built = false;  // box tables follow the new shape
+  }
+}
+
+template <class T>
+static double time_apply(Batch& B, const T* u, T* y, int nb, int reps, hipStream_t s) {
+  hipEvent_t a, b;
+  SGDG_CHECK_HIP(hipEventCreate(&a));
+  SGDG_CHECK_HIP(hipEventCreate(&b));
+  apply<T>(B, K_FULL, u, y, nb, s);
+  SGDG_CHECK_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) apply<T>(B, K_FULL, u, y, nb, s);
+  SGDG_CHECK_HIP(hipEventRecord(b, s));
+  SGDG_CHECK_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  SGDG_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return double(ms) / reps;
+}
+
+template <class T>
+static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t s) {
+  sgdg_tune_result r{};
+  const std::string key = tune_key(B, int(sizeof(T)), nb);
+  TuneCfg best{};
+  double best_ms = 0;
+  if (!force && tune_lookup(key, best, best_ms)) {
+    set_cfg(B, best);
+    r = {best.variant, best.bc, best.xbox, best_ms, 1};
+    return r;
+  }
+  const int64_t n = kind(B, K_FULL).total * nb;
+  DevBuf u, y;
+  u.alloc(sizeof(T) * n);
+  y.alloc(sizeof(T) * n);
+  KernelsT<T>::fill(n, T(1), ptr<T>(u), s);
+  const bool prof = B.prof;
+  B.prof = false;
+  best_ms = 1e300;
+  for (const TuneCfg& c : tune_candidates(B.d)) {
+    set_cfg(B, c);
+    const double ms = time_apply<T>(B, ptr<T>(u), ptr<T>(y), nb, std::max(1, reps), s);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  B.prof = prof;
+  set_cfg(B, best);
+  SGDG_CHECK_HIP(hipStreamSynchronize(s));
+  tune_store(key, best, best_ms);
+  r = {best.variant, best.bc, best.xbox, best_ms, 0};
+  return r;
+}
+
 // ================================================================== ABI ===
 extern "C" sgdg_status sgdg_apply_operator(sgdg_ops o, int kind_, const void* u_dev, void* y_dev, sgdg_dtype t,
                                            int batch, hipStream_t s) {
@@ -1192,7 +1318,7 @@ extern "C" sgdg_status sgdg_profile(sgdg_ops o, int mode) {
   Batch& B = self_batch(o);
   drain_events(B);
   if (mode == 1)
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < Batch::kSlots; ++i) {
       B.prof_ms[i] = 0;
       B.prof_n[i] = 0;
     }
@@ -1202,7 +1328,7 @@ extern "C" sgdg_status sgdg_profile(sgdg_ops o, int mode) {
 
 extern "C" sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launches) {
   API_BEGIN
-  require(o != nullptr && slot >= 0 && slot < 3, "bad slot");
+  require(o != nullptr && slot >= 0 && slot < Batch::kSlots, "bad slot");
   Batch& B = self_batch(o);
   drain_events(B);
   if (ms) *ms = B.prof_ms[slot];
@@ -1223,5 +1349,28 @@ extern "C" sgdg_status sgdg_op_info(sgdg_ops o, int kind_, int* nterms, int* nvg
   if (Sv) *Sv = o->dv.d.S;
   if (Rin) *Rin = op.Rin;
   if (Rout) *Rout = op.Rout;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_tune(sgdg_ops o, sgdg_dtype t, int batch, int reps, int force, sgdg_tune_result* out,
+                                 hipStream_t s) {
+  API_BEGIN
+  require(o != nullptr && batch >= 1 && reps >= 1, "bad arguments");
+  require(t == SGDG_F64 || t == SGDG_F32, "dtype must be F64 or F32");
+  Batch& B = self_batch(o);
+  const sgdg_tune_result r = t == SGDG_F64 ? tune<double>(B, batch, reps, force != 0, s)
+                                           : tune<float>(B, batch, reps, force != 0, s);
+  if (out) *out = r;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int force, sgdg_tune_result* out,
+                                       hipStream_t s) {
+  API_BEGIN
+  require(b != nullptr && reps >= 1, "bad arguments");
+  require(t == SGDG_F64 || t == SGDG_F32, "dtype must be F64 or F32");
+  const sgdg_tune_result r = t == SGDG_F64 ? tune<double>(*b, 1, reps, force != 0, s)
+                                           : tune<float>(*b, 1, reps, force != 0, s);
+  if (out) *out = r;
   API_END
 }

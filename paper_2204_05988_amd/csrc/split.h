@@ -1,15 +1,16 @@
-// Split (two-pass streaming) operator application (device code in split.hip).
+// Split (multi-pass streaming) operator application (device code in split.hip).
 #pragma once
 
 #include "batch.h"
 
 namespace sgdg {
 
-// y = A u for every problem and vector of the call: v-stencil stage into C.Z,
-// then x-stencils and upper-partner terms into C.y (the scans must have run).
+// One pass of y = A u for every problem and vector of the call (the scans must
+// have run): stage 0 writes the v-stage W into C.Z, stage 1 writes the
+// upper-partner part into C.y, stage 2 adds the x-stencils of W to C.y.
 // bc: vectors per thread (1, 2 or 4 for d <= 2; 1 for d = 3)
 template <class T>
-void split_apply(const SplitCall<T>& C, int d, int R, int bc, hipStream_t s);
+void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s);
 int split_points_per_item();
 int split_default_bc(int d);
 

@@ -1,20 +1,22 @@
 // Split operator application for gfx950: two streaming passes over the points
-// of every upper grid, with the v-stencil stage kept in HBM between them.
+// of every upper grid, with a v-stage kept in HBM between them.
 //
-// With V-groups j (terms sharing a v-factor) and X-groups m (terms sharing an
-// x-factor), the block row of upper grid i is (Sect. 4.2, with the embedding
+// With X-groups m (terms sharing an x-factor X_m) and the V-group j(k) of each
+// term, the block row of upper grid i is (Sect. 4.2, with the embedding
 // identities X_{l,l'} = X_l E_{l<-l'} below and E_{l'<-l}^T X_{l'} above):
 //
-//   y_i = sum_k Tm_k (X_k (x) I) Z_i^{j(k)} + sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt_i^{m(k)}
-//   Z_i^j = (I (x) V_j) u_i + (E^x (x) I) Pt_i^j
+//   y_i = sum_m (X_m (x) I) W_i^m + sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt_i^{m(k)}
+//   W_i^m = sum_{k in m} Tm_k [ (I (x) V_k) u_i + (E^x (x) I) Pt_i^{j(k)} ]
 //
-// Pass 1 (k_vstage) computes Z for every group: the v-stencil of u (v is the
-// fastest axis, so the 2^d-neighbour gathers stay in L1/L2) plus the x-prolonged
-// lower-partner scan array.  Pass 2 (k_xstage) applies the x-stencils of the
-// terms to Z (rows x +- 1 are nv apart: one coalesced row per neighbour) and
-// adds the upper-partner part, prolonging Qt in v on the fly.  One thread owns
-// one point and BC vectors of the batch; the stencil indices, parent tables
-// and factor values of its point are loaded once and reused across them.
+// Pass 1 (k_vstage) computes W for every X-group: the v-stencils of u (v is
+// the fastest axis, so the neighbour gathers stay in L1/L2), the x-prolonged
+// lower-partner scan arrays and the time-block mixing.  Pass 2 (k_xstage)
+// applies one x-stencil per X-group to W (rows x +- 1 are nv apart: one
+// coalesced row per neighbour) and adds the upper-partner part, prolonging Qt
+// in v on the fly.  Grouping by x-factor makes the number of staged arrays and
+// of x-stencil passes the number of distinct x-factors.  One thread owns one
+// point and BC vectors of the batch; the stencil indices, parent tables and
+// factor values of its point are loaded once and reused across them.
 #include <hip/hip_runtime.h>
 
 #include "split.h"
@@ -46,6 +48,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
   const int lx = A.G.lx[g], lv = A.G.lv[g];
   const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
+  const DevOp& op = A.op;
   int32_t nbv[SS];
 #pragma unroll
   for (int e = 0; e < SS; ++e) nbv[e] = A.DV.tnbr[vlo + int64_t(e) * nv + v];
@@ -65,6 +68,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const int64_t total = A.G.off[A.G.n];
   const int64_t ltotal = A.Gl.off[A.Gl.n];
   const T* vv = vals<T>(A.DV);
+  const T* tm = tmat<T>(op);
   T un[BC][R][SS];
 #pragma unroll
   for (int q = 0; q < BC; ++q) {
@@ -75,31 +79,54 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 #pragma unroll
       for (int e = 0; e < SS; ++e) un[q][s][e] = ub[int64_t(s) * plane + nbv[e]];
   }
-  for (int j = 0; j < A.op.nvg; ++j) {
-    const T* f = vv + int64_t(A.op.vg_fac[j]) * A.DV.fac_stride + vlo + v;
-    T fv[SS];
+  for (int m = 0; m < op.nxg; ++m) {
+    T w[BC][R];
 #pragma unroll
-    for (int e = 0; e < SS; ++e) fv[e] = f[int64_t(e) * nv];
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int s = 0; s < R; ++s) w[q][s] = T(0);
+    for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
+      const int k = op.xg_terms[kk];
+      const T* f = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
+      T fv[SS];
+#pragma unroll
+      for (int e = 0; e < SS; ++e) fv[e] = f[int64_t(e) * nv];
+      const T* tk = tm + int64_t(k) * R * R;
+      T tkv[R * R];
+#pragma unroll
+      for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
+      const int j = op.term_vg[k];
+#pragma unroll
+      for (int q = 0; q < BC; ++q) {
+        const int b = b0 + q < C.B ? b0 + q : b0;
+        const T* pt = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v;
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) {
+          T z = T(0);
+#pragma unroll
+          for (int e = 0; e < SS; ++e) z += fv[e] * un[q][s2][e];
+          if (has_p)
+            z += wx0 * pt[int64_t(s2) * lplane + int64_t(px0) * nv] + wx1 * pt[int64_t(s2) * lplane + int64_t(px1) * nv];
+#pragma unroll
+          for (int s = 0; s < R; ++s) w[q][s] += tkv[s * R + s2] * z;
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q;
       if (b >= C.B) break;
-      T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(j) * total + A.G.off[g] + p;
-      const T* pt = has_p ? C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v : nullptr;
+      T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p;
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        T z = T(0);
-#pragma unroll
-        for (int e = 0; e < SS; ++e) z += fv[e] * un[q][s][e];
-        if (has_p) z += wx0 * pt[int64_t(s) * lplane + int64_t(px0) * nv] + wx1 * pt[int64_t(s) * lplane + int64_t(px1) * nv];
-        zb[int64_t(s) * plane] = z;
-      }
+      for (int s = 0; s < R; ++s) zb[int64_t(s) * plane] = w[q][s];
     }
   }
 }
 
+// Pass 1b: y = upper-partner part sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt^{m(k)}
+// (zero for grids without an upper partner); pass 2 then adds the x-stencils.
 template <class T, int D, int R, int BC>
-__global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
+__global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
   const SplitItem it = C.items[blockIdx.x];
   const int b0 = int(blockIdx.y) * BC;
@@ -110,56 +137,16 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   const int64_t p = it.p0 + threadIdx.x;
   if (p >= plane) return;
   const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
-  const int lx = A.G.lx[g], lv = A.G.lv[g];
-  const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
+  const int lv = A.G.lv[g];
   const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
   const DevOp& op = A.op;
-  const T* xv = vals<T>(A.DX);
   const T* vv = vals<T>(A.DV);
   const T* tm = tmat<T>(op);
-  const int64_t total = A.G.off[A.G.n];
-  int32_t nbx[SS];
-#pragma unroll
-  for (int e = 0; e < SS; ++e) nbx[e] = A.DX.tnbr[xlo + int64_t(e) * nx + x];
   T acc[BC][R];
 #pragma unroll
   for (int q = 0; q < BC; ++q)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
-  // diagonal + lower partners: x-stencils of the staged Z
-  for (int j = 0; j < op.nvg; ++j) {
-    T z[BC][R][SS];
-#pragma unroll
-    for (int q = 0; q < BC; ++q) {
-      const int b = b0 + q < C.B ? b0 + q : b0;
-      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(j) * total + A.G.off[g] + v;
-#pragma unroll
-      for (int s = 0; s < R; ++s)
-#pragma unroll
-        for (int e = 0; e < SS; ++e) z[q][s][e] = zb[int64_t(s) * plane + int64_t(nbx[e]) * nv];
-    }
-    for (int kk = op.vg_start[j]; kk < op.vg_start[j + 1]; ++kk) {
-      const int k = op.vg_terms[kk];
-      const T* f = xv + int64_t(op.term_xf[k]) * A.DX.fac_stride + xlo + x;
-      T xf[SS];
-#pragma unroll
-      for (int e = 0; e < SS; ++e) xf[e] = f[int64_t(e) * nx];
-      const T* tk = tm + int64_t(k) * R * R;
-      T tkv[R * R];
-#pragma unroll
-      for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
-#pragma unroll
-      for (int q = 0; q < BC; ++q)
-#pragma unroll
-        for (int s2 = 0; s2 < R; ++s2) {
-          T t = T(0);
-#pragma unroll
-          for (int e = 0; e < SS; ++e) t += xf[e] * z[q][s2][e];
-#pragma unroll
-          for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
-        }
-    }
-  }
   // upper partners: v-stencils of the v-prolonged Qt
   const bool has_q = !A.diag_only && g + 1 < A.G.n;
   if (has_q) {
@@ -223,23 +210,77 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   }
 }
 
+template <class T, int D, int R, int BC>
+__global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  const SplitItem it = C.items[blockIdx.x];
+  const int b0 = int(blockIdx.y) * BC;
+  const ProbDesc& A = C.descs[it.prob];
+  const int g = it.grid;
+  const int nx = A.G.nx[g], nv = A.G.nv[g];
+  const int64_t plane = int64_t(nx) * nv;
+  const int64_t p = it.p0 + threadIdx.x;
+  if (p >= plane) return;
+  const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
+  const int lx = A.G.lx[g];
+  const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
+  const DevOp& op = A.op;
+  const T* xv = vals<T>(A.DX);
+  const int64_t total = A.G.off[A.G.n];
+  int32_t nbx[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) nbx[e] = A.DX.tnbr[xlo + int64_t(e) * nx + x];
+  T acc[BC][R];
+#pragma unroll
+  for (int q = 0; q < BC; ++q)
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[q][s] = T(0);
+  // diagonal + lower partners: one x-stencil per X-group on the staged W
+  for (int m = 0; m < op.nxg; ++m) {
+    const T* f = xv + int64_t(op.xg_fac[m]) * A.DX.fac_stride + xlo + x;
+    T xf[SS];
+#pragma unroll
+    for (int e = 0; e < SS; ++e) xf[e] = f[int64_t(e) * nx];
+#pragma unroll
+    for (int q = 0; q < BC; ++q) {
+      const int b = b0 + q < C.B ? b0 + q : b0;
+      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + v;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        T t = T(0);
+#pragma unroll
+        for (int e = 0; e < SS; ++e) t += xf[e] * zb[int64_t(s) * plane + int64_t(nbx[e]) * nv];
+        acc[q][s] += t;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < BC; ++q) {
+    const int b = b0 + q;
+    if (b >= C.B) break;
+    T* yb = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(R) * A.poff[g] + p;
+#pragma unroll
+    for (int s = 0; s < R; ++s) yb[int64_t(s) * plane] += acc[q][s];  // after the upper-partner pass
+  }
+}
+
 }  // namespace
 
 int split_points_per_item() { return kSB; }
 int split_default_bc(int d) { return d == 3 ? 1 : 2; }
 
 template <class T>
-void split_apply(const SplitCall<T>& C, int d, int R, int bc, hipStream_t s) {
+void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s) {
   if (C.nitems == 0) return;
   if (d == 3 || (bc != 1 && bc != 2 && bc != 4)) bc = d == 3 ? 1 : 2;
   dim3 grid(unsigned(C.nitems), unsigned((C.B + bc - 1) / bc));
-#define SGDG_SPLIT_CASE(DD, RR, BB)                                                   \
-  if (d == DD && R == RR && bc == BB) {                                               \
-    hipLaunchKernelGGL((k_vstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);          \
-    SGDG_CHECK_HIP(hipGetLastError());                                                \
-    hipLaunchKernelGGL((k_xstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);          \
-    SGDG_CHECK_HIP(hipGetLastError());                                                \
-    return;                                                                           \
+#define SGDG_SPLIT_CASE(DD, RR, BB)                                                                 \
+  if (d == DD && R == RR && bc == BB) {                                                             \
+    if (stage == 0) hipLaunchKernelGGL((k_vstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);        \
+    else if (stage == 1) hipLaunchKernelGGL((k_ustage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);   \
+    else hipLaunchKernelGGL((k_xstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);                   \
+    SGDG_CHECK_HIP(hipGetLastError());                                                              \
+    return;                                                                                         \
   }
 #define SGDG_SPLIT_R(DD, BB) SGDG_SPLIT_CASE(DD, 1, BB) SGDG_SPLIT_CASE(DD, 2, BB) SGDG_SPLIT_CASE(DD, 3, BB)
   SGDG_SPLIT_R(1, 1) SGDG_SPLIT_R(1, 2) SGDG_SPLIT_R(1, 4)
@@ -250,7 +291,7 @@ void split_apply(const SplitCall<T>& C, int d, int R, int bc, hipStream_t s) {
   throw Error{SGDG_E_ARG, "unsupported dimension or time degree"};
 }
 
-template void split_apply<double>(const SplitCall<double>&, int, int, int, hipStream_t);
-template void split_apply<float>(const SplitCall<float>&, int, int, int, hipStream_t);
+template void split_stage<double>(const SplitCall<double>&, int, int, int, int, hipStream_t);
+template void split_stage<float>(const SplitCall<float>&, int, int, int, int, hipStream_t);
 
 }  // namespace sgdg

@@ -26,7 +26,7 @@ EXPORTS = [
     "sgdg_batch_create", "sgdg_batch_layout", "sgdg_batch_apply", "sgdg_batch_solve", "sgdg_batch_destroy",
     "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
-    "sgdg_net_backward", "sgdg_net_destroy",
+    "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune",
 ]
 
 
@@ -65,6 +65,15 @@ class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("refinement_steps", C.c_int), ("inner_iters_total", C.c_int),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("fallback_used", C.c_int),
                 ("pc_applications", C.c_int)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("variant", C.c_int), ("vectors_per_thread", C.c_int), ("xbox", C.c_int), ("ms", C.c_double),
+                ("from_cache", C.c_int)]
+
+    def as_dict(self):
+        return {"variant": "split" if self.variant == 0 else "fused", "vectors_per_thread": self.vectors_per_thread,
+                "xbox": self.xbox, "ms": self.ms, "from_cache": bool(self.from_cache)}
 
 
 class TrainOpts(C.Structure):
@@ -125,6 +134,8 @@ def lib():
     L.sgdg_net_backward.argtypes = [vp, vp, vp, vp, vp]
     L.sgdg_net_destroy.argtypes = [vp]
     L.sgdg_net_destroy.restype = None
+    L.sgdg_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
+    L.sgdg_batch_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
     for name in EXPORTS:
         if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy",
                         "sgdg_net_destroy"):
@@ -302,6 +313,13 @@ class SparseGridOps:
         _check(lib().sgdg_op_info(self.ops, kind, *[C.byref(x) for x in v]))
         return dict(zip(["nterms", "nvg", "nxg", "Sx", "Sv", "Rin", "Rout"], [x.value for x in v]))
 
+    def tune(self, dtype="f64", batch=1, reps=3, force=False, stream=None):
+        """Pick the fastest launch configuration of the full apply (cached on disk)."""
+        r = TuneResult()
+        _check(lib().sgdg_tune(self.ops, F64 if dtype == "f64" else F32, batch, reps, int(force), C.byref(r),
+                               _stream(stream)))
+        return r.as_dict()
+
     def solve_strip(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
         o = opts or default_solve_opts()
         st = SolveStats()
@@ -335,6 +353,12 @@ class SparseGridBatch:
         assert u.numel() == self.ndof and y.numel() == self.ndof, "shape mismatch"
         _check(lib().sgdg_batch_apply(self.h, _ptr(u), _ptr(y), dt, _stream(stream)))
         return y
+
+    def tune(self, dtype="f64", reps=3, force=False, stream=None):
+        r = TuneResult()
+        _check(lib().sgdg_batch_tune(self.h, F64 if dtype == "f64" else F32, reps, int(force), C.byref(r),
+                                     _stream(stream)))
+        return r.as_dict()
 
     def solve(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
         assert b.numel() == self.ndof and u.numel() == self.ndof
