@@ -340,6 +340,10 @@ sgdg_status sgdg_tune(sgdg_ops o, sgdg_dtype t, int batch, int reps, int force, 
                       hipStream_t s);
 /* The same for a multi-problem batch (one vector per problem). */
 sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int force, sgdg_tune_result* out, hipStream_t s);
+/* Sets the launch configuration directly (variant 0: vectors_per_thread in
+ * {1, 2, 4}, 1 for d = 3; variant 1: xbox >= 1, shrunk to the LDS budget).
+ * SGDG_E_ARG on other values.  ms and from_cache are ignored. */
+sgdg_status sgdg_set_launch(sgdg_ops o, const sgdg_tune_result* cfg);
 
 /* ------------------------------------------------------------ diagnostics -- */
 

@@ -50,7 +50,7 @@ struct FusedCall {
   const FusedItem* items;
   const ScanItem* sitems;
   int nitems;
-  int max_stage, max_tab;  // LDS elements / ints per block
+  int max_u, max_stage, max_tab;  // LDS elements (u halo box, group stage) / ints per block
   int B;                   // vectors per problem
   int64_t u_bstride, y_bstride, pt_bstride, qt_bstride;  // batch strides
   const T* u;

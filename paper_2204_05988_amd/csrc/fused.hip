@@ -62,6 +62,8 @@ __device__ __forceinline__ int node_of(const int* c, int m, int periodic_cells) 
   return p;
 }
 
+// LDS of a block: U (the item's u values on the x-halo box times the v-halo
+// box, all slices) | the group stage | index tables.
 // Per-block index tables live in LDS after the staging area:
 //   xh_node[nxh]  x node of each halo row (-1 outside a non-periodic lattice)
 //   xb_halo[nxb]  halo row of each box row;  xb_node[nxb] x node of each box row
@@ -106,8 +108,10 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
   }
   const bool has_p = !A.diag_only && g > 0;
   const bool has_q = !A.diag_only && g + 1 < G.n;
+  T* U = lds;                    // [R][nxh][nvh]
+  T* stg = lds + C.max_u;        // group stage
   // index tables
-  int* tab = reinterpret_cast<int*>(lds + C.max_stage);
+  int* tab = reinterpret_cast<int*>(lds + C.max_u + C.max_stage);
   int* xh_node = tab;
   int* xb_halo = xh_node + nxh;
   int* xb_node = xb_halo + nxb;
@@ -145,14 +149,13 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
     vb_halo[i] = h;
     vb_node[i] = node_of<D>(c, mv, 0);
   }
-  if (has_q)
-    for (int i = threadIdx.x; i < nvh; i += kFB) {
-      int c[3];
-      unflat<D>(i, vh, c);
+  for (int i = threadIdx.x; i < nvh; i += kFB) {
+    int c[3];
+    unflat<D>(i, vh, c);
 #pragma unroll
-      for (int a = 0; a < D; ++a) c[a] += it.vb[a] - 1;
-      vh_node[i] = node_of<D>(c, mv, pcv);
-    }
+    for (int a = 0; a < D; ++a) c[a] += it.vb[a] - 1;
+    vh_node[i] = node_of<D>(c, mv, pcv);
+  }
   // halo offsets of the stencil slots
   int dxh[SS], dvh[SS];
 #pragma unroll
@@ -167,6 +170,17 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
     dvh[e] = ov;
   }
   __syncthreads();
+  // stage u on the halo boxes once (zero outside the lattices)
+  {
+    const int nhh = nxh * nvh;
+    for (int i = threadIdx.x; i < R * nhh; i += kFB) {
+      const int s = i / nhh, rem = i - s * nhh;
+      const int r = rem / nvh, c = rem - r * nvh;
+      const int xn = xh_node[r], vn = vh_node[c];
+      U[i] = (xn >= 0 && vn >= 0) ? ug[int64_t(s) * plane + int64_t(xn) * nv + vn] : T(0);
+    }
+  }
+  __syncthreads();
 
   const int nrg = kFB / nvb;            // row groups (nvb <= kFB)
   const int col = threadIdx.x % nvb;
@@ -179,9 +193,6 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
   const T* tm = tmx<T>(op);
   const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
   const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
-  int32_t nbv[SS];
-#pragma unroll
-  for (int e = 0; e < SS; ++e) nbv[e] = active ? A.DV.nbr[vlo + int64_t(vi) * SV + e] : 0;
 
   T acc[kRows][R];
 #pragma unroll
@@ -208,9 +219,9 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
         for (int s = 0; s < R; ++s) {
           T z = T(0);
           if (xi >= 0) {
-            const T* urow = ug + int64_t(s) * plane + int64_t(xi) * nv;
+            const T* urow = U + (s * nxh + r) * nvh + vhc;
 #pragma unroll
-            for (int e = 0; e < SS; ++e) z += fvv[e] * urow[nbv[e]];
+            for (int e = 0; e < SS; ++e) z += fvv[e] * urow[dvh[e]];
             if (has_p) {
               const int64_t pp = po + 2 * int64_t(xi);
               const T* pr = pt + int64_t(s) * lplane;
@@ -218,7 +229,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
                    T(A.DX.parw[pp + 1]) * pr[int64_t(A.DX.par[pp + 1]) * nv];
             }
           }
-          lds[(s * nxh + r) * nvb + col] = z;
+          stg[(s * nxh + r) * nvb + col] = z;
         }
       }
     }
@@ -234,7 +245,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
 #pragma unroll
         for (int s2 = 0; s2 < R; ++s2) {
           // staged values of the x-neighbourhood, shared by every term of the group
-          const T* l = lds + (s2 * nxh + hb) * nvb + col;
+          const T* l = stg + (s2 * nxh + hb) * nvb + col;
           T z[SS];
 #pragma unroll
           for (int e = 0; e < SS; ++e) z[e] = l[dxh[e] * nvb];
@@ -274,7 +285,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
             const T* qr = qt + int64_t(s) * qplane + int64_t(xi) * nvl;
             z = T(A.DV.parw[pp]) * qr[A.DV.par[pp]] + T(A.DV.parw[pp + 1]) * qr[A.DV.par[pp + 1]];
           }
-          lds[(s * nxb + r) * nvh + c] = z;
+          stg[(s * nxb + r) * nvh + c] = z;
         }
       }
       __syncthreads();
@@ -292,7 +303,7 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
             if (r >= nxb) break;
 #pragma unroll
             for (int s2 = 0; s2 < R; ++s2) {
-              const T* l = lds + (s2 * nxb + r) * nvh + vhc;
+              const T* l = stg + (s2 * nxb + r) * nvh + vhc;
               T t = T(0);
 #pragma unroll
               for (int e = 0; e < SS; ++e) t += fvv[e] * l[dvh[e]];
@@ -490,7 +501,8 @@ void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, hipStream
 
 template <class T>
 void fused_tiles(const FusedCall<T>& C, int d, int R, hipStream_t s) {
-  const size_t sm = size_t(C.max_stage) * sizeof(T) + size_t(C.max_tab) * sizeof(int);
+  const size_t sm = size_t(C.max_u + C.max_stage) * sizeof(T) + size_t(C.max_tab) * sizeof(int);
+  if (sm > 64 * 1024) throw Error{SGDG_E_ARG, "box tiles exceed the LDS budget"};
   dim3 grid(unsigned(C.nitems), C.B);
 #define SGDG_FUSED_CASE(DD, RR) \
   if (d == DD && R == RR) hipLaunchKernelGGL((k_fused<T, DD, RR>), grid, dim3(kFB), sm, s, C);

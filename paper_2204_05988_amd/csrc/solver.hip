@@ -28,7 +28,7 @@ struct SegTab {
 
 struct Items {
   DevBuf items, sitems;
-  int n = 0, max_stage = 0, max_tab = 0;
+  int n = 0, max_u = 0, max_stage = 0, max_tab = 0;
   std::vector<int> step_first, step_count;
   bool built = false;
 };
@@ -215,7 +215,7 @@ static KindData& kind(Batch& B, int k) {
 // under the per-thread row limit and a bounded LDS stage.
 static void choose_boxes(int d, int bx, int mx, int mv, int R, int elem, int* xs, int* vs) {
   const int nthr = fused_threads(), rows = fused_rows_per_thread();
-  const size_t lds_cap = 60 * 1024;
+  const size_t lds_cap = 64 * 1024;
   for (int a = 0; a < 3; ++a) {
     xs[a] = a < d ? std::min(bx, mx) : 1;
     vs[a] = 1;
@@ -231,9 +231,18 @@ static void choose_boxes(int d, int bx, int mx, int mv, int R, int elem, int* xs
     if (nvb > size_t(nthr)) return false;
     if (nx > size_t(rows) * (nthr / nvb)) return false;
     const size_t st = std::max(nxh * nvb, nx * nvh) * size_t(R) * elem;
+    const size_t uh = nxh * nvh * size_t(R) * elem;  // u on the halo boxes
     const size_t tab = (nxh + 2 * nx + 2 * nvb + nvh) * sizeof(int);
-    return st + tab <= lds_cap;
+    return uh + st + tab <= lds_cap;
   };
+  const int one[3] = {1, 1, 1};
+  while (!fits(one)) {  // shrink the x-box until the smallest v-box fits
+    int a = 0;
+    for (int c = 1; c < d; ++c)
+      if (xs[c] > xs[a]) a = c;
+    if (xs[a] <= 1) throw Error{SGDG_E_ARG, "no box shape fits the LDS budget"};
+    xs[a] = (xs[a] + 1) / 2;
+  }
   bool grew = true;
   while (grew) {
     grew = false;
@@ -257,7 +266,7 @@ static Items& items(Batch& B, int k, int elem) {
   if (I.built) return I;
   const int bx = B.xbox[elem == 8 ? 0 : 1] > 0 ? B.xbox[elem == 8 ? 0 : 1] : default_xbox(B.d);
   std::vector<FusedItem> its;
-  int64_t max_stage = 1, max_tab = 1;
+  int64_t max_stage = 1, max_tab = 1, max_u = 1;
   int maxn = 0;
   for (size_t p = 0; p < B.P.size(); ++p) {
     const ProbDesc& D = K.host[p];
@@ -278,6 +287,7 @@ static Items& items(Batch& B, int k, int elem) {
         nv_h *= vs[a] + 2;
       }
       max_stage = std::max<int64_t>(max_stage, std::max(nx_h * nv_b, nx_b * nv_h) * K.R);
+      max_u = std::max<int64_t>(max_u, nx_h * nv_h * K.R);
       max_tab = std::max<int64_t>(max_tab, nx_h + 2 * nx_b + 2 * nv_b + nv_h);
       for (int i0 = 0; i0 < nbx[0]; ++i0)
         for (int i1 = 0; i1 < nbx[1]; ++i1)
@@ -302,6 +312,7 @@ static Items& items(Batch& B, int k, int elem) {
   upload(I.items, its);
   I.n = int(its.size());
   I.max_stage = int(max_stage);
+  I.max_u = int(max_u);
   I.max_tab = int(max_tab);
   // scan work: one table per step, all problems
   std::vector<ScanItem> sits;
@@ -338,6 +349,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   C.sitems = ptr<ScanItem>(I.sitems);
   C.nitems = I.n;
   C.max_stage = I.max_stage;
+  C.max_u = I.max_u;
   C.max_tab = I.max_tab;
   C.B = nb;
   C.u_bstride = C.y_bstride = K.total;
@@ -1372,5 +1384,20 @@ extern "C" sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int
   const sgdg_tune_result r = t == SGDG_F64 ? tune<double>(*b, 1, reps, force != 0, s)
                                            : tune<float>(*b, 1, reps, force != 0, s);
   if (out) *out = r;
+  API_END
+}
+
+extern "C" sgdg_status sgdg_set_launch(sgdg_ops o, const sgdg_tune_result* cfg) {
+  API_BEGIN
+  require(o != nullptr && cfg != nullptr, "null argument");
+  require(cfg->variant == 0 || cfg->variant == 1, "variant must be 0 (split) or 1 (fused)");
+  Batch& B = self_batch(o);
+  if (cfg->variant == 0)
+    require(cfg->vectors_per_thread == 1 || (B.d < 3 && (cfg->vectors_per_thread == 2 || cfg->vectors_per_thread == 4)),
+            "vectors_per_thread must be 1, 2 or 4 (1 for d = 3)");
+  else
+    require(cfg->xbox >= 1 && cfg->xbox <= 256, "xbox must be 1..256");
+  set_cfg(B, TuneCfg{cfg->variant, cfg->variant == 0 ? cfg->vectors_per_thread : 0,
+                     cfg->variant == 1 ? cfg->xbox : B.xbox[0]});
   API_END
 }

@@ -26,7 +26,7 @@ EXPORTS = [
     "sgdg_batch_create", "sgdg_batch_layout", "sgdg_batch_apply", "sgdg_batch_solve", "sgdg_batch_destroy",
     "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
-    "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune",
+    "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune", "sgdg_set_launch",
 ]
 
 
@@ -136,6 +136,7 @@ def lib():
     L.sgdg_net_destroy.restype = None
     L.sgdg_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
     L.sgdg_batch_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
+    L.sgdg_set_launch.argtypes = [vp, C.POINTER(TuneResult)]
     for name in EXPORTS:
         if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy",
                         "sgdg_net_destroy"):
@@ -319,6 +320,10 @@ class SparseGridOps:
         _check(lib().sgdg_tune(self.ops, F64 if dtype == "f64" else F32, batch, reps, int(force), C.byref(r),
                                _stream(stream)))
         return r.as_dict()
+
+    def set_launch(self, variant="split", vectors_per_thread=2, xbox=8):
+        r = TuneResult(0 if variant == "split" else 1, vectors_per_thread, xbox, 0.0, 0)
+        _check(lib().sgdg_set_launch(self.ops, C.byref(r)))
 
     def solve_strip(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
         o = opts or default_solve_opts()

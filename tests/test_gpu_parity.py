@@ -103,6 +103,37 @@ def test_apply_parity(dev, case, kind):
         assert err32 <= 2e-5, err32
 
 
+LAUNCHES = [("split", 1, 8), ("split", 2, 8), ("split", 4, 8), ("fused", 0, 4), ("fused", 0, 8), ("fused", 0, 16)]
+
+
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1p", "tiny_d2", "tiny_d3", "c1", "c2_L5", "c5_L5"])
+@pytest.mark.parametrize("launch", LAUNCHES, ids=lambda l: f"{l[0]}{l[1] if l[0] == 'split' else l[2]}")
+def test_apply_launch_configs(dev, case, launch):
+    """Every launch configuration the tuner may pick computes the same operator (FP64 and FP32, batch 3)."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem(case, CASES[case])
+    variant, bc, xb = launch
+    if variant == "split" and w.d == 3 and bc != 1:
+        pytest.skip("d = 3 runs one vector per thread")
+    ops.set_launch(variant, bc, xb)
+    try:
+        B = 3
+        u = random_vector(P.ndof, 31, batch=B)
+        ut = torch.tensor(u, device=dev)
+        yt = torch.empty_like(ut)
+        _say(f"apply {case} {launch}")
+        ops.apply(ut, yt, batch=B)
+        y32 = torch.empty(ut.shape, dtype=torch.float32, device=dev)
+        ops.apply(ut.float(), y32, batch=B)
+        torch.cuda.synchronize()
+        for b in range(B):
+            ref = P.apply(u[b])
+            assert _rel(yt[b].cpu().numpy(), ref) <= 1e-10
+            assert _rel(y32[b].double().cpu().numpy(), ref) <= 2e-5
+    finally:
+        ops.set_launch("split", 1 if w.d == 3 else 2, 8)
+
+
 def test_apply_batch_equals_single(dev):
     w, P, ops = _problem("c2_L5", CASES["c2_L5"])
     B = 3
