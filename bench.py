@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
+    ap.add_argument("--c3-level", type=int, default=6, help="level of the 6D apply leg (0 = skip)")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calib-copy", action="store_true",
@@ -209,6 +210,8 @@ def main():
         out["learned"] = learned_leg(dev, a.train_steps)
     if a.batched > 0:
         out["batched"] = batched_leg(dev, a.batched)
+    if a.c3_level > 0:
+        out["apply_6d"] = apply_6d_leg(dev, a.c3_level)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, value)
     print(json.dumps(out), flush=True)
@@ -314,6 +317,35 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
         _log(f"learned leg: {row}")
         u = x
     net.close()
+    ops.close()
+    return out
+
+
+def apply_6d_leg(dev, L, steps=5):
+    """Operator-apply throughput of the 6D phase-space problem (d=3, r=0), one vector, FP64 and FP32."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c3, random_vector
+    w = config_c3(L=L)
+    t0 = time.perf_counter()
+    ops = sgdg.SparseGridOps(w)
+    setup = time.perf_counter() - t0
+    _log(f"6d leg: L={L}, {ops.ndof} DOFs, assembled in {setup:.1f}s")
+    out = {"workload": f"6D phase space d=3, r=0, sparse grid L={L} (c3), full SD-DG operator", "dofs": ops.ndof,
+           "grids": len(ops.upper), "setup_s": round(setup, 2)}
+    u64 = torch.tensor(random_vector(ops.ndof, 0)[0], device=dev)
+    for name, u in (("f64", u64), ("f32", u64.float())):
+        tuned = ops.tune(name, batch=1, reps=2)
+        y = torch.empty_like(u)
+        ops.apply(u, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ops.apply(u, y)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[name] = {"ms": round(el * 1e3, 3), "dof_applies_per_s": ops.ndof / el, "launch_config": tuned}
+        _log(f"6d leg: {name} {out[name]}")
     ops.close()
     return out
 

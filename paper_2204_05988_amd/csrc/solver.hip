@@ -215,7 +215,7 @@ static KindData& kind(Batch& B, int k) {
 // under the per-thread row limit and a bounded LDS stage.
 static void choose_boxes(int d, int bx, int mx, int mv, int R, int elem, int* xs, int* vs) {
   const int nthr = fused_threads(), rows = fused_rows_per_thread();
-  const size_t lds_cap = 64 * 1024;
+  const size_t lds_cap = 56 * 1024;  // per item; the launch sizes for the largest stage and halo over all items
   for (int a = 0; a < 3; ++a) {
     xs[a] = a < d ? std::min(bx, mx) : 1;
     vs[a] = 1;
@@ -1144,13 +1144,20 @@ static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t
   best_ms = 1e300;
   for (const TuneCfg& c : tune_candidates(B.d)) {
     set_cfg(B, c);
-    const double ms = time_apply<T>(B, ptr<T>(u), ptr<T>(y), nb, std::max(1, reps), s);
+    double ms = 0;
+    try {
+      ms = time_apply<T>(B, ptr<T>(u), ptr<T>(y), nb, std::max(1, reps), s);
+    } catch (const Error& e) {
+      if (e.code != SGDG_E_ARG) throw;
+      continue;  // configuration not available for these grids (e.g. beyond the LDS budget)
+    }
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
     }
   }
   B.prof = prof;
+  if (best_ms >= 1e300) throw Error{SGDG_E_STATE, "no launch configuration could run"};
   set_cfg(B, best);
   SGDG_CHECK_HIP(hipStreamSynchronize(s));
   tune_store(key, best, best_ms);
