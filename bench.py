@@ -63,7 +63,9 @@ def kernel_work(ops, B, R, elem_bytes):
       k_vstage  W^m = sum_{k in m} Tm_k [V_k u + E^x Pt^{j(k)}]:
                 flops nt R 2S + nt 2R^2 (+ nt R 4 if i > 0);
                 bytes u (R) + W (nxg R) [+ Pt (nt R / 2^d) if i > 0]
-      k_ustage  sum_k Tm_k V_k E^v Qt^{m(k)}, i < n-1 (zero fill otherwise):
+      k_ustage  sum_k Tm_k (V_k E^v) Qt^{m(k)}, i < n-1 (zero fill otherwise); d <= 2
+                with the prolongated stencils V_k E^v (3^d coarse nodes per fine node):
+                flops nt (R 2 3^d + 2R^2); d = 3 prolonging Qt on the fly:
                 flops nxg S R 4 + nt (R 2S + 2R^2); bytes Qt (nxg R / 2^d) + y (R)
       k_xstage  y += sum_m X_m W^m:  flops nxg R 2S; bytes W (nxg R) + y (2R)
       k_fused   the whole block row from LDS-staged boxes:
@@ -86,7 +88,8 @@ def kernel_work(ops, B, R, elem_bytes):
             work[k][1] += pts * by * elem_bytes
         add("vstage", nt * R * 2 * S + nt * 2 * R * R + (nt * R * 4 if hp else 0),
             R + nxg * R + (nt * R / 2 ** d if hp else 0))
-        add("ustage", (nxg * S * R * 4 + nt * (R * 2 * S + 2 * R * R)) if hq else 0,
+        uf = nt * (R * 2 * 3 ** d + 2 * R * R) if d <= 2 else nxg * S * R * 4 + nt * (R * 2 * S + 2 * R * R)
+        add("ustage", uf if hq else 0,
             (nxg * R / 2 ** d if hq else 0) + R)
         add("xstage", nxg * R * 2 * S, nxg * R + 2 * R)
         add("fused", nvg * R * (2 * S + 4) + nt * R * (2 * S + 2 * R) + ((nxg * R * 4 + nt * R * (2 * S + 2 * R)) if hq else 0),

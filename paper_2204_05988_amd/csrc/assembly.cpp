@@ -333,6 +333,82 @@ void restrict_factor(DomainData& D, int fid) {
   }
 }
 
+// Kuhn refinement: a fine node 2a + b (b in {0,1}^d) is the midpoint of the
+// coarse edge a -> a + b, so its parents are floor(q/2) and ceil(q/2) with
+// weights 1/2 each, or the single node q/2 when q is even.
+static int pro_slot(const int* q, const int* base, int d) {
+  int s = 0;
+  for (int a = d - 1; a >= 0; --a) s = s * 3 + (q[a] - base[a] + 1);
+  return s;
+}
+
+void build_prolong_tables(DomainData& D) {
+  const Dom& dom = D.dom;
+  const int d = dom.d;
+  int PW = 1;
+  for (int a = 0; a < d; ++a) PW *= 3;
+  D.pro_idx.assign(D.lmax - D.lmin + 1, {});
+  int q[3], base[3], c[3];
+  for (int l = D.lmin + 1; l <= D.lmax; ++l) {
+    const LevelTables& F = D.L(l);
+    const int mc = dom.axis_nodes(l - 1), nc = 1 << (l - 1);
+    auto& tab = D.pro_idx[l - D.lmin];
+    tab.assign(size_t(F.n) * PW, 0);
+    for (int64_t P = 0; P < F.n; ++P) {
+      unflat(P, d, F.m, q);
+      for (int a = 0; a < d; ++a) base[a] = q[a] >> 1;
+      for (int sl = 0; sl < PW; ++sl) {
+        int t = sl;
+        bool ok = true;
+        for (int a = 0; a < d; ++a) {
+          c[a] = base[a] + (t % 3) - 1;
+          t /= 3;
+          if (!dom.periodic && (c[a] < 0 || c[a] >= mc)) ok = false;
+        }
+        tab[size_t(sl) * F.n + P] = ok ? int32_t(flat_wrap(c, d, mc, dom.periodic, nc)) : 0;
+      }
+    }
+  }
+}
+
+void prolong_factor(DomainData& D, int fid) {
+  const Dom& dom = D.dom;
+  const int d = dom.d, S = D.st.S;
+  int PW = 1;
+  for (int a = 0; a < d; ++a) PW *= 3;
+  auto& out = D.pvalues[fid];
+  out.assign(D.lmax - D.lmin + 1, {});
+  int q[3], base[3], f[3], lo[3], hi[3];
+  for (int l = D.lmin + 1; l <= D.lmax; ++l) {
+    const LevelTables& F = D.L(l);
+    const auto& X = D.values[fid][l - D.lmin];
+    auto& r = out[l - D.lmin];
+    r.assign(size_t(F.n) * PW, 0.0);
+    for (int64_t P = 0; P < F.n; ++P) {
+      unflat(P, d, F.m, q);
+      for (int a = 0; a < d; ++a) base[a] = q[a] >> 1;
+      for (int e = 0; e < S; ++e) {
+        if (!F.valid[P * S + e]) continue;
+        const double xv = X[P * S + e];
+        if (xv == 0.0) continue;
+        bool even = true;
+        for (int a = 0; a < d; ++a) {
+          f[a] = q[a] + D.st.off[e][a];  // unwrapped fine neighbour
+          lo[a] = f[a] >> 1;             // arithmetic shift: floor for -1 too
+          hi[a] = (f[a] + 1) >> 1;
+          even = even && lo[a] == hi[a];
+        }
+        if (even) {
+          r[size_t(pro_slot(lo, base, d)) * F.n + P] += xv;
+        } else {
+          r[size_t(pro_slot(lo, base, d)) * F.n + P] += 0.5 * xv;
+          r[size_t(pro_slot(hi, base, d)) * F.n + P] += 0.5 * xv;
+        }
+      }
+    }
+  }
+}
+
 void assemble_factor(DomainData& D, int fid) {
   FactorKey key = D.factors[fid];
   const int nlev = D.lmax - D.lmin + 1;

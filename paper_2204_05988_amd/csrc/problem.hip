@@ -222,6 +222,31 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   for (size_t i = 0; i < trv.size(); ++i) trv32[i] = float(trv[i]);
   d.trvals = upload(dd.trvals, trv);
   d.trvals32 = upload(dd.trvals32, trv32);
+  // prolongated stencils (already slot-major per level)
+  int PW = 1;
+  for (int a = 0; a < D.dom.d; ++a) PW *= 3;
+  d.PW = PW;
+  std::vector<int32_t> pidx;
+  int64_t pof = 0;
+  for (int l = D.lmin; l <= D.lmax; ++l) {
+    d.plev_off[l - D.lmin] = pof;
+    const int64_t n = D.L(l).n;
+    if (l > D.lmin) pidx.insert(pidx.end(), D.pro_idx[l - D.lmin].begin(), D.pro_idx[l - D.lmin].end());
+    else pidx.insert(pidx.end(), size_t(n) * PW, 0);
+    pof += n * PW;
+  }
+  d.pidx = upload(dd.pidx, pidx);
+  d.pstride = pof;
+  std::vector<double> pv(nf * pof, 0.0);
+  for (size_t f = 0; f < nf; ++f)
+    for (int l = D.lmin + 1; l <= D.lmax; ++l) {
+      const auto& src = D.pvalues[f][l - D.lmin];
+      std::copy(src.begin(), src.end(), pv.begin() + f * pof + d.plev_off[l - D.lmin]);
+    }
+  std::vector<float> pv32(pv.size());
+  for (size_t i = 0; i < pv.size(); ++i) pv32[i] = float(pv[i]);
+  d.pvals = upload(dd.pvals, pv);
+  d.pvals32 = upload(dd.pvals32, pv32);
 }
 
 static void upload_op(OpDev& od) {
@@ -350,11 +375,14 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
     DomainData& D = side == 0 ? o->X : o->V;
     D.values.assign(D.factors.size(), {});
     D.rvalues.assign(D.factors.size(), {});
+    D.pvalues.assign(D.factors.size(), {});
     build_wide_tables(D);
+    build_prolong_tables(D);
 #pragma omp parallel for schedule(dynamic)
     for (int f = 0; f < int(D.factors.size()); ++f) {
       assemble_factor(D, f);
       restrict_factor(D, f);
+      prolong_factor(D, f);
     }
   }
   const int mfx = o->dx.d.mass_fac, mfv = o->dv.d.mass_fac;

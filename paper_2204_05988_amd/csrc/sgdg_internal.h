@@ -101,6 +101,11 @@ struct DomainData {
   std::vector<std::array<int, 3>> woff;
   std::vector<std::vector<int32_t>> wide_idx;             // [level-lmin][n*W] fine node index
   std::vector<std::vector<std::vector<double>>> rvalues;  // [factor][level-lmin][n*W]
+  // prolongated stencils X_l E_{l<-l-1}: fine node P of level l couples to the
+  // coarse nodes floor(P/2) + o, o in {-1,0,1}^d (3^d slots, slot-major per level);
+  // levels lmin+1..lmax
+  std::vector<std::vector<int32_t>> pro_idx;              // [level-lmin][slot*n + P] coarse node (0 if unused)
+  std::vector<std::vector<std::vector<double>>> pvalues;  // [factor][level-lmin][slot*n + P]
   int field_id(const double* src, int64_t n);
   int factor_id(const FactorKey& k);
   const LevelTables& L(int l) const { return lev[l - lmin]; }
@@ -122,6 +127,8 @@ void build_domain_tables(DomainData& D);
 void assemble_factor(DomainData& D, int fid);  // all levels of one factor
 void build_wide_tables(DomainData& D);          // woff and wide_idx
 void restrict_factor(DomainData& D, int fid);   // rvalues of one factor
+void build_prolong_tables(DomainData& D);       // pro_idx
+void prolong_factor(DomainData& D, int fid);    // pvalues of one factor
 struct ProblemIn {
   const sgdg_problem* p;
   int d, r;
@@ -158,6 +165,12 @@ struct DevDomain {
   const float* trvals32 = nullptr;
   const int32_t* tchi = nullptr;      // slot-major children [S][n] per level
   const double* tchiw = nullptr;
+  int PW = 0;                         // prolongated-stencil slots (3^d)
+  int64_t plev_off[kMaxLevels] = {};  // start of level l in the [PW][n] tables
+  const int32_t* pidx = nullptr;      // coarse node of each slot
+  const double* pvals = nullptr;      // [factor][levels [PW][n]] FP64
+  const float* pvals32 = nullptr;
+  int64_t pstride = 0;                // elements per factor
   int64_t rstride = 0;                // elements per factor
 };
 

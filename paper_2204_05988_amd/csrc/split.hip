@@ -30,6 +30,9 @@ constexpr int kSB = 256;  // threads (points) per block
 template <class T> __device__ __forceinline__ const T* vals(const DevDomain& D);
 template <> __device__ __forceinline__ const double* vals<double>(const DevDomain& D) { return D.tvals; }
 template <> __device__ __forceinline__ const float* vals<float>(const DevDomain& D) { return D.tvals32; }
+template <class T> __device__ __forceinline__ const T* pvals(const DevDomain& D);
+template <> __device__ __forceinline__ const double* pvals<double>(const DevDomain& D) { return D.pvals; }
+template <> __device__ __forceinline__ const float* pvals<float>(const DevDomain& D) { return D.pvals32; }
 template <class T> __device__ __forceinline__ const T* tmat(const DevOp& op);
 template <> __device__ __forceinline__ const double* tmat<double>(const DevOp& op) { return op.term_tm; }
 template <> __device__ __forceinline__ const float* tmat<float>(const DevOp& op) { return op.term_tm32; }
@@ -123,11 +126,12 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   }
 }
 
-// Pass 1b: y = upper-partner part sum_k Tm_k (I (x) V_k) (I (x) E^v) Qt^{m(k)}
-// (zero for grids without an upper partner); pass 2 then adds the x-stencils.
+// Pass 1b: y = upper-partner part sum_k Tm_k (I (x) V_k E^v) Qt^{m(k)}, with the
+// prolongated stencils V_k E^v (fine node -> 3^d coarse nodes around floor(v/2))
+// precomputed per level; zero for grids without an upper partner.  Pass 2 then
+// adds the x-stencils.
 template <class T, int D, int R, int BC>
 __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
-  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
   const SplitItem it = C.items[blockIdx.x];
   const int b0 = int(blockIdx.y) * BC;
   const ProbDesc& A = C.descs[it.prob];
@@ -138,34 +142,57 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
   if (p >= plane) return;
   const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
   const int lv = A.G.lv[g];
-  const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
   const DevOp& op = A.op;
-  const T* vv = vals<T>(A.DV);
   const T* tm = tmat<T>(op);
   T acc[BC][R];
 #pragma unroll
   for (int q = 0; q < BC; ++q)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
-  // upper partners: v-stencils of the v-prolonged Qt
   const bool has_q = !A.diag_only && g + 1 < A.G.n;
   if (has_q) {
     const int nvl = A.Gl.nv[g];  // lower grid g: (lx, lv - 1)
     const int64_t qplane = int64_t(nx) * nvl;
     const int64_t ltotal = A.Gl.off[A.Gl.n];
-    const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
-    int32_t vp0[SS], vp1[SS];
-    T vw0[SS], vw1[SS];
+    // Either the prolongated stencils V_k E^v on 3^d coarse slots (d <= 2), or,
+    // for d = 3 where 27 slots cost more than 2 parents of 15 neighbours,
+    // the v-stencil of Qt prolonged on the fly.
+    constexpr bool kPro = D <= 2;
+    constexpr int NS = kPro ? (D == 1 ? 3 : 9) : 15;  // slots per point
+    int32_t i0[NS], i1[NS];
+    T w0[NS], w1[NS];
+    int64_t fbase;
+    int64_t fstride;
+    const T* fvals;
+    if constexpr (kPro) {
+      const int64_t plo = A.DV.plev_off[lv - A.DV.lmin];
 #pragma unroll
-    for (int e = 0; e < SS; ++e) {
-      const int32_t vn = A.DV.tnbr[vlo + int64_t(e) * nv + v];
-      vp0[e] = A.DV.par[vpo + 2 * int64_t(vn)];
-      vp1[e] = A.DV.par[vpo + 2 * int64_t(vn) + 1];
-      vw0[e] = T(A.DV.parw[vpo + 2 * int64_t(vn)]);
-      vw1[e] = T(A.DV.parw[vpo + 2 * int64_t(vn) + 1]);
+      for (int sl = 0; sl < NS; ++sl) {
+        i0[sl] = A.DV.pidx[plo + int64_t(sl) * nv + v];
+        i1[sl] = 0;
+        w0[sl] = T(1);
+        w1[sl] = T(0);
+      }
+      fvals = pvals<T>(A.DV);
+      fbase = plo + v;
+      fstride = A.DV.pstride;
+    } else {
+      const int64_t vlo = A.DV.lev_off[lv - A.DV.lmin];
+      const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
+#pragma unroll
+      for (int e = 0; e < NS; ++e) {
+        const int32_t vn = A.DV.tnbr[vlo + int64_t(e) * nv + v];
+        i0[e] = A.DV.par[vpo + 2 * int64_t(vn)];
+        i1[e] = A.DV.par[vpo + 2 * int64_t(vn) + 1];
+        w0[e] = T(A.DV.parw[vpo + 2 * int64_t(vn)]);
+        w1[e] = T(A.DV.parw[vpo + 2 * int64_t(vn) + 1]);
+      }
+      fvals = vals<T>(A.DV);
+      fbase = vlo + v;
+      fstride = A.DV.fac_stride;
     }
     for (int m = 0; m < op.nxg; ++m) {
-      T qv[BC][R][SS];
+      T qv[BC][R][NS];
 #pragma unroll
       for (int q = 0; q < BC; ++q) {
         const int b = b0 + q < C.B ? b0 + q : b0;
@@ -174,15 +201,17 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
 #pragma unroll
         for (int s = 0; s < R; ++s)
 #pragma unroll
-          for (int e = 0; e < SS; ++e)
-            qv[q][s][e] = vw0[e] * qb[int64_t(s) * qplane + vp0[e]] + vw1[e] * qb[int64_t(s) * qplane + vp1[e]];
+          for (int e = 0; e < NS; ++e) {
+            const T* row = qb + int64_t(s) * qplane;
+            qv[q][s][e] = kPro ? row[i0[e]] : w0[e] * row[i0[e]] + w1[e] * row[i1[e]];
+          }
       }
       for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
         const int k = op.xg_terms[kk];
-        const T* f = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
-        T vf[SS];
+        const T* f = fvals + int64_t(op.term_vf[k]) * fstride + fbase;
+        T vf[NS];
 #pragma unroll
-        for (int e = 0; e < SS; ++e) vf[e] = f[int64_t(e) * nv];
+        for (int e = 0; e < NS; ++e) vf[e] = f[int64_t(e) * nv];
         const T* tk = tm + int64_t(k) * R * R;
         T tkv[R * R];
 #pragma unroll
@@ -193,7 +222,7 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
           for (int s2 = 0; s2 < R; ++s2) {
             T t = T(0);
 #pragma unroll
-            for (int e = 0; e < SS; ++e) t += vf[e] * qv[q][s2][e];
+            for (int e = 0; e < NS; ++e) t += vf[e] * qv[q][s2][e];
 #pragma unroll
             for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
           }
