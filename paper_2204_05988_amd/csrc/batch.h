@@ -27,6 +27,12 @@ struct ProbDesc {
   int64_t y_off;       // start of its output vector
   int64_t pt_off, qt_off;  // start of its scan arrays
   int64_t z_off;           // start of its staged v-stage arrays (split application)
+  // partner-scan recursion through restricted scan arrays:
+  //   Rv_t = (I (x) E^vT) Pt on lower grid t-1, shape nx(low t-1) x nv(low t), feeds lower target t
+  //   Rx_l = (E^xT (x) I) Qt on lower grid l+1, shape nx(low l) x nv(low l+1), feeds upper target l
+  int64_t rv_off, rx_off;              // start of this problem's arrays (per factor group stride rv_len/rx_len)
+  int64_t rv_len, rx_len;              // elements per factor group (all slices, all targets)
+  int64_t rvo[kMaxGrids], rxo[kMaxGrids];  // start of target t's block within one group
 };
 
 // A box of x-nodes times a box of v-nodes of one grid of one problem.
@@ -40,7 +46,7 @@ struct FusedItem {
 struct ScanItem {
   int prob, side;      // side 0: lower partners (Pt), 1: upper partners (Qt)
   int lg;              // target lower grid
-  int grp;             // unused (0)
+  int grp;             // 0: scan step (base + recursion), 2: restriction feeding the next step
   int64_t start;       // first element of the block in the target
 };
 
@@ -57,6 +63,9 @@ struct FusedCall {
   T* y;
   T* Pt;
   T* Qt;
+  int64_t rv_bstride, rx_bstride;
+  T* Rv;
+  T* Rx;
 };
 
 // Split application: one block of points of one grid of one problem.

@@ -341,6 +341,12 @@ template <class T> __device__ __forceinline__ const T* rv(const DevDomain& D);
 template <> __device__ __forceinline__ const double* rv<double>(const DevDomain& D) { return D.trvals; }
 template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.trvals32; }
 
+// One launch of the partner scans.  Mode 0 (a step): the restricted-stencil
+// part from u plus the recursion term, which acts on the previous step's array
+// through its restriction (E^x and E^vT act on different axes and commute):
+//   Pt_{t}   = (I (x) E^vT V) u_t + (E^x (x) I) Rv_t,   Rv_t = (I (x) E^vT) Pt_{t-1}
+//   Qt_l     = (E^xT X (x) I) u_{l+1} + (I (x) E^v) Rx_l, Rx_l = (E^xT (x) I) Qt_{l+1}
+// Mode 2 computes Rv_t and Rx_l from the arrays the previous step finished.
 template <class T, int D, int R>
 __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   constexpr int W = D == 1 ? 5 : (D == 2 ? 19 : 65);
@@ -354,17 +360,75 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   const int b = blockIdx.y;
   const DevOp& op = A.op;
   const int lg = si.lg;
+  const int64_t ltotal = L.off[L.n];
+  T* Ptb = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off;
+  T* Qtb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off;
+  T* Rvb = C.Rv + int64_t(b) * C.rv_bstride + A.rv_off;
+  T* Rxb = C.Rx + int64_t(b) * C.rx_bstride + A.rx_off;
+  if (si.grp == 2) {
+    if (lower) {
+      // Rv_t[xc][vc] = sum_c chiw_c(vc) Pt_{t-1}[xc][chi_c(vc)], vc on the target's v-level
+      const int nxs = L.nx[lg - 1], nvs = L.nv[lg - 1], nvt = L.nv[lg];
+      const int64_t n = int64_t(nxs) * nvt;
+      const int64_t e = si.start + threadIdx.x;
+      if (e >= n) return;
+      const int xc = int(e / nvt), vc = int(e - int64_t(e / nvt) * nvt);
+      const int lvc = G.lv[lg] - 1 - A.DV.lmin;
+      const int64_t co = A.DV.lev_off[lvc] + vc;
+      int32_t ch[SS];
+      T cw[SS];
+#pragma unroll
+      for (int c = 0; c < SS; ++c) {
+        ch[c] = A.DV.tchi[co + int64_t(c) * nvt];
+        cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvt]);
+      }
+      const int64_t splane = int64_t(nxs) * nvs;
+      for (int j = 0; j < op.nvg; ++j)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(s) * splane + int64_t(xc) * nvs;
+          T acc = T(0);
+#pragma unroll
+          for (int c = 0; c < SS; ++c) acc += cw[c] * row[ch[c]];
+          Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(s) * n + e] = acc;
+        }
+    } else {
+      // Rx_l[xc][vq] = sum_c chiw_c(xc) Qt_{l+1}[chi_c(xc)][vq], xc on the target's x-level
+      const int nxt = L.nx[lg], nxs = L.nx[lg + 1], nvs = L.nv[lg + 1];
+      const int64_t n = int64_t(nxt) * nvs;
+      const int64_t e = si.start + threadIdx.x;
+      if (e >= n) return;
+      const int xc = int(e / nvs), vq = int(e - int64_t(e / nvs) * nvs);
+      const int lxc = G.lx[lg] - A.DX.lmin;  // target x-level (= lower grid lg's)
+      const int64_t co = A.DX.lev_off[lxc] + xc;
+      int32_t ch[SS];
+      T cw[SS];
+#pragma unroll
+      for (int c = 0; c < SS; ++c) {
+        ch[c] = A.DX.tchi[co + int64_t(c) * nxt];
+        cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxt]);
+      }
+      const int64_t splane = int64_t(nxs) * nvs;
+      for (int m = 0; m < op.nxg; ++m)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(s) * splane + vq;
+          T acc = T(0);
+#pragma unroll
+          for (int c = 0; c < SS; ++c) acc += cw[c] * col[int64_t(ch[c]) * nvs];
+          Rxb[int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(s) * n + e] = acc;
+        }
+    }
+    return;
+  }
   const int nxl = L.nx[lg], nvl = L.nv[lg];
   const int64_t lplane = int64_t(nxl) * nvl;
   const int64_t pt = si.start + threadIdx.x;  // target point x * nvl + v
   if (pt >= lplane) return;
   const int x = int(pt / nvl), v = int(pt - int64_t(pt / nvl) * nvl);
-  const int64_t ltotal = L.off[L.n];
   const T* ub = C.u + int64_t(b) * C.u_bstride + A.u_off;
-  T* Ptb = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off;
-  T* Qtb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off;
   if (lower) {
-    // source grid t (lx, lv); target (lx, lv-1); previous Pt_t on lower grid t-1 (lx-1, lv)
+    // source grid t (lx, lv); target (lx, lv-1); recursion from Rv_t (x-level lx-1)
     const int src = lg;
     const int nv = G.nv[src];
     const int lvc = G.lv[src] - 1 - A.DV.lmin;  // level of v (coarse) = the target's
@@ -375,22 +439,15 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
     const bool has_p = src > 0;
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
-    int32_t ch[SS];
-    T cw[SS];
+    int64_t rn = 0;
     if (has_p) {
       const int64_t po = A.DX.par_off[G.lx[src] - A.DX.lmin] + 2 * int64_t(x);
       p0 = A.DX.par[po];
       p1 = A.DX.par[po + 1];
       w0 = T(A.DX.parw[po]);
       w1 = T(A.DX.parw[po + 1]);
-      const int64_t co = A.DV.lev_off[lvc] + v;
-#pragma unroll
-      for (int c = 0; c < SS; ++c) {
-        ch[c] = A.DV.tchi[co + int64_t(c) * nvl];
-        cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvl]);
-      }
+      rn = int64_t(L.nx[src - 1]) * nvl;
     }
-    const int64_t pl = has_p ? int64_t(L.nx[src - 1]) * nv : 0;
     for (int s0 = 0; s0 < R; s0 += RS) {
       T un[RS][W];
 #pragma unroll
@@ -411,18 +468,15 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
           if (has_p) {
-            const T* pp = Ptb + int64_t(j) * ltotal + L.off[src - 1] + int64_t(s) * pl;
-            const T* r0 = pp + int64_t(p0) * nv;
-            const T* r1 = pp + int64_t(p1) * nv;
-#pragma unroll
-            for (int c = 0; c < SS; ++c) acc += cw[c] * (w0 * r0[ch[c]] + w1 * r1[ch[c]]);
+            const T* rvp = Rvb + int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(s) * rn + v;
+            acc += w0 * rvp[int64_t(p0) * nvl] + w1 * rvp[int64_t(p1) * nvl];
           }
           Ptb[int64_t(j) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
         }
       }
     }
   } else {
-    // source grid lg+1 (lx+1, lv-1); target lower lg (lx, lv-1); previous Qt on lower grid lg+1 (lx+1, lv-2)
+    // source grid lg+1 (lx+1, lv-1); target lower lg (lx, lv-1); recursion from Rx_lg (v-level lv-2)
     const int src = lg + 1;
     const int nv = G.nv[src];
     const int lxc = G.lx[src] - 1 - A.DX.lmin;  // level of x (coarse) = the target's
@@ -433,24 +487,17 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
     const bool has_q = src + 1 < G.n;
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
-    int32_t ch[SS];
-    T cw[SS];
     int nvq = 0;
+    int64_t rn = 0;
     if (has_q) {
       const int64_t po = A.DV.par_off[G.lv[src] - A.DV.lmin] + 2 * int64_t(v);
       p0 = A.DV.par[po];
       p1 = A.DV.par[po + 1];
       w0 = T(A.DV.parw[po]);
       w1 = T(A.DV.parw[po + 1]);
-      const int64_t co = A.DX.lev_off[lxc] + x;
-#pragma unroll
-      for (int c = 0; c < SS; ++c) {
-        ch[c] = A.DX.tchi[co + int64_t(c) * nxl];
-        cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxl]);
-      }
       nvq = L.nv[src];
+      rn = int64_t(nxl) * nvq;
     }
-    const int64_t ql = has_q ? int64_t(L.nx[src]) * nvq : 0;
     for (int s0 = 0; s0 < R; s0 += RS) {
       T un[RS][W];
 #pragma unroll
@@ -471,12 +518,8 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
           if (has_q) {
-            const T* qq = Qtb + int64_t(m) * ltotal + L.off[src] + int64_t(s) * ql;
-#pragma unroll
-            for (int c = 0; c < SS; ++c) {
-              const T* row = qq + int64_t(ch[c]) * nvq;
-              acc += cw[c] * (w0 * row[p0] + w1 * row[p1]);
-            }
+            const T* rxp = Rxb + int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(s) * rn + int64_t(x) * nvq;
+            acc += w0 * rxp[p0] + w1 * rxp[p1];
           }
           Qtb[int64_t(m) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
         }

@@ -36,7 +36,7 @@ struct Items {
 struct KindData {
   DevBuf desc;
   std::vector<ProbDesc> host;
-  int64_t pt_bstride = 0, qt_bstride = 0, z_bstride = 0, total = 0;
+  int64_t pt_bstride = 0, qt_bstride = 0, z_bstride = 0, rv_bstride = 0, rx_bstride = 0, total = 0;
   int R = 1;
   bool any_scan = false;
   Items it[2];  // FP64, FP32
@@ -46,7 +46,7 @@ struct KindData {
 
 template <class T>
 struct BWork {
-  DevBuf Pt, Qt, Z, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
+  DevBuf Pt, Qt, Rv, Rx, Z, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
 };
 
 }  // namespace
@@ -155,7 +155,7 @@ static KindData& kind(Batch& B, int k) {
   const int opidx = (k == K_FULL || k == K_DIAG || k == K_CT) ? 0 : (k == K_MASS ? 1 : (k == K_DATAF ? 2 : 3));
   const int R = B.P[0]->ops[opidx].op.Rin;
   K.R = R;
-  int64_t off = 0, pt = 0, qt = 0, zo = 0;
+  int64_t off = 0, pt = 0, qt = 0, zo = 0, rvb = 0, rxb = 0;
   std::vector<SplitItem> sitems;
   for (size_t p = 0; p < B.P.size(); ++p) {
     sgdg_ops o = B.P[p];
@@ -193,11 +193,23 @@ static KindData& kind(Batch& B, int k) {
       const int64_t plane = int64_t(D.G.nx[gi]) * D.G.nv[gi];
       for (int64_t p0 = 0; p0 < plane; p0 += split_points_per_item()) sitems.push_back(SplitItem{int(p), gi, p0});
     }
+    D.rv_off = rvb;
+    D.rx_off = rxb;
+    D.rv_len = D.rx_len = 0;
     if (!D.diag_only) {
       K.any_scan = true;
       const int64_t lt = D.Gl.off[D.Gl.n];
       pt += int64_t(std::max(1, D.op.nvg)) * lt;
       qt += int64_t(std::max(1, D.op.nxg)) * lt;
+      const int nlow = D.Gl.n;
+      for (int t = 0; t < nlow; ++t) {
+        D.rvo[t] = D.rv_len;
+        if (t >= 1) D.rv_len += int64_t(R) * D.Gl.nx[t - 1] * D.Gl.nv[t];
+        D.rxo[t] = D.rx_len;
+        if (t + 1 < nlow) D.rx_len += int64_t(R) * D.Gl.nx[t] * D.Gl.nv[t + 1];
+      }
+      rvb += int64_t(std::max(1, D.op.nvg)) * std::max<int64_t>(1, D.rv_len);
+      rxb += int64_t(std::max(1, D.op.nxg)) * std::max<int64_t>(1, D.rx_len);
     }
     K.host.push_back(D);
   }
@@ -205,6 +217,8 @@ static KindData& kind(Batch& B, int k) {
   K.pt_bstride = pt;
   K.qt_bstride = qt;
   K.z_bstride = zo;
+  K.rv_bstride = rvb;
+  K.rx_bstride = rxb;
   upload(K.desc, K.host);
   upload(K.split_items, sitems);
   K.n_split = int(sitems.size());
@@ -314,23 +328,33 @@ static Items& items(Batch& B, int k, int elem) {
   I.max_stage = int(max_stage);
   I.max_u = int(max_u);
   I.max_tab = int(max_tab);
-  // scan work: one table per step, all problems
+  // scan work: launch 2t is step t (base + recursion from the restricted
+  // arrays), launch 2t-1 restricts the arrays step t - 1 finished (t >= 1)
   std::vector<ScanItem> sits;
   I.step_first.clear();
   I.step_count.clear();
   if (K.any_scan) {
     for (int t = 0; t + 1 < maxn; ++t) {
-      I.step_first.push_back(int(sits.size()));
-      for (size_t p = 0; p < B.P.size(); ++p) {
-        const ProbDesc& D = K.host[p];
-        if (D.diag_only || t + 1 >= D.G.n) continue;
-        for (int side = 0; side < 2; ++side) {
-          const int lg = side == 0 ? t : D.Gl.n - 1 - t;
-          const int64_t len = int64_t(D.Gl.nx[lg]) * D.Gl.nv[lg];  // points; slices loop in the kernel
-          for (int64_t st = 0; st < len; st += fused_threads()) sits.push_back(ScanItem{int(p), side, lg, 0, st});
+      for (int phase = (t == 0 ? 1 : 0); phase < 2; ++phase) {
+        I.step_first.push_back(int(sits.size()));
+        for (size_t p = 0; p < B.P.size(); ++p) {
+          const ProbDesc& D = K.host[p];
+          if (D.diag_only || t + 1 >= D.G.n) continue;
+          const int nlow = D.Gl.n;
+          for (int side = 0; side < 2; ++side) {
+            const int lg = side == 0 ? t : nlow - 1 - t;
+            int64_t len;
+            if (phase == 1) {
+              len = int64_t(D.Gl.nx[lg]) * D.Gl.nv[lg];  // target points; slices loop in the kernel
+            } else {
+              len = side == 0 ? int64_t(D.Gl.nx[lg - 1]) * D.Gl.nv[lg] : int64_t(D.Gl.nx[lg]) * D.Gl.nv[lg + 1];
+            }
+            for (int64_t st = 0; st < len; st += fused_threads())
+              sits.push_back(ScanItem{int(p), side, lg, phase == 1 ? 0 : 2, st});
+          }
         }
+        I.step_count.push_back(int(sits.size()) - I.step_first.back());
       }
-      I.step_count.push_back(int(sits.size()) - I.step_first.back());
     }
   }
   upload(I.sitems, sits);
@@ -362,6 +386,12 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
     C.Qt = ptr<T>(w.Qt);
     C.pt_bstride = K.pt_bstride;
     C.qt_bstride = K.qt_bstride;
+    w.Rv.ensure(sizeof(T) * size_t(K.rv_bstride) * nb);
+    w.Rx.ensure(sizeof(T) * size_t(K.rx_bstride) * nb);
+    C.Rv = ptr<T>(w.Rv);
+    C.Rx = ptr<T>(w.Rx);
+    C.rv_bstride = K.rv_bstride;
+    C.rx_bstride = K.rx_bstride;
     timed(B, 0, s, [&] {
       for (size_t t = 0; t < I.step_first.size(); ++t) {
         FusedCall<T> Cs = C;
