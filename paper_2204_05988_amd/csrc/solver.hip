@@ -190,8 +190,26 @@ static KindData& kind(Batch& B, int k) {
     D.z_off = zo;
     zo += int64_t(std::max(1, D.op.nxg)) * D.G.off[D.G.n];  // one staged array per X-group
     for (int gi = 0; gi < D.G.n; ++gi) {
-      const int64_t plane = int64_t(D.G.nx[gi]) * D.G.nv[gi];
-      for (int64_t p0 = 0; p0 < plane; p0 += split_points_per_item()) sitems.push_back(SplitItem{int(p), gi, p0});
+      // blocks in Morton order of their x-node (then v): x-rows that share
+      // parents or stencil neighbours run close together in time
+      const int64_t nvg = D.G.nv[gi];
+      const int64_t plane = int64_t(D.G.nx[gi]) * nvg;
+      const int mxg = g->x.axis_nodes(D.G.lx[gi]);
+      std::vector<std::pair<uint64_t, int64_t>> keyed;
+      for (int64_t p0 = 0; p0 < plane; p0 += split_points_per_item()) {
+        int64_t xn = p0 / nvg;
+        int c[3] = {0, 0, 0};
+        for (int a = B.d - 1; a >= 0; --a) {
+          c[a] = int(xn % mxg);
+          xn /= mxg;
+        }
+        uint64_t key = 0;
+        for (int bit = 0; bit < 16; ++bit)
+          for (int a = 0; a < B.d; ++a) key |= uint64_t((c[a] >> bit) & 1) << (bit * B.d + a);
+        keyed.push_back({(key << 24) | uint64_t((p0 % nvg) / split_points_per_item()), p0});
+      }
+      std::stable_sort(keyed.begin(), keyed.end());
+      for (const auto& kp : keyed) sitems.push_back(SplitItem{int(p), gi, kp.second});
     }
     D.rv_off = rvb;
     D.rx_off = rxb;
