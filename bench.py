@@ -244,11 +244,15 @@ def solve_times(ops, w, dev):
 
     b = ops.rhs(u0, 1, nodal(w.f), nodal(w.g))
     res = {}
-    for name, mixed in (("fp64", False), ("mixed_fp32", True)):
+    # grid problems to 1e-8 (at most 200 GMRES iterations), and inexact (10 iterations each)
+    for name, mixed, cap in (("fp64", False, 200), ("mixed_fp32", True, 200),
+                             ("fp64_inexact_ct", False, 10), ("mixed_fp32_inexact_ct", True, 10)):
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, st = ops.solve_strip(b, x, sgdg.default_solve_opts(rtol=1e-8, mixed=mixed), raise_on_noconv=False)
+        opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=mixed,
+                                       pc=sgdg.default_precond_opts(inner_maxit=cap))
+        x, st = ops.solve_strip(b, x, opts, raise_on_noconv=False)
         torch.cuda.synchronize()
         res[name] = {"seconds": round(time.perf_counter() - t0, 4), "outer_iters": st.outer_iters,
                      "inner_iters": st.inner_iters_total, "rel_residual": st.rel_residual,
@@ -308,14 +312,23 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
                      "loss_first": ts.loss_first, "loss_last": ts.loss_last}, "strips": []}
     learned = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(net=net))
     learned_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True, pc=sgdg.default_precond_opts(net=net))
+    # inexact grid problems (10 GMRES iterations each): the combination technique
+    # alone, and as the learned preconditioner's fallback
+    ct_inexact = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(inner_maxit=10))
+    learned_inexact = sgdg.default_solve_opts(rtol=1e-8, maxit=400,
+                                              pc=sgdg.default_precond_opts(net=net, inner_maxit=10))
     for j in range(record_strips + 1, record_strips + test_strips + 1):
         b = ops.rhs(u, prev)
         row = {"strip": j}
         x, row["ct_fp64"] = _timed_solve(ops, b, ct)
         _, row["learned_fp64"] = _timed_solve(ops, b, learned)
         _, row["learned_mixed"] = _timed_solve(ops, b, learned_mixed)
-        row["gain_learned_fp64"] = round(row["ct_fp64"]["seconds"] / row["learned_fp64"]["seconds"], 3)
-        row["gain_learned_mixed"] = round(row["ct_fp64"]["seconds"] / row["learned_mixed"]["seconds"], 3)
+        _, row["ct_inexact_fp64"] = _timed_solve(ops, b, ct_inexact)
+        _, row["learned_inexact_fallback_fp64"] = _timed_solve(ops, b, learned_inexact)
+        t0 = row["ct_fp64"]["seconds"]
+        row["gain_vs_ct_fp64"] = {k: round(t0 / row[k]["seconds"], 3)
+                                  for k in ("learned_fp64", "learned_mixed", "ct_inexact_fp64",
+                                            "learned_inexact_fallback_fp64")}
         out["strips"].append(row)
         _log(f"learned leg: {row}")
         u = x
@@ -399,6 +412,17 @@ def batched_leg(dev, n):
     out["batched_mixed_solve"] = {"seconds": round(tb, 3), "outer_iters": st.outer_iters,
                                   "refinements": st.refinement_steps, "max_rel_residual": st.rel_residual}
     _log(f"batched leg: {out['batched_mixed_solve']}")
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = batch.solve(b, x, sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                                      pc=sgdg.default_precond_opts(inner_maxit=10)),
+                        raise_on_noconv=False)
+    torch.cuda.synchronize()
+    tbi = time.perf_counter() - t0
+    out["batched_mixed_solve_inexact_ct"] = {"seconds": round(tbi, 3), "outer_iters": st.outer_iters,
+                                             "refinements": st.refinement_steps, "max_rel_residual": st.rel_residual}
+    _log(f"batched leg: {out['batched_mixed_solve_inexact_ct']}")
     seq, worst = 0.0, 0.0
     for ops, bb in zip(ops_list, bs):
         _, r = _timed_solve(ops, bb, sgdg.default_solve_opts(rtol=1e-8, maxit=400))
@@ -406,6 +430,7 @@ def batched_leg(dev, n):
         worst = max(worst, r["rel_residual"])
     out["sequential_fp64_solve"] = {"seconds": round(seq, 3), "max_rel_residual": worst}
     out["speedup_batched_mixed_vs_sequential_fp64"] = round(seq / tb, 3)
+    out["speedup_batched_mixed_inexact_ct_vs_sequential_fp64"] = round(seq / tbi, 3)
     batch.close()
     for o in ops_list:
         o.close()
