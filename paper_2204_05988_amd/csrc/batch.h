@@ -117,6 +117,6 @@ struct BlockRef {  // one block of a segmented launch
   int seg, chunk;
 };
 
-constexpr int kChunk = 4096;  // elements per block in segmented launches
+constexpr int kChunk = 1024;  // elements per block in segmented launches
 
 }  // namespace sgdg

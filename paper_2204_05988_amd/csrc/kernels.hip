@@ -45,11 +45,15 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
                                                      const T* __restrict__ V, int64_t vstride, int nvec,
                                                      const T* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double sh[kBlock / 64];
+  // wave sums per vector in LDS, one barrier, then thread k adds the waves of vector k
+  constexpr int kWaves = kBlock / 64;
+  constexpr int kMaxVec = 72;
+  __shared__ double sh[kWaves][kMaxVec];
   const BlockRef br = blk[blockIdx.x];
   const SegInfo& S = segs[br.seg];
   const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
   const int64_t end = S.off + S.len;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double wl[kPer];
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
@@ -57,16 +61,27 @@ __global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__
     wl[t] = i < end ? double(w[i]) : 0.0;
   }
   double* out = partial + int64_t(S.chunk0 + br.chunk) * nvec;
-  for (int k = 0; k < nvec; ++k) {
-    const T* vk = V + int64_t(k) * vstride;
-    double acc = 0;
+  for (int k0 = 0; k0 < nvec; k0 += kMaxVec) {
+    const int nk = nvec - k0 < kMaxVec ? nvec - k0 : kMaxVec;
+    for (int k = 0; k < nk; ++k) {
+      const T* vk = V + int64_t(k0 + k) * vstride;
+      double acc = 0;
 #pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
-      if (i < end) acc += double(vk[i]) * wl[t];
+      for (int t = 0; t < kPer; ++t) {
+        const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
+        if (i < end) acc += double(vk[i]) * wl[t];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) sh[wv][k] = acc;
     }
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[k] = acc;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nk; k += kBlock) {
+      double a = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) a += sh[q][k];
+      out[k0 + k] = a;
+    }
+    __syncthreads();
   }
 }
 
@@ -142,18 +157,29 @@ __global__ void k_f2d(int64_t n, const float* __restrict__ x, double* __restrict
 // ------------------------------------------------------ GMRES bookkeeping --
 __device__ __forceinline__ bool finite(double x) { return x == x && x - x == 0.0; }
 
-__global__ void k_gmres_start(int nseg, GmresState st, const SegInfo* __restrict__ segs,
-                              const double* __restrict__ partial, double tol, int first) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nseg) return;
+// Sum of partial[(chunk0 + c) * stride + idx] over the segment's chunks with the
+// whole block (fixed order per thread, then a fixed tree): valid in thread 0.
+__device__ double seg_chunk_sum(const SegInfo& S, const double* __restrict__ partial, int stride, int idx,
+                                double* sh) {
+  double a = 0;
+  for (int c = threadIdx.x; c < S.nchunk; c += kBlock) a += partial[int64_t(S.chunk0 + c) * stride + idx];
+  return block_sum(a, sh);
+}
+
+// one block per segment
+__global__ void __launch_bounds__(kBlock) k_gmres_start(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                                                        const double* __restrict__ partial, double tol, int first) {
+  __shared__ double sh[kBlock / 64];
+  const int g = blockIdx.x;
   const int m = st.m;
-  double s = 0;
-  for (int c = 0; c < segs[g].nchunk; ++c) s += partial[segs[g].chunk0 + c];
+  const double s = seg_chunk_sum(segs[g], partial, 1, 0, sh);
+  for (int i = threadIdx.x; i < (m + 1) * m; i += kBlock) st.H[int64_t(g) * (m + 1) * m + i] = 0.0;
+  for (int i = threadIdx.x; i <= m; i += kBlock) st.g[int64_t(g) * (m + 1) + i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double beta = sqrt(s);
   if (first) st.bnorm[g] = beta;
   st.beta[g] = beta;
-  for (int i = 0; i < (m + 1) * m; ++i) st.H[int64_t(g) * (m + 1) * m + i] = 0.0;
-  for (int i = 0; i <= m; ++i) st.g[int64_t(g) * (m + 1) + i] = 0.0;
   st.g[int64_t(g) * (m + 1)] = beta;
   const bool act = finite(beta) && beta > 0.0 && beta > tol * st.bnorm[g];
   st.active[g] = act ? 1 : (finite(beta) ? 0 : -1);
@@ -161,31 +187,50 @@ __global__ void k_gmres_start(int nseg, GmresState st, const SegInfo* __restrict
   st.inv[g] = act ? 1.0 / beta : 0.0;
 }
 
-__global__ void k_gmres_proj(int nseg, GmresState st, const SegInfo* __restrict__ segs,
-                             const double* __restrict__ partial, int j) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// one block per segment; thread i < nv owns projection coefficient i, the
+// block's waves split the chunks and are combined in a fixed order
+__global__ void __launch_bounds__(kBlock) k_gmres_proj(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                                                       const double* __restrict__ partial, int j) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ double sh[kWaves][64];
+  const int g = blockIdx.x;
   const int nv = j + 1;
-  if (t >= nseg * nv) return;
-  const int g = t / nv, i = t - g * nv;
   const int m = st.m;
-  double a = 0;
-  for (int c = 0; c < segs[g].nchunk; ++c) a += partial[int64_t(segs[g].chunk0 + c) * nv + i];
-  if (st.active[g] != 1) a = 0.0;
-  st.hcol[int64_t(g) * (m + 1) + i] = a;
-  st.H[int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1) + i] += a;
+  const SegInfo& S = segs[g];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool act = st.active[g] == 1;
+  for (int i0 = 0; i0 < nv; i0 += 64) {
+    const int i = i0 + lane;
+    double a = 0;
+    if (i < nv)
+      for (int c = wv; c < S.nchunk; c += kWaves) a += partial[int64_t(S.chunk0 + c) * nv + i];
+    sh[wv][lane] = a;
+    __syncthreads();
+    if (wv == 0 && i < nv) {
+      double t = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) t += sh[q][lane];
+      if (!act) t = 0.0;
+      st.hcol[int64_t(g) * (m + 1) + i] = t;
+      st.H[int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1) + i] += t;
+    }
+    __syncthreads();
+  }
 }
 
-__global__ void k_gmres_givens(int nseg, GmresState st, const SegInfo* __restrict__ segs,
-                               const double* __restrict__ partial, int j, double tol) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nseg) return;
+// one block per segment: the norm of the new direction from the chunk
+// partials, then the Givens rotations in thread 0
+__global__ void __launch_bounds__(kBlock) k_gmres_givens(int nseg, GmresState st, const SegInfo* __restrict__ segs,
+                                                         const double* __restrict__ partial, int j, double tol) {
+  __shared__ double sh[kBlock / 64];
+  const int g = blockIdx.x;
   const int m = st.m;
+  const double s = seg_chunk_sum(segs[g], partial, 1, 0, sh);
+  if (threadIdx.x != 0) return;
   if (st.active[g] != 1) {
     st.inv[g] = 0.0;
     return;
   }
-  double s = 0;
-  for (int c = 0; c < segs[g].nchunk; ++c) s += partial[segs[g].chunk0 + c];
   const double hn = sqrt(s);
   double* H = st.H + int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1);
   double* cs = st.cs + int64_t(g) * m;
@@ -434,16 +479,19 @@ void convert_f32_to_f64(int64_t n, const float* x, double* y, hipStream_t s) {
 }
 void gmres_start(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, double tol, int first,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_start, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, segs, partial, tol, first);
+  if (nseg == 0) return;
+  hipLaunchKernelGGL(k_gmres_start, dim3(nseg), dim3(kBlock), 0, s, nseg, st, segs, partial, tol, first);
   LAUNCH_CHECK();
 }
 void gmres_add_proj(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_proj, dim3(nblk(int64_t(nseg) * (j + 1))), dim3(kBlock), 0, s, nseg, st, segs, partial, j);
+  if (nseg == 0) return;
+  hipLaunchKernelGGL(k_gmres_proj, dim3(nseg), dim3(kBlock), 0, s, nseg, st, segs, partial, j);
   LAUNCH_CHECK();
 }
 void gmres_givens(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, double tol,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(nblk(nseg)), dim3(kBlock), 0, s, nseg, st, segs, partial, j, tol);
+  if (nseg == 0) return;
+  hipLaunchKernelGGL(k_gmres_givens, dim3(nseg), dim3(kBlock), 0, s, nseg, st, segs, partial, j, tol);
   LAUNCH_CHECK();
 }
 void gmres_lsq(int nseg, const GmresState& st, hipStream_t s) {

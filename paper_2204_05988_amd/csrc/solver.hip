@@ -437,7 +437,8 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   S.Qt = C.Qt;
   w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
   S.Z = ptr<T>(w.Z);
-  const int bc = B.split_bc > 0 ? B.split_bc : split_default_bc(B.d);
+  // one vector per thread for single vectors (the solvers); tuned otherwise
+  const int bc = nb == 1 ? 1 : (B.split_bc > 0 ? B.split_bc : split_default_bc(B.d));
   for (int stage = 0; stage < 3; ++stage) timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
 }
 
