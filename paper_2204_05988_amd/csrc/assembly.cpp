@@ -357,15 +357,16 @@ void build_prolong_tables(DomainData& D) {
     for (int64_t P = 0; P < F.n; ++P) {
       unflat(P, d, F.m, q);
       for (int a = 0; a < d; ++a) base[a] = q[a] >> 1;
+      // a slot outside a non-periodic lattice carries weight 0; it points at the
+      // nearest lattice node so that every slot of a node stays next to its base
       for (int sl = 0; sl < PW; ++sl) {
         int t = sl;
-        bool ok = true;
         for (int a = 0; a < d; ++a) {
           c[a] = base[a] + (t % 3) - 1;
           t /= 3;
-          if (!dom.periodic && (c[a] < 0 || c[a] >= mc)) ok = false;
+          if (!dom.periodic) c[a] = std::min(std::max(c[a], 0), mc - 1);
         }
-        tab[size_t(sl) * F.n + P] = ok ? int32_t(flat_wrap(c, d, mc, dom.periodic, nc)) : 0;
+        tab[size_t(sl) * F.n + P] = int32_t(flat_wrap(c, d, mc, dom.periodic, nc));
       }
     }
   }

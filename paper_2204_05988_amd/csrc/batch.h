@@ -72,6 +72,11 @@ struct FusedCall {
 struct SplitItem {
   int prob, grid;
   int64_t p0;  // first point (x * nv + v) of the block
+  // upper-partner pass (d <= 2): the in-lattice prolongation slots of the
+  // block's points, as x * nvl + coarse node on the lower grid, lie in
+  // [q0, q0 + qn); qn = 0 when the grid has no upper partner
+  int64_t q0;
+  int qn;
 };
 
 template <class T>
@@ -86,6 +91,8 @@ struct SplitCall {
   const T* Pt;
   const T* Qt;
   T* Z;                    // [b][problem: X-group m][grid layout] staged v-stage W^m
+  int max_qn;              // largest SplitItem::qn (LDS of the upper-partner pass)
+  int xcd;                 // 1: each XCD takes a contiguous range of (vector group, item) blocks
 };
 
 // A contiguous segment of a concatenated vector: one component grid of one

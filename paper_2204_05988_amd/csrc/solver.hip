@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <fstream>
+#include <limits>
 #include <sstream>
 
 #include "ops_internal.h"
@@ -42,6 +43,7 @@ struct KindData {
   Items it[2];  // FP64, FP32
   DevBuf split_items;
   int n_split = 0;
+  int max_qn = 0;  // largest coarse range of an item in the upper-partner pass
 };
 
 template <class T>
@@ -148,6 +150,10 @@ static void drain_events(Batch& B) {
 // ------------------------------------------------------- descriptors -----
 static int64_t up_pts(sgdg_ops o) { return o->grid->up_pts; }
 
+// longest coarse range an item of the upper-partner pass stages in LDS; with a
+// longer one anywhere in the batch the pass reads the slots from memory
+constexpr int64_t kMaxItemRange = 512;
+
 static KindData& kind(Batch& B, int k) {
   KindData& K = B.kinds[k];
   if (!K.host.empty()) return K;
@@ -206,10 +212,34 @@ static KindData& kind(Batch& B, int k) {
         uint64_t key = 0;
         for (int bit = 0; bit < 16; ++bit)
           for (int a = 0; a < B.d; ++a) key |= uint64_t((c[a] >> bit) & 1) << (bit * B.d + a);
-        keyed.push_back({(key << 24) | uint64_t((p0 % nvg) / split_points_per_item()), p0});
+        const uint64_t vb = uint64_t((p0 % nvg) / split_points_per_item());
+        keyed.push_back({split_vmajor() ? (vb << 40) | key : (key << 24) | vb, p0});
       }
       std::stable_sort(keyed.begin(), keyed.end());
-      for (const auto& kp : keyed) sitems.push_back(SplitItem{int(p), gi, kp.second});
+      const bool upper = !D.diag_only && gi + 1 < D.G.n && B.d <= 2;
+      for (const auto& kp : keyed) {
+        SplitItem it{int(p), gi, kp.second, 0, 0};
+        if (upper) {
+          // the prolongation slots of every point, from the level's slot table
+          const std::vector<int32_t>& ptab = o->V.pro_idx[D.G.lv[gi] - o->V.lmin];
+          const int npw = int(ptab.size() / size_t(nvg));
+          const int64_t nvl = D.Gl.nv[gi];
+          int64_t lo = std::numeric_limits<int64_t>::max(), hi = -1;
+          const int64_t pend = std::min<int64_t>(kp.second + split_points_per_item(), plane);
+          for (int64_t pp = kp.second; pp < pend; ++pp) {
+            const int64_t xn = pp / nvg, vn = pp % nvg;
+            for (int sl = 0; sl < npw; ++sl) {
+              const int64_t f = xn * nvl + ptab[size_t(sl) * nvg + vn];
+              lo = std::min(lo, f);
+              hi = std::max(hi, f);
+            }
+          }
+          it.q0 = lo;
+          it.qn = int(std::min<int64_t>(hi - lo + 1, kMaxItemRange + 1));
+          K.max_qn = std::max(K.max_qn, it.qn);
+        }
+        sitems.push_back(it);
+      }
     }
     D.rv_off = rvb;
     D.rx_off = rxb;
@@ -231,6 +261,7 @@ static KindData& kind(Batch& B, int k) {
     }
     K.host.push_back(D);
   }
+  if (K.max_qn > kMaxItemRange) K.max_qn = 0;  // some range too long: every item reads from memory
   K.total = off;
   K.pt_bstride = pt;
   K.qt_bstride = qt;
@@ -437,6 +468,8 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   S.Qt = C.Qt;
   w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
   S.Z = ptr<T>(w.Z);
+  S.max_qn = K.max_qn;
+  S.xcd = split_xcd();
   // one vector per thread for single vectors (the solvers); tuned otherwise
   const int bc = nb == 1 ? 1 : (B.split_bc > 0 ? B.split_bc : split_default_bc(B.d));
   for (int stage = 0; stage < 3; ++stage) timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });

@@ -13,5 +13,7 @@ template <class T>
 void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s);
 int split_points_per_item();
 int split_default_bc(int d);
+bool split_vmajor();
+int split_xcd();
 
 }  // namespace sgdg

@@ -19,6 +19,8 @@
 // factor values of its point are loaded once and reused across them.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "split.h"
 
 namespace sgdg {
@@ -26,6 +28,7 @@ namespace sgdg {
 namespace {
 
 constexpr int kSB = 256;  // threads (points) per block
+constexpr int kQlIters = 2;  // staged coarse range of an item: at most kQlIters * kSB nodes
 // slot-major factor tables: entry e of the nodes of one level is contiguous
 template <class T> __device__ __forceinline__ const T* vals(const DevDomain& D);
 template <> __device__ __forceinline__ const double* vals<double>(const DevDomain& D) { return D.tvals; }
@@ -37,11 +40,29 @@ template <class T> __device__ __forceinline__ const T* tmat(const DevOp& op);
 template <> __device__ __forceinline__ const double* tmat<double>(const DevOp& op) { return op.term_tm; }
 template <> __device__ __forceinline__ const float* tmat<float>(const DevOp& op) { return op.term_tm32; }
 
+// Item and vector group of this block.  With C.xcd the linear block id is
+// remapped so that XCD k (blocks are dealt to the 8 XCDs round-robin) runs one
+// contiguous range of (vector group, item) pairs and its L2 sees neighbouring
+// items together.
+template <class T>
+__device__ __forceinline__ void block_coords(const SplitCall<T>& C, int& item, int& vg) {
+  int L = int(blockIdx.y) * int(gridDim.x) + int(blockIdx.x);
+  if (C.xcd) {
+    const int total = int(gridDim.x) * int(gridDim.y);
+    const int per = total >> 3, rem = total & 7, k = L & 7;
+    L = k * per + min(k, rem) + (L >> 3);
+  }
+  vg = L / int(gridDim.x);
+  item = L - vg * int(gridDim.x);
+}
+
 template <class T, int D, int R, int BC>
 __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
-  const SplitItem it = C.items[blockIdx.x];
-  const int b0 = int(blockIdx.y) * BC;
+  int ii, vg;
+  block_coords(C, ii, vg);
+  const SplitItem it = C.items[ii];
+  const int b0 = vg * BC;
   const ProbDesc& A = C.descs[it.prob];
   const int g = it.grid;
   const int nx = A.G.nx[g], nv = A.G.nv[g];
@@ -129,18 +150,28 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 // Pass 1b: y = upper-partner part sum_k Tm_k (I (x) V_k E^v) Qt^{m(k)}, with the
 // prolongated stencils V_k E^v (fine node -> 3^d coarse nodes around floor(v/2))
 // precomputed per level; zero for grids without an upper partner.  Pass 2 then
-// adds the x-stencils.
-template <class T, int D, int R, int BC>
+// adds the x-stencils.  For d <= 2 the coarse range an item touches (host
+// computed) is staged in LDS once per X-group, so the 3^d slot reads of every
+// point come from LDS instead of the vector L1 (QL); without staging (a range
+// too long for LDS) the slots are read from memory.  The 3^d-slot gathers are
+// what bounds this pass: served by the vector L1 they run at a fraction of
+// the LDS read rate.
+template <class T, int D, int R, int BC, bool QL>
 __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
-  const SplitItem it = C.items[blockIdx.x];
-  const int b0 = int(blockIdx.y) * BC;
+  extern __shared__ unsigned char split_smem[];
+  T* sq = reinterpret_cast<T*>(split_smem);  // two buffers [BC][R][qn]
+  int ii, vg;
+  block_coords(C, ii, vg);
+  const SplitItem it = C.items[ii];
+  const int b0 = vg * BC;
   const ProbDesc& A = C.descs[it.prob];
   const int g = it.grid;
   const int nx = A.G.nx[g], nv = A.G.nv[g];
   const int64_t plane = int64_t(nx) * nv;
   const int64_t p = it.p0 + threadIdx.x;
-  if (p >= plane) return;
-  const int x = int(p / nv), v = int(p - int64_t(p / nv) * nv);
+  const bool act = p < plane;
+  const int x = act ? int(p / nv) : 0;
+  const int v = act ? int(p - int64_t(x) * nv) : 0;
   const int lv = A.G.lv[g];
   const DevOp& op = A.op;
   const T* tm = tmat<T>(op);
@@ -159,6 +190,7 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
     // the v-stencil of Qt prolonged on the fly.
     constexpr bool kPro = D <= 2;
     constexpr int NS = kPro ? (D == 1 ? 3 : 9) : 15;  // slots per point
+    constexpr bool ql = kPro && QL;
     int32_t i0[NS], i1[NS];
     T w0[NS], w1[NS];
     int64_t fbase;
@@ -191,44 +223,105 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
       fbase = vlo + v;
       fstride = A.DV.fac_stride;
     }
-    for (int m = 0; m < op.nxg; ++m) {
-      T qv[BC][R][NS];
+    // one term of X-group m: acc += Tm_k (slots of V_k) . qv
+    auto term = [&](int k, const T (&vf)[NS], const T (&qv)[BC][R][NS]) {
+      const T* tk = tm + int64_t(k) * R * R;
+      T tkv[R * R];
 #pragma unroll
-      for (int q = 0; q < BC; ++q) {
-        const int b = b0 + q < C.B ? b0 + q : b0;
-        const T* qb = C.Qt + int64_t(b) * C.qt_bstride + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g] +
-                      int64_t(x) * nvl;
+      for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
 #pragma unroll
-        for (int s = 0; s < R; ++s)
+      for (int q = 0; q < BC; ++q)
 #pragma unroll
-          for (int e = 0; e < NS; ++e) {
-            const T* row = qb + int64_t(s) * qplane;
-            qv[q][s][e] = kPro ? row[i0[e]] : w0[e] * row[i0[e]] + w1[e] * row[i1[e]];
+        for (int s2 = 0; s2 < R; ++s2) {
+          T t = T(0);
+#pragma unroll
+          for (int e = 0; e < NS; ++e) t += vf[e] * qv[q][s2][e];
+#pragma unroll
+          for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
+        }
+    };
+    auto factors = [&](int k, T (&vf)[NS]) {
+      const T* f = fvals + int64_t(op.term_vf[k]) * fstride + fbase;
+#pragma unroll
+      for (int e = 0; e < NS; ++e) vf[e] = f[int64_t(e) * nv];
+    };
+    if constexpr (ql) {
+      // Software pipeline over the X-groups with two LDS buffers: the coarse
+      // range of group m + 1 is fetched into registers while group m is
+      // computed, so one barrier per group and no exposed fetch latency.
+      const int qn = it.qn;
+      T pre[BC * R][kQlIters];
+      auto fetch = [&](int m) {
+        const T* qm = C.Qt + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g] + it.q0;
+#pragma unroll
+        for (int q = 0; q < BC; ++q) {
+          const int b = b0 + q < C.B ? b0 + q : b0;
+#pragma unroll
+          for (int s = 0; s < R; ++s)
+#pragma unroll
+            for (int j = 0; j < kQlIters; ++j) {
+              const int i = int(threadIdx.x) + j * kSB;
+              if (i < qn) pre[q * R + s][j] = qm[int64_t(b) * C.qt_bstride + int64_t(s) * qplane + i];
+            }
+        }
+      };
+      fetch(0);
+      const int qo = int(int64_t(x) * nvl - it.q0);  // every slot of the item lies in the range (host)
+      for (int m = 0; m < op.nxg; ++m) {
+        T* cur = sq + (m & 1) * (BC * R * qn);
+#pragma unroll
+        for (int t = 0; t < BC * R; ++t)
+#pragma unroll
+          for (int j = 0; j < kQlIters; ++j) {
+            const int i = int(threadIdx.x) + j * kSB;
+            if (i < qn) cur[t * qn + i] = pre[t][j];
           }
-      }
-      for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
-        const int k = op.xg_terms[kk];
-        const T* f = fvals + int64_t(op.term_vf[k]) * fstride + fbase;
+        const int ka = op.xg_start[m], kb = op.xg_start[m + 1];
         T vf[NS];
+        if (ka < kb) factors(op.xg_terms[ka], vf);
+        if (m + 1 < op.nxg) fetch(m + 1);
+        __syncthreads();  // cur is complete; the buffer written next was last read before this barrier
+        if (act && ka < kb) {
+          T qv[BC][R][NS];
 #pragma unroll
-        for (int e = 0; e < NS; ++e) vf[e] = f[int64_t(e) * nv];
-        const T* tk = tm + int64_t(k) * R * R;
-        T tkv[R * R];
+          for (int q = 0; q < BC; ++q)
 #pragma unroll
-        for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
+            for (int s = 0; s < R; ++s)
 #pragma unroll
-        for (int q = 0; q < BC; ++q)
-#pragma unroll
-          for (int s2 = 0; s2 < R; ++s2) {
-            T t = T(0);
-#pragma unroll
-            for (int e = 0; e < NS; ++e) t += vf[e] * qv[q][s2][e];
-#pragma unroll
-            for (int s = 0; s < R; ++s) acc[q][s] += tkv[s * R + s2] * t;
+              for (int e = 0; e < NS; ++e) qv[q][s][e] = cur[(q * R + s) * qn + qo + i0[e]];
+          term(op.xg_terms[ka], vf, qv);
+          for (int kk = ka + 1; kk < kb; ++kk) {
+            factors(op.xg_terms[kk], vf);
+            term(op.xg_terms[kk], vf, qv);
           }
+        }
+      }
+    } else {
+      for (int m = 0; m < op.nxg; ++m) {
+        if (!act) continue;
+        const T* qm = C.Qt + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g];
+        T qv[BC][R][NS];
+#pragma unroll
+        for (int q = 0; q < BC; ++q) {
+          const int b = b0 + q < C.B ? b0 + q : b0;
+          const T* qb = qm + int64_t(b) * C.qt_bstride + int64_t(x) * nvl;
+#pragma unroll
+          for (int s = 0; s < R; ++s)
+#pragma unroll
+            for (int e = 0; e < NS; ++e) {
+              const T* row = qb + int64_t(s) * qplane;
+              qv[q][s][e] = kPro ? row[i0[e]] : w0[e] * row[i0[e]] + w1[e] * row[i1[e]];
+            }
+        }
+        for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
+          T vf[NS];
+          factors(op.xg_terms[kk], vf);
+          term(op.xg_terms[kk], vf, qv);
+        }
       }
     }
   }
+  if (!act) return;
 #pragma unroll
   for (int q = 0; q < BC; ++q) {
     const int b = b0 + q;
@@ -242,8 +335,10 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
 template <class T, int D, int R, int BC>
 __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
-  const SplitItem it = C.items[blockIdx.x];
-  const int b0 = int(blockIdx.y) * BC;
+  int ii, vg;
+  block_coords(C, ii, vg);
+  const SplitItem it = C.items[ii];
+  const int b0 = vg * BC;
   const ProbDesc& A = C.descs[it.prob];
   const int g = it.grid;
   const int nx = A.G.nx[g], nv = A.G.nv[g];
@@ -297,16 +392,31 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
 
 int split_points_per_item() { return kSB; }
 int split_default_bc(int d) { return d == 3 ? 1 : 2; }
+bool split_vmajor() {
+  const char* v = getenv("SGDG_SPLIT_ORDER");
+  return v && atoi(v) == 1;
+}
+int split_xcd() {
+  const char* v = getenv("SGDG_SPLIT_XCD");
+  return v && atoi(v) == 1 ? 1 : 0;
+}
+
+// LDS budget of the upper-partner staging; larger ranges read from memory
+constexpr size_t kQLdsMax = 32 * 1024;
 
 template <class T>
 void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s) {
   if (C.nitems == 0) return;
   if (d == 3 || (bc != 1 && bc != 2 && bc != 4)) bc = d == 3 ? 1 : 2;
+  size_t lds = 2 * size_t(C.max_qn) * R * bc * sizeof(T);  // two buffers
+  const bool ql = stage == 1 && d <= 2 && C.max_qn > 0 && C.max_qn <= kQlIters * kSB && lds <= kQLdsMax;
+  if (!ql) lds = 0;
   dim3 grid(unsigned(C.nitems), unsigned((C.B + bc - 1) / bc));
 #define SGDG_SPLIT_CASE(DD, RR, BB)                                                                 \
   if (d == DD && R == RR && bc == BB) {                                                             \
     if (stage == 0) hipLaunchKernelGGL((k_vstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);        \
-    else if (stage == 1) hipLaunchKernelGGL((k_ustage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);   \
+    else if (stage == 1 && ql) hipLaunchKernelGGL((k_ustage<T, DD, RR, BB, true>), grid, dim3(kSB), lds, s, C); \
+    else if (stage == 1) hipLaunchKernelGGL((k_ustage<T, DD, RR, BB, false>), grid, dim3(kSB), 0, s, C);   \
     else hipLaunchKernelGGL((k_xstage<T, DD, RR, BB>), grid, dim3(kSB), 0, s, C);                   \
     SGDG_CHECK_HIP(hipGetLastError());                                                              \
     return;                                                                                         \
