@@ -319,12 +319,16 @@ void sgdg_net_destroy(sgdg_net n);
 
 /* Launch configuration of the operator application.  variant 0: split
  * application (v-stage, upper-partner and x-stage passes) with
- * vectors_per_thread vectors per thread; variant 1: fused box tiles with
- * x-boxes of xbox nodes per axis. */
+ * vectors_per_thread vectors per thread, and block_map 1 to give each of the
+ * chip's 8 XCDs one contiguous range of blocks (0: the hardware's round-robin
+ * order); variant 2: the same with the x-stage on LDS tiles (tiles for 1 or 2
+ * vectors per thread; with 4 the x-stage runs per point); variant 1: fused
+ * box tiles with x-boxes of xbox nodes per axis. */
 typedef struct {
   int variant;
   int vectors_per_thread;
   int xbox;
+  int block_map;
   double ms;        /* measured time of one full application with this configuration */
   int from_cache;   /* 1 if taken from the tuning cache without measuring */
 } sgdg_tune_result;
@@ -340,9 +344,10 @@ sgdg_status sgdg_tune(sgdg_ops o, sgdg_dtype t, int batch, int reps, int force, 
                       hipStream_t s);
 /* The same for a multi-problem batch (one vector per problem). */
 sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int force, sgdg_tune_result* out, hipStream_t s);
-/* Sets the launch configuration directly (variant 0: vectors_per_thread in
- * {1, 2, 4}, 1 for d = 3; variant 1: xbox >= 1, shrunk to the LDS budget).
- * SGDG_E_ARG on other values.  ms and from_cache are ignored. */
+/* Sets the launch configuration directly (variants 0 and 2:
+ * vectors_per_thread in {1, 2, 4}, 1 for d = 3, block_map 0 or 1; variant 1:
+ * xbox >= 1, shrunk to the LDS budget).  SGDG_E_ARG on other values.  ms and from_cache are
+ * ignored. */
 sgdg_status sgdg_set_launch(sgdg_ops o, const sgdg_tune_result* cfg);
 
 /* ------------------------------------------------------------ diagnostics -- */

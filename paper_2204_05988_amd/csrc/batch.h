@@ -79,6 +79,14 @@ struct SplitItem {
   int qn;
 };
 
+// A tile of the x-stencil pass: t^d x-nodes from x0 (lattice coordinates)
+// times vb v-nodes from v0, staged in LDS with a one-node x-halo.
+struct TileItem {
+  int prob, grid;
+  int x0[3];
+  int v0, t, vb;
+};
+
 template <class T>
 struct SplitCall {
   const ProbDesc* descs;
@@ -92,6 +100,9 @@ struct SplitCall {
   const T* Qt;
   T* Z;                    // [b][problem: X-group m][grid layout] staged v-stage W^m
   int max_qn;              // largest SplitItem::qn (LDS of the upper-partner pass)
+  const TileItem* tiles;   // x-stencil pass on LDS tiles (ntiles = 0: per-point items)
+  int ntiles;
+  int max_tile;            // largest (t + 2)^d vb of a tile
   int xcd;                 // 1: each XCD takes a contiguous range of (vector group, item) blocks
 };
 

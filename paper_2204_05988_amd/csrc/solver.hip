@@ -44,6 +44,9 @@ struct KindData {
   DevBuf split_items;
   int n_split = 0;
   int max_qn = 0;  // largest coarse range of an item in the upper-partner pass
+  DevBuf tile_items;
+  int n_tile = 0;
+  int max_tile = 0;  // largest staged tile of the x-stencil pass
 };
 
 template <class T>
@@ -68,9 +71,11 @@ struct sgdg_batch_s {
   bool owned_by_ops = false;
   // box-shape choice of the fused kernel per element size (tuned or default)
   int xbox[2] = {0, 0};
-  // operator application variant: 0 split (two streaming passes), 1 fused box tiles
+  // operator application variant: 0 split (streaming passes), 1 fused box
+  // tiles, 2 split with the x-stage on LDS tiles
   int variant = 0;
   int split_bc = 0;  // vectors per thread of the split passes (0: default for d)
+  int split_xcd = 0;  // 1: XCD-contiguous block order in the split passes
   // graphs of grid-problem GMRES cycles
   std::map<std::string, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
@@ -104,8 +109,11 @@ Batch& self_batch(sgdg_ops o) {
     b->d = o->X.dom.d;
     b->R = o->grid->R;
     b->owned_by_ops = true;
-    if (const char* v = getenv("SGDG_APPLY_VARIANT")) b->variant = std::string(v) == "fused" ? 1 : 0;
+    if (const char* v = getenv("SGDG_APPLY_VARIANT"))
+      b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
     if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
+  b->split_xcd = split_xcd();
+    b->split_xcd = split_xcd();
     o->self.reset(b);
   }
   return *o->self;
@@ -163,6 +171,8 @@ static KindData& kind(Batch& B, int k) {
   K.R = R;
   int64_t off = 0, pt = 0, qt = 0, zo = 0, rvb = 0, rxb = 0;
   std::vector<SplitItem> sitems;
+  std::vector<TileItem> titems;
+  bool tiles_ok = true;  // tiles address a grid plane with 32-bit offsets
   for (size_t p = 0; p < B.P.size(); ++p) {
     sgdg_ops o = B.P[p];
     sgdg_grid g = o->grid;
@@ -240,6 +250,35 @@ static KindData& kind(Batch& B, int k) {
         }
         sitems.push_back(it);
       }
+      // x-stencil tiles: t^d x-nodes times vb v-nodes
+      if (plane >= (int64_t(1) << 31)) tiles_ok = false;
+      {
+        const int mxg2 = g->x.axis_nodes(D.G.lx[gi]);
+        int t = 1, vb = 1;
+        split_tile_shape(B.d, mxg2, int(nvg), t, vb);
+        const int ntx = (mxg2 + t - 1) / t;
+        int ntt = 1;
+        for (int a = 0; a < B.d; ++a) ntt *= ntx;
+        for (int tt = 0; tt < ntt; ++tt) {
+          TileItem ti{};
+          ti.prob = int(p);
+          ti.grid = gi;
+          int r = tt;
+          for (int a = B.d - 1; a >= 0; --a) {
+            ti.x0[a] = (r % ntx) * t;
+            r /= ntx;
+          }
+          ti.t = t;
+          ti.vb = vb;
+          int halo = 1;
+          for (int a = 0; a < B.d; ++a) halo *= t + 2;
+          K.max_tile = std::max(K.max_tile, halo * vb);
+          for (int v0 = 0; v0 < nvg; v0 += vb) {
+            ti.v0 = v0;
+            titems.push_back(ti);
+          }
+        }
+      }
     }
     D.rv_off = rvb;
     D.rx_off = rxb;
@@ -270,6 +309,8 @@ static KindData& kind(Batch& B, int k) {
   K.rx_bstride = rxb;
   upload(K.desc, K.host);
   upload(K.split_items, sitems);
+  upload(K.tile_items, titems);
+  K.n_tile = tiles_ok ? int(titems.size()) : 0;
   K.n_split = int(sitems.size());
   return K;
 }
@@ -469,7 +510,10 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
   S.Z = ptr<T>(w.Z);
   S.max_qn = K.max_qn;
-  S.xcd = split_xcd();
+  S.tiles = ptr<TileItem>(K.tile_items);
+  S.ntiles = B.variant == 2 ? K.n_tile : 0;
+  S.max_tile = K.max_tile;
+  S.xcd = B.split_xcd;
   // one vector per thread for single vectors (the solvers); tuned otherwise
   const int bc = nb == 1 ? 1 : (B.split_bc > 0 ? B.split_bc : split_default_bc(B.d));
   for (int stage = 0; stage < 3; ++stage) timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
@@ -1120,24 +1164,23 @@ static void nodal_to_coef(Batch& B, const double* samples, int nq, const double*
 
 // ------------------------------------------------------------ autotuner --
 struct TuneCfg {
-  int variant, bc, xbox;
+  int variant, bc, xbox, xcd;
 };
 
 static std::vector<TuneCfg> tune_candidates(int d) {
   std::vector<TuneCfg> c;
-  if (d == 3) {
-    c.push_back({0, 1, 0});
-  } else {
-    for (int bc : {1, 2, 4}) c.push_back({0, bc, 0});
-  }
+  for (int variant : {0, 2})
+    for (int bc : {1, 2, 4})
+      for (int xcd : {0, 1})
+        if (bc == 1 || (d < 3 && (variant == 0 || bc == 2))) c.push_back({variant, bc, 0, xcd});
   const int base = d == 1 ? 32 : (d == 2 ? 8 : 4);
-  for (int xb : {base / 2, base, base * 2}) c.push_back({1, 0, xb});
+  for (int xb : {base / 2, base, base * 2}) c.push_back({1, 0, xb, 0});
   return c;
 }
 
 static std::string tune_key(const Batch& B, int elem, int nb) {
   std::ostringstream k;
-  k << "d" << B.d << "_R" << B.R << "_e" << elem << "_b" << nb << "_p" << B.P.size() << "_g";
+  k << "v2_d" << B.d << "_R" << B.R << "_e" << elem << "_b" << nb << "_p" << B.P.size() << "_g";
   for (sgdg_ops o : B.P) {
     for (const auto& gd : o->grid->up) k << gd.lx << "." << gd.lv << ",";
     k << (o->grid->x.periodic ? "P" : "N") << (o->grid->v.periodic ? "P" : "N") << ";";
@@ -1160,7 +1203,7 @@ static bool tune_lookup(const std::string& key, TuneCfg& cfg, double& ms) {
     std::string k;
     TuneCfg c{};
     double t = 0;
-    if (in >> k >> c.variant >> c.bc >> c.xbox >> t && k == key) {
+    if (in >> k >> c.variant >> c.bc >> c.xbox >> c.xcd >> t && k == key) {
       cfg = c;
       ms = t;
       found = true;
@@ -1174,12 +1217,13 @@ static void tune_store(const std::string& key, const TuneCfg& c, double ms) {
   const size_t slash = path.find_last_of('/');
   if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << c.variant << " " << c.bc << " " << c.xbox << " " << ms << "\n";
+  if (f) f << key << " " << c.variant << " " << c.bc << " " << c.xbox << " " << c.xcd << " " << ms << "\n";
 }
 
 static void set_cfg(Batch& B, const TuneCfg& c) {
   B.variant = c.variant;
   B.split_bc = c.bc;
+  B.split_xcd = c.xcd;
   if (c.variant == 1 && (B.xbox[0] != c.xbox || B.xbox[1] != c.xbox)) {
     SGDG_CHECK_HIP(hipDeviceSynchronize());
     B.xbox[0] = B.xbox[1] = c.xbox;
@@ -1213,7 +1257,7 @@ static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t
   double best_ms = 0;
   if (!force && tune_lookup(key, best, best_ms)) {
     set_cfg(B, best);
-    r = {best.variant, best.bc, best.xbox, best_ms, 1};
+    r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 1};
     return r;
   }
   const int64_t n = kind(B, K_FULL).total * nb;
@@ -1243,7 +1287,7 @@ static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t
   set_cfg(B, best);
   SGDG_CHECK_HIP(hipStreamSynchronize(s));
   tune_store(key, best, best_ms);
-  r = {best.variant, best.bc, best.xbox, best_ms, 0};
+  r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 0};
   return r;
 }
 
@@ -1371,8 +1415,10 @@ extern "C" sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch*
   b->P.assign(ops, ops + n);
   b->d = d;
   b->R = r + 1;
-  if (const char* v = getenv("SGDG_APPLY_VARIANT")) b->variant = std::string(v) == "fused" ? 1 : 0;
+  if (const char* v = getenv("SGDG_APPLY_VARIANT"))
+    b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
   if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
+  b->split_xcd = split_xcd();
   *out = b;
   API_END
 }
@@ -1479,14 +1525,15 @@ extern "C" sgdg_status sgdg_batch_tune(sgdg_batch b, sgdg_dtype t, int reps, int
 extern "C" sgdg_status sgdg_set_launch(sgdg_ops o, const sgdg_tune_result* cfg) {
   API_BEGIN
   require(o != nullptr && cfg != nullptr, "null argument");
-  require(cfg->variant == 0 || cfg->variant == 1, "variant must be 0 (split) or 1 (fused)");
+  require(cfg->variant >= 0 && cfg->variant <= 2, "variant must be 0 (split), 1 (fused) or 2 (split, tiled x-stage)");
   Batch& B = self_batch(o);
-  if (cfg->variant == 0)
+  if (cfg->variant != 1)
     require(cfg->vectors_per_thread == 1 || (B.d < 3 && (cfg->vectors_per_thread == 2 || cfg->vectors_per_thread == 4)),
             "vectors_per_thread must be 1, 2 or 4 (1 for d = 3)");
   else
     require(cfg->xbox >= 1 && cfg->xbox <= 256, "xbox must be 1..256");
-  set_cfg(B, TuneCfg{cfg->variant, cfg->variant == 0 ? cfg->vectors_per_thread : 0,
-                     cfg->variant == 1 ? cfg->xbox : B.xbox[0]});
+  require(cfg->block_map == 0 || cfg->block_map == 1, "block_map must be 0 or 1");
+  set_cfg(B, TuneCfg{cfg->variant, cfg->variant != 1 ? cfg->vectors_per_thread : 0,
+                     cfg->variant == 1 ? cfg->xbox : B.xbox[0], cfg->variant != 1 ? cfg->block_map : 0});
   API_END
 }

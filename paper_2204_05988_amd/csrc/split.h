@@ -12,6 +12,8 @@ namespace sgdg {
 template <class T>
 void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s);
 int split_points_per_item();
+// x-stencil tile (edge t, v-run vb) for a grid with mx nodes per x-axis and nv v-nodes
+void split_tile_shape(int d, int mx, int nv, int& t, int& vb);
 int split_default_bc(int d);
 bool split_vmajor();
 int split_xcd();

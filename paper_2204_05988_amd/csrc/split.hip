@@ -19,6 +19,7 @@
 // factor values of its point are loaded once and reused across them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "split.h"
@@ -29,6 +30,7 @@ namespace {
 
 constexpr int kSB = 256;  // threads (points) per block
 constexpr int kQlIters = 2;  // staged coarse range of an item: at most kQlIters * kSB nodes
+constexpr int kTileIters = 4;  // staged x-stencil tile: at most kTileIters * kSB values per slab
 // slot-major factor tables: entry e of the nodes of one level is contiguous
 template <class T> __device__ __forceinline__ const T* vals(const DevDomain& D);
 template <> __device__ __forceinline__ const double* vals<double>(const DevDomain& D) { return D.tvals; }
@@ -103,48 +105,84 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 #pragma unroll
       for (int e = 0; e < SS; ++e) un[q][s][e] = ub[int64_t(s) * plane + nbv[e]];
   }
-  for (int m = 0; m < op.nxg; ++m) {
-    T w[BC][R];
+  // Terms in X-group order, software-pipelined for d <= 2: the v-factors and
+  // the lower-partner values of term kk + 1 are loaded while term kk is
+  // computed; W^m is stored when its group's last term is done (empty groups
+  // store 0).
+  const int nt = op.xg_start[op.nxg];
+  auto load = [&](int kk, T (&f)[SS], T (&pv)[BC][R][2]) {
+    const int k = op.xg_terms[kk];
+    const T* fp = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
 #pragma unroll
-    for (int q = 0; q < BC; ++q)
+    for (int e = 0; e < SS; ++e) f[e] = fp[int64_t(e) * nv];
+    const int j = op.term_vg[k];
 #pragma unroll
-      for (int s = 0; s < R; ++s) w[q][s] = T(0);
-    for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
-      const int k = op.xg_terms[kk];
-      const T* f = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
-      T fv[SS];
+    for (int q = 0; q < BC; ++q) {
+      const int b = b0 + q < C.B ? b0 + q : b0;
+      const T* pt = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v;
 #pragma unroll
-      for (int e = 0; e < SS; ++e) fv[e] = f[int64_t(e) * nv];
-      const T* tk = tm + int64_t(k) * R * R;
-      T tkv[R * R];
-#pragma unroll
-      for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
-      const int j = op.term_vg[k];
-#pragma unroll
-      for (int q = 0; q < BC; ++q) {
-        const int b = b0 + q < C.B ? b0 + q : b0;
-        const T* pt = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v;
-#pragma unroll
-        for (int s2 = 0; s2 < R; ++s2) {
-          T z = T(0);
-#pragma unroll
-          for (int e = 0; e < SS; ++e) z += fv[e] * un[q][s2][e];
-          if (has_p)
-            z += wx0 * pt[int64_t(s2) * lplane + int64_t(px0) * nv] + wx1 * pt[int64_t(s2) * lplane + int64_t(px1) * nv];
-#pragma unroll
-          for (int s = 0; s < R; ++s) w[q][s] += tkv[s * R + s2] * z;
-        }
+      for (int s2 = 0; s2 < R; ++s2) {
+        pv[q][s2][0] = has_p ? pt[int64_t(s2) * lplane + int64_t(px0) * nv] : T(0);
+        pv[q][s2][1] = has_p ? pt[int64_t(s2) * lplane + int64_t(px1) * nv] : T(0);
       }
     }
+  };
+  T w[BC][R];
+#pragma unroll
+  for (int q = 0; q < BC; ++q)
+#pragma unroll
+    for (int s = 0; s < R; ++s) w[q][s] = T(0);
+  auto store = [&](int m) {
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q;
-      if (b >= C.B) break;
-      T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p;
+      if (b < C.B) {
+        T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p;
 #pragma unroll
-      for (int s = 0; s < R; ++s) zb[int64_t(s) * plane] = w[q][s];
+        for (int s = 0; s < R; ++s) zb[int64_t(s) * plane] = w[q][s];
+      }
+#pragma unroll
+      for (int s = 0; s < R; ++s) w[q][s] = T(0);
     }
+  };
+  constexpr bool kPipe = D <= 2;  // for d = 3 the extra registers cost more occupancy than they hide
+  T fn[SS], pn[BC][R][2];
+  if (kPipe && nt > 0) load(0, fn, pn);
+  int m = 0;
+  for (int kk = 0; kk < nt; ++kk) {
+    T fc[SS], pc[BC][R][2];
+    if constexpr (kPipe) {
+#pragma unroll
+      for (int e = 0; e < SS; ++e) fc[e] = fn[e];
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) {
+          pc[q][s2][0] = pn[q][s2][0];
+          pc[q][s2][1] = pn[q][s2][1];
+        }
+      if (kk + 1 < nt) load(kk + 1, fn, pn);
+    } else {
+      load(kk, fc, pc);
+    }
+    while (kk >= op.xg_start[m + 1]) store(m++);  // empty groups before this term's
+    const T* tk = tm + int64_t(op.xg_terms[kk]) * R * R;
+    T tkv[R * R];
+#pragma unroll
+    for (int i = 0; i < R * R; ++i) tkv[i] = tk[i];
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int s2 = 0; s2 < R; ++s2) {
+        T z = wx0 * pc[q][s2][0] + wx1 * pc[q][s2][1];
+#pragma unroll
+        for (int e = 0; e < SS; ++e) z += fc[e] * un[q][s2][e];
+#pragma unroll
+        for (int s = 0; s < R; ++s) w[q][s] += tkv[s * R + s2] * z;
+      }
+    if (kk + 1 == op.xg_start[m + 1]) store(m++);
   }
+  while (m < op.nxg) store(m++);
 }
 
 // Pass 1b: y = upper-partner part sum_k Tm_k (I (x) V_k E^v) Qt^{m(k)}, with the
@@ -388,10 +426,203 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   }
 }
 
+
+// Pass 2 on tiles: a block owns t^d x-nodes times vb v-nodes and stages W^m
+// on the tile plus a one-node x-halo in LDS (zero outside a non-periodic
+// lattice), so each point's x-stencil reads come from LDS; the next group's
+// halo is fetched into registers while the current one is computed.  Thread
+// (xl, vl) = (tid / vb, tid % vb).  The stencil slots follow the lattice
+// offsets of the Kuhn stencil, like the factor tables.
+template <class T, int D, int R, int BC>
+__global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
+  constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
+  constexpr int KS = kTileIters;
+  extern __shared__ unsigned char split_smem[];
+  T* sz = reinterpret_cast<T*>(split_smem);  // [BC][R][halo nodes][vb]
+  int ii, vg;
+  block_coords(C, ii, vg);
+  const TileItem it = C.tiles[ii];
+  const int b0 = vg * BC;
+  const ProbDesc& A = C.descs[it.prob];
+  const int g = it.grid;
+  const int nx = A.G.nx[g], nv = A.G.nv[g];
+  const int lx = A.G.lx[g];
+  const int mx = A.mx[lx];
+  const bool xper = A.xper != 0;
+  const int64_t plane = int64_t(nx) * nv;
+  const int64_t total = A.G.off[A.G.n];
+  const int t = it.t, vb = it.vb, hw = t + 2;
+  int hn = 1, tn = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    hn *= hw;
+    tn *= t;
+  }
+  const int hsz = hn * vb;  // staged values per (vector, slice)
+  // this thread's output point
+  const int xl = int(threadIdx.x) / vb, vl = int(threadIdx.x) - xl * vb;
+  bool act = xl < tn && it.v0 + vl < nv;
+  int x = 0, hb = 0;
+  {
+    int r = xl, lc[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      lc[a] = r % t;
+      r /= t;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int c = it.x0[a] + lc[a];
+      act = act && c < mx;
+      x = x * mx + c;
+      hb = hb * hw + lc[a] + 1;
+    }
+  }
+  if (!act) x = 0;
+  const int v = act ? it.v0 + vl : 0;
+  int hoff[SS];
+#pragma unroll
+  for (int e = 0; e < SS; ++e) {
+    int o = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) o = o * hw + A.off[e][a];
+    hoff[e] = (hb + o) * vb + vl;
+  }
+  // staging: element w = h vb + wv of a (vector, slice) slab <- plane offset
+  // node(h) nv + v0 + wv, or -1 (zero) outside the lattice
+  int32_t goff[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const int w = int(threadIdx.x) + j * kSB;
+    goff[j] = -1;
+    if (w < hsz) {
+      const int h = w / vb, vv = it.v0 + (w - h * vb);
+      bool ok = vv < nv;
+      int node = 0, r = h, c[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) {
+        c[a] = r % hw + it.x0[a] - 1;
+        r /= hw;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        int cc = c[a];
+        if (xper) cc = cc < 0 ? cc + mx : (cc >= mx ? cc - mx : cc);
+        ok = ok && cc >= 0 && cc < mx;
+        node = node * mx + cc;
+      }
+      if (ok) goff[j] = node * nv + vv;
+    }
+  }
+  const int xlo = int(A.DX.lev_off[lx - A.DX.lmin]);
+  const T* xv = vals<T>(A.DX);
+  const DevOp& op = A.op;
+  T pre[BC * R][KS];
+  auto fetch = [&](int m) {
+#pragma unroll
+    for (int q = 0; q < BC; ++q) {
+      const int b = b0 + q < C.B ? b0 + q : b0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + int64_t(s) * plane;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) pre[q * R + s][j] = goff[j] >= 0 ? zb[goff[j]] : T(0);
+      }
+    }
+  };
+  auto xfac = [&](int m, T (&f)[SS]) {
+    const T* fp = xv + int64_t(op.xg_fac[m]) * A.DX.fac_stride + xlo + x;
+#pragma unroll
+    for (int e = 0; e < SS; ++e) f[e] = fp[int64_t(e) * nx];
+  };
+  T acc[BC][R];
+#pragma unroll
+  for (int q = 0; q < BC; ++q)
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[q][s] = T(0);
+  T xf[SS];
+  fetch(0);
+  xfac(0, xf);
+  for (int m = 0; m < op.nxg; ++m) {
+    __syncthreads();  // the previous group's reads are done
+#pragma unroll
+    for (int i = 0; i < BC * R; ++i)
+#pragma unroll
+      for (int j = 0; j < KS; ++j) {
+        const int w = int(threadIdx.x) + j * kSB;
+        if (w < hsz) sz[i * hsz + w] = pre[i][j];
+      }
+    T xc[SS];
+#pragma unroll
+    for (int e = 0; e < SS; ++e) xc[e] = xf[e];
+    if (m + 1 < op.nxg) {
+      fetch(m + 1);
+      xfac(m + 1, xf);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const T* l = sz + (q * R + s) * hsz;
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < SS; ++e) a += xc[e] * l[hoff[e]];
+          acc[q][s] += a;
+        }
+    }
+  }
+  if (!act) return;
+  const int64_t p = int64_t(x) * nv + v;
+#pragma unroll
+  for (int q = 0; q < BC; ++q) {
+    const int b = b0 + q;
+    if (b >= C.B) break;
+    T* yb = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(R) * A.poff[g] + p;
+#pragma unroll
+    for (int s = 0; s < R; ++s) yb[int64_t(s) * plane] += acc[q][s];  // after the upper-partner pass
+  }
+}
+
 }  // namespace
 
 int split_points_per_item() { return kSB; }
 int split_default_bc(int d) { return d == 3 ? 1 : 2; }
+// Tile edge t (x-nodes per axis) and v-run vb: every thread owns one point
+// (t^d vb <= kSB), the halo box fits the staging registers ((t+2)^d vb <=
+// kTileIters kSB), and among those the shape with the fewest thread slots plus
+// staged in-lattice values wins.
+void split_tile_shape(int d, int mx, int nv, int& t_out, int& vb_out) {
+  auto inlat = [&](int t) {  // in-lattice halo coordinates over the tiles of one axis
+    int64_t s = 0;
+    for (int x0 = 0; x0 < mx; x0 += t) s += std::min(x0 + t + 1, mx) - std::max(x0 - 1, 0);
+    return s;
+  };
+  double best = -1;
+  t_out = 1;
+  vb_out = std::min(nv, kSB);
+  const int cand[] = {8, 16, 32, 64, nv};
+  for (int t = 1; t <= std::min(mx, 16); ++t) {
+    int64_t td = 1, hd = 1, il = 1;
+    for (int a = 0; a < d; ++a) {
+      td *= t;
+      hd *= t + 2;
+      il *= inlat(t);
+    }
+    for (int vb : cand) {
+      if (vb > nv || (vb == nv && nv > 64) || td * vb > kSB || hd * vb > int64_t(kTileIters) * kSB) continue;
+      int64_t ntx = (mx + t - 1) / t, nt = (nv + vb - 1) / vb;
+      for (int a = 0; a < d; ++a) nt *= ntx;
+      const double cost = double(nt) * kSB + double(il) * nv;
+      if (best < 0 || cost < best) {
+        best = cost;
+        t_out = t;
+        vb_out = vb;
+      }
+    }
+  }
+}
 bool split_vmajor() {
   const char* v = getenv("SGDG_SPLIT_ORDER");
   return v && atoi(v) == 1;
@@ -401,8 +632,11 @@ int split_xcd() {
   return v && atoi(v) == 1 ? 1 : 0;
 }
 
-// LDS budget of the upper-partner staging; larger ranges read from memory
+// LDS budgets of the upper-partner staging and of the x-stencil tiles (about a
+// quarter of a CU's LDS, so several blocks share a CU); beyond them the
+// per-point kernels read from memory
 constexpr size_t kQLdsMax = 32 * 1024;
+constexpr size_t kTileLdsMax = 40 * 1024;
 
 template <class T>
 void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStream_t s) {
@@ -411,6 +645,21 @@ void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStre
   size_t lds = 2 * size_t(C.max_qn) * R * bc * sizeof(T);  // two buffers
   const bool ql = stage == 1 && d <= 2 && C.max_qn > 0 && C.max_qn <= kQlIters * kSB && lds <= kQLdsMax;
   if (!ql) lds = 0;
+  const size_t tlds = size_t(C.max_tile) * R * bc * sizeof(T);
+  const bool tiles = stage == 2 && C.ntiles > 0 && bc <= 2 && C.max_tile <= kTileIters * kSB && tlds <= kTileLdsMax;
+  if (tiles) {
+    const dim3 tgrid(unsigned(C.ntiles), unsigned((C.B + bc - 1) / bc));
+#define SGDG_TILE_CASE(DD, RR, BB)                                                                 \
+    if (d == DD && R == RR && bc == BB) {                                                          \
+      hipLaunchKernelGGL((k_xtile<T, DD, RR, BB>), tgrid, dim3(kSB), tlds, s, C);                  \
+      SGDG_CHECK_HIP(hipGetLastError());                                                           \
+      return;                                                                                      \
+    }
+#define SGDG_TILE_R(DD, BB) SGDG_TILE_CASE(DD, 1, BB) SGDG_TILE_CASE(DD, 2, BB) SGDG_TILE_CASE(DD, 3, BB)
+    SGDG_TILE_R(1, 1) SGDG_TILE_R(1, 2) SGDG_TILE_R(2, 1) SGDG_TILE_R(2, 2) SGDG_TILE_R(3, 1)
+#undef SGDG_TILE_R
+#undef SGDG_TILE_CASE
+  }
   dim3 grid(unsigned(C.nitems), unsigned((C.B + bc - 1) / bc));
 #define SGDG_SPLIT_CASE(DD, RR, BB)                                                                 \
   if (d == DD && R == RR && bc == BB) {                                                             \

@@ -67,13 +67,17 @@ class SolveStats(C.Structure):
                 ("pc_applications", C.c_int)]
 
 
+VARIANTS = ("split", "fused", "split_tiled")
+
+
 class TuneResult(C.Structure):
-    _fields_ = [("variant", C.c_int), ("vectors_per_thread", C.c_int), ("xbox", C.c_int), ("ms", C.c_double),
-                ("from_cache", C.c_int)]
+    _fields_ = [("variant", C.c_int), ("vectors_per_thread", C.c_int), ("xbox", C.c_int), ("block_map", C.c_int),
+                ("ms", C.c_double), ("from_cache", C.c_int)]
 
     def as_dict(self):
-        return {"variant": "split" if self.variant == 0 else "fused", "vectors_per_thread": self.vectors_per_thread,
-                "xbox": self.xbox, "ms": self.ms, "from_cache": bool(self.from_cache)}
+        return {"variant": VARIANTS[self.variant], "vectors_per_thread": self.vectors_per_thread,
+                "xbox": self.xbox, "block_map": "xcd" if self.block_map else "round_robin", "ms": self.ms,
+                "from_cache": bool(self.from_cache)}
 
 
 class TrainOpts(C.Structure):
@@ -321,8 +325,8 @@ class SparseGridOps:
                                _stream(stream)))
         return r.as_dict()
 
-    def set_launch(self, variant="split", vectors_per_thread=2, xbox=8):
-        r = TuneResult(0 if variant == "split" else 1, vectors_per_thread, xbox, 0.0, 0)
+    def set_launch(self, variant="split", vectors_per_thread=2, xbox=8, block_map=0):
+        r = TuneResult(VARIANTS.index(variant), vectors_per_thread, xbox, block_map, 0.0, 0)
         _check(lib().sgdg_set_launch(self.ops, C.byref(r)))
 
     def solve_strip(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):

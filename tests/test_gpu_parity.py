@@ -103,19 +103,22 @@ def test_apply_parity(dev, case, kind):
         assert err32 <= 2e-5, err32
 
 
-LAUNCHES = [("split", 1, 8), ("split", 2, 8), ("split", 4, 8), ("fused", 0, 4), ("fused", 0, 8), ("fused", 0, 16)]
+LAUNCHES = [("split", 1, 8, 0), ("split", 2, 8, 0), ("split", 4, 8, 0), ("split", 2, 8, 1),
+            ("split_tiled", 1, 8, 0), ("split_tiled", 2, 8, 0), ("split_tiled", 1, 8, 1),
+            ("fused", 0, 4, 0), ("fused", 0, 8, 0), ("fused", 0, 16, 0)]
 
 
 @pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1p", "tiny_d2", "tiny_d3", "c1", "c2_L5", "c5_L5"])
-@pytest.mark.parametrize("launch", LAUNCHES, ids=lambda l: f"{l[0]}{l[1] if l[0] == 'split' else l[2]}")
+@pytest.mark.parametrize("launch", LAUNCHES,
+                         ids=lambda l: f"{l[0]}{l[2] if l[0] == 'fused' else l[1]}{'x' if l[3] else ''}")
 def test_apply_launch_configs(dev, case, launch):
     """Every launch configuration the tuner may pick computes the same operator (FP64 and FP32, batch 3)."""
     from paper_2204_05988_amd import sgdg
     w, P, ops = _problem(case, CASES[case])
-    variant, bc, xb = launch
-    if variant == "split" and w.d == 3 and bc != 1:
+    variant, bc, xb, bmap = launch
+    if variant != "fused" and w.d == 3 and bc != 1:
         pytest.skip("d = 3 runs one vector per thread")
-    ops.set_launch(variant, bc, xb)
+    ops.set_launch(variant, bc, xb, bmap)
     try:
         B = 3
         u = random_vector(P.ndof, 31, batch=B)
