@@ -5,9 +5,10 @@
 
 namespace sgdg {
 
-// one step of both partner-sum scans over every problem of the batch
+// one step of both partner-sum scans over every problem of the batch, the
+// factor groups split over `chunks` blocks per item
 template <class T>
-void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, hipStream_t s);
+void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, int chunks, hipStream_t s);
 // the box-tiled accumulation over all grids of all problems (one launch)
 template <class T>
 void fused_tiles(const FusedCall<T>& C, int d, int R, hipStream_t s);

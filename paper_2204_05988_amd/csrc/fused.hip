@@ -21,6 +21,8 @@
 // when the staged values are fetched.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fused.h"
 
 namespace sgdg {
@@ -359,6 +361,10 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   const bool lower = si.side == 0;
   const int b = blockIdx.y;
   const DevOp& op = A.op;
+  // blockIdx.z: this block's share of the factor groups (shorter dependent
+  // chains per thread, more blocks for the small steps)
+  const int ng = lower ? op.nvg : op.nxg;
+  const int g0 = int(blockIdx.z) * ng / int(gridDim.z), g1 = int(blockIdx.z + 1) * ng / int(gridDim.z);
   const int lg = si.lg;
   const int64_t ltotal = L.off[L.n];
   T* Ptb = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off;
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvt]);
       }
       const int64_t splane = int64_t(nxs) * nvs;
-      for (int j = 0; j < op.nvg; ++j)
+      for (int j = g0; j < g1; ++j)
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(s) * splane + int64_t(xc) * nvs;
@@ -409,7 +415,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxt]);
       }
       const int64_t splane = int64_t(nxs) * nvs;
-      for (int m = 0; m < op.nxg; ++m)
+      for (int m = g0; m < g1; ++m)
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(s) * splane + vq;
@@ -456,7 +462,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
         for (int o = 0; o < W; ++o) un[q][o] = us[wi[o]];
       }
-      for (int j = 0; j < op.nvg; ++j) {
+      for (int j = g0; j < g1; ++j) {
         const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + v;
         T rr[W];
 #pragma unroll
@@ -506,7 +512,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
         for (int o = 0; o < W; ++o) un[q][o] = us[int64_t(wi[o]) * nv];
       }
-      for (int m = 0; m < op.nxg; ++m) {
+      for (int m = g0; m < g1; ++m) {
         const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + x;
         T rr[W];
 #pragma unroll
@@ -530,9 +536,9 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 
 // ------------------------------------------------------------- launchers --
 template <class T>
-void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, hipStream_t s) {
+void fused_scan_step(const FusedCall<T>& C, int nsitems, int d, int R, int chunks, hipStream_t s) {
   if (nsitems == 0) return;
-  dim3 grid(unsigned(nsitems), C.B);
+  dim3 grid(unsigned(nsitems), C.B, unsigned(std::max(1, chunks)));
 #define SGDG_SCAN_CASE(DD, RR) \
   if (d == DD && R == RR) hipLaunchKernelGGL((k_scan2<T, DD, RR>), grid, dim3(kFB), 0, s, C);
   SGDG_SCAN_CASE(1, 1) SGDG_SCAN_CASE(1, 2) SGDG_SCAN_CASE(1, 3)
@@ -556,8 +562,8 @@ void fused_tiles(const FusedCall<T>& C, int d, int R, hipStream_t s) {
   SGDG_CHECK_HIP(hipGetLastError());
 }
 
-template void fused_scan_step<double>(const FusedCall<double>&, int, int, int, hipStream_t);
-template void fused_scan_step<float>(const FusedCall<float>&, int, int, int, hipStream_t);
+template void fused_scan_step<double>(const FusedCall<double>&, int, int, int, int, hipStream_t);
+template void fused_scan_step<float>(const FusedCall<float>&, int, int, int, int, hipStream_t);
 template void fused_tiles<double>(const FusedCall<double>&, int, int, hipStream_t);
 template void fused_tiles<float>(const FusedCall<float>&, int, int, hipStream_t);
 

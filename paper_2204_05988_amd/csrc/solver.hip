@@ -76,6 +76,7 @@ struct sgdg_batch_s {
   int variant = 0;
   int split_bc = 0;  // vectors per thread of the split passes (0: default for d)
   int split_xcd = 0;  // 1: XCD-contiguous block order in the split passes
+  int scan_chunks = 1;  // blocks sharing the factor groups of a scan item
   // graphs of grid-problem GMRES cycles
   std::map<std::string, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
@@ -113,7 +114,10 @@ Batch& self_batch(sgdg_ops o) {
       b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
     if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
   b->split_xcd = split_xcd();
+  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
     b->split_xcd = split_xcd();
+  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
+    if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
     o->self.reset(b);
   }
   return *o->self;
@@ -486,7 +490,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
       for (size_t t = 0; t < I.step_first.size(); ++t) {
         FusedCall<T> Cs = C;
         Cs.sitems = C.sitems + I.step_first[t];
-        fused_scan_step<T>(Cs, I.step_count[t], B.d, K.R, s);
+        fused_scan_step<T>(Cs, I.step_count[t], B.d, K.R, B.scan_chunks, s);
       }
     });
   }
@@ -1419,6 +1423,7 @@ extern "C" sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch*
     b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
   if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
   b->split_xcd = split_xcd();
+  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
   *out = b;
   API_END
 }

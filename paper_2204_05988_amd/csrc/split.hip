@@ -31,6 +31,7 @@ namespace {
 constexpr int kSB = 256;  // threads (points) per block
 constexpr int kQlIters = 2;  // staged coarse range of an item: at most kQlIters * kSB nodes
 constexpr int kTileIters = 4;  // staged x-stencil tile: at most kTileIters * kSB values per slab
+constexpr int kTileFacIters = 2;  // staged x-factors of a tile: at most kTileFacIters * kSB values
 // slot-major factor tables: entry e of the nodes of one level is contiguous
 template <class T> __device__ __forceinline__ const T* vals(const DevDomain& D);
 template <> __device__ __forceinline__ const double* vals<double>(const DevDomain& D) { return D.tvals; }
@@ -514,7 +515,7 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
       if (ok) goff[j] = node * nv + vv;
     }
   }
-  const int xlo = int(A.DX.lev_off[lx - A.DX.lmin]);
+  const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
   const T* xv = vals<T>(A.DX);
   const DevOp& op = A.op;
   T pre[BC * R][KS];
@@ -530,19 +531,54 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
       }
     }
   };
-  auto xfac = [&](int m, T (&f)[SS]) {
-    const T* fp = xv + int64_t(op.xg_fac[m]) * A.DX.fac_stride + xlo + x;
+  // The group's x-factor values: for d = 3 (15 slots) the tile's nodes are
+  // staged after the halo (element f = e tn + xi, slot e of tile node xi; -1
+  // outside the lattice) and read from LDS; for d <= 2 each thread loads its
+  // node's slots directly, which measured faster there.
+  constexpr bool kFacLds = D == 3;
+  T* sf = sz + BC * R * hsz;
+  const int nf = SS * tn;
+  int32_t fidx[kTileFacIters];
 #pragma unroll
-    for (int e = 0; e < SS; ++e) f[e] = fp[int64_t(e) * nx];
+  for (int j = 0; j < kTileFacIters; ++j) {
+    const int f = int(threadIdx.x) + j * kSB;
+    fidx[j] = -1;
+    if (kFacLds && f < nf) {
+      const int e = f / tn, xi = f - e * tn;
+      int r = xi, node = 0, lc[3] = {0, 0, 0};
+      bool ok = true;
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) {
+        lc[a] = r % t;
+        r /= t;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int c = it.x0[a] + lc[a];
+        ok = ok && c < mx;
+        node = node * mx + c;
+      }
+      if (ok) fidx[j] = e * nx + node;
+    }
+  }
+  T fpre[kFacLds ? kTileFacIters : SS];
+  auto ffetch = [&](int m) {
+    const T* fp = xv + int64_t(op.xg_fac[m]) * A.DX.fac_stride + xlo;
+    if constexpr (kFacLds) {
+#pragma unroll
+      for (int j = 0; j < kTileFacIters; ++j) fpre[j] = fidx[j] >= 0 ? fp[fidx[j]] : T(0);
+    } else {
+#pragma unroll
+      for (int e = 0; e < SS; ++e) fpre[e] = fp[int64_t(e) * nx + x];
+    }
   };
   T acc[BC][R];
 #pragma unroll
   for (int q = 0; q < BC; ++q)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
-  T xf[SS];
   fetch(0);
-  xfac(0, xf);
+  ffetch(0);
   for (int m = 0; m < op.nxg; ++m) {
     __syncthreads();  // the previous group's reads are done
 #pragma unroll
@@ -553,14 +589,26 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
         if (w < hsz) sz[i * hsz + w] = pre[i][j];
       }
     T xc[SS];
+    if constexpr (kFacLds) {
 #pragma unroll
-    for (int e = 0; e < SS; ++e) xc[e] = xf[e];
+      for (int j = 0; j < kTileFacIters; ++j) {
+        const int f = int(threadIdx.x) + j * kSB;
+        if (f < nf) sf[f] = fpre[j];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < SS; ++e) xc[e] = fpre[e];
+    }
     if (m + 1 < op.nxg) {
       fetch(m + 1);
-      xfac(m + 1, xf);
+      ffetch(m + 1);
     }
     __syncthreads();
     if (act) {
+      if constexpr (kFacLds) {
+#pragma unroll
+        for (int e = 0; e < SS; ++e) xc[e] = sf[e * tn + xl];
+      }
 #pragma unroll
       for (int q = 0; q < BC; ++q)
 #pragma unroll
@@ -611,7 +659,10 @@ void split_tile_shape(int d, int mx, int nv, int& t_out, int& vb_out) {
       il *= inlat(t);
     }
     for (int vb : cand) {
-      if (vb > nv || (vb == nv && nv > 64) || td * vb > kSB || hd * vb > int64_t(kTileIters) * kSB) continue;
+      const int ss = d == 1 ? 3 : (d == 2 ? 7 : 15);
+      if (vb > nv || (vb == nv && nv > 64) || td * vb > kSB || hd * vb > int64_t(kTileIters) * kSB ||
+          td * ss > int64_t(kTileFacIters) * kSB)
+        continue;
       int64_t ntx = (mx + t - 1) / t, nt = (nv + vb - 1) / vb;
       for (int a = 0; a < d; ++a) nt *= ntx;
       const double cost = double(nt) * kSB + double(il) * nv;
@@ -645,7 +696,7 @@ void split_stage(const SplitCall<T>& C, int d, int R, int bc, int stage, hipStre
   size_t lds = 2 * size_t(C.max_qn) * R * bc * sizeof(T);  // two buffers
   const bool ql = stage == 1 && d <= 2 && C.max_qn > 0 && C.max_qn <= kQlIters * kSB && lds <= kQLdsMax;
   if (!ql) lds = 0;
-  const size_t tlds = size_t(C.max_tile) * R * bc * sizeof(T);
+  const size_t tlds = (size_t(C.max_tile) * R * bc + (d == 3 ? size_t(kTileFacIters) * kSB : 0)) * sizeof(T);
   const bool tiles = stage == 2 && C.ntiles > 0 && bc <= 2 && C.max_tile <= kTileIters * kSB && tlds <= kTileLdsMax;
   if (tiles) {
     const dim3 tgrid(unsigned(C.ntiles), unsigned((C.B + bc - 1) / bc));
