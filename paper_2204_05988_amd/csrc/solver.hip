@@ -762,6 +762,12 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
           << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b;
       auto g = B.graphs.find(key.str());
       if (g == B.graphs.end()) {
+        // One eager application of M and A first: workspaces and item tables
+        // are created on first use, and allocation and table uploads cannot be
+        // captured.  Its result is overwritten by the cycle.
+        M(V, tmp, s);
+        A(tmp, w, s);
+        SGDG_CHECK_HIP(hipStreamSynchronize(s));
         // capture on a private stream (the caller's may be the null stream, which cannot be captured)
         if (!B.cap_stream) SGDG_CHECK_HIP(hipStreamCreate(&B.cap_stream));
         const bool prof = B.prof;

@@ -161,3 +161,22 @@ def test_graph_solve_matches_eager(dev):
         assert res <= 2e-10
         assert dist <= 1e-7
     ops.close()
+
+
+def test_graph_solve_on_fresh_handle(dev):
+    """The first solve of a fresh handle may be a captured one: workspaces the
+    apply creates on first use exist before the capture starts."""
+    from paper_2204_05988_amd import sgdg
+    w = config_c2(L=5)
+    P = Problem(w)
+    ops = sgdg.SparseGridOps(w)
+    bref = P.apply(random_vector(P.ndof, 6)[0])
+    b = torch.tensor(bref, device=dev)
+    _say("graph strip solve on a fresh handle c2_L5")
+    xg, stg = ops.solve_strip(b, torch.zeros_like(b), sgdg.default_solve_opts(rtol=1e-10, maxit=200, use_graph=True))
+    torch.cuda.synchronize()
+    res = np.linalg.norm(bref - P.apply(xg.cpu().numpy())) / np.linalg.norm(bref)
+    _say(f"  outer {stg.outer_iters}, oracle residual {res:.2e}")
+    assert res <= 2e-10
+    ops.close()
+
