@@ -135,6 +135,6 @@ struct BlockRef {  // one block of a segmented launch
   int seg, chunk;
 };
 
-constexpr int kChunk = 1024;  // elements per block in segmented launches
+constexpr int kChunk = 512;  // elements per block in segmented launches
 
 }  // namespace sgdg

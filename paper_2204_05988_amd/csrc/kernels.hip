@@ -63,7 +63,26 @@ __global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__
   double* out = partial + int64_t(S.chunk0 + br.chunk) * nvec;
   for (int k0 = 0; k0 < nvec; k0 += kMaxVec) {
     const int nk = nvec - k0 < kMaxVec ? nvec - k0 : kMaxVec;
-    for (int k = 0; k < nk; ++k) {
+    // four vectors at a time: their loads and wave reductions overlap
+    int k = 0;
+    for (; k + 4 <= nk; k += 4) {
+      double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
+        if (i < end) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += double(V[int64_t(k0 + k + q) * vstride + i]) * wl[t];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh[wv][k + q] = acc[q];
+      }
+    }
+    for (; k < nk; ++k) {
       const T* vk = V + int64_t(k0 + k) * vstride;
       double acc = 0;
 #pragma unroll
@@ -102,7 +121,16 @@ __global__ void __launch_bounds__(kBlock) k_seg_axpy(const SegInfo* __restrict__
     const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
     if (i < end) {
       double a = double(w[i]);
-      for (int k = 0; k < nvec; ++k) a += sign * c[k] * double(V[int64_t(k) * vstride + i]);
+      // four independent loads in flight per step; the sum keeps the order k = 0, 1, ...
+      int k = 0;
+      for (; k + 4 <= nvec; k += 4) {
+        double v4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v4[q] = double(V[int64_t(k + q) * vstride + i]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a += sign * c[k + q] * v4[q];
+      }
+      for (; k < nvec; ++k) a += sign * c[k] * double(V[int64_t(k) * vstride + i]);
       const T r = T(a);
       w[i] = r;
       nrm += double(r) * double(r);
