@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 #pragma unroll
       for (int e = 0; e < SS; ++e) un[q][s][e] = ub[int64_t(s) * plane + nbv[e]];
   }
-  // Terms in X-group order, software-pipelined for d <= 2: the v-factors and
+  // Terms in X-group order, software-pipelined for d <= 2 and BC > 1: the v-factors and
   // the lower-partner values of term kk + 1 are loaded while term kk is
   // computed; W^m is stored when its group's last term is done (empty groups
   // store 0).
@@ -146,7 +146,9 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
       for (int s = 0; s < R; ++s) w[q][s] = T(0);
     }
   };
-  constexpr bool kPipe = D <= 2;  // for d = 3 the extra registers cost more occupancy than they hide
+  // for d = 3, and for one vector per thread, the extra registers cost more
+  // occupancy than the pipelining hides (measured)
+  constexpr bool kPipe = D <= 2 && BC > 1;
   T fn[SS], pn[BC][R][2];
   if (kPipe && nt > 0) load(0, fn, pn);
   int m = 0;
