@@ -43,6 +43,22 @@ template <class T> __device__ __forceinline__ const T* tmat(const DevOp& op);
 template <> __device__ __forceinline__ const double* tmat<double>(const DevOp& op) { return op.term_tm; }
 template <> __device__ __forceinline__ const float* tmat<float>(const DevOp& op) { return op.term_tm32; }
 
+// The staged W keeps the R slices of a point contiguous ([grid][x][v][R]), so
+// the x-stage reads a pair of slices with one 2-wide load (half the memory
+// instructions).
+template <class T, int R>
+__device__ __forceinline__ void load_slices(const T* p, T (&v)[R]) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  int s = 0;
+#pragma unroll
+  for (; s + 2 <= R; s += 2) {
+    const T2 a = *reinterpret_cast<const T2*>(p + s);
+    v[s] = a.x;
+    v[s + 1] = a.y;
+  }
+  if constexpr (R % 2 == 1) v[R - 1] = p[R - 1];
+}
+
 // Item and vector group of this block.  With C.xcd the linear block id is
 // remapped so that XCD k (blocks are dealt to the 8 XCDs round-robin) runs one
 // contiguous range of (vector group, item) pairs and its L2 sees neighbouring
@@ -138,9 +154,11 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q;
       if (b < C.B) {
-        T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p;
+        // W is read once, by the x-stage pass: stream it past the caches (a
+        // 2-wide store of the slice pair measured slower than two scalar ones)
+        T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p * R;
 #pragma unroll
-        for (int s = 0; s < R; ++s) zb[int64_t(s) * plane] = w[q][s];
+        for (int s = 0; s < R; ++s) __builtin_nontemporal_store(w[q][s], zb + s);
       }
 #pragma unroll
       for (int s = 0; s < R; ++s) w[q][s] = T(0);
@@ -409,14 +427,19 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q < C.B ? b0 + q : b0;
-      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + v;
+      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + int64_t(v) * R;
+      T t[R];
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        T t = T(0);
+      for (int s = 0; s < R; ++s) t[s] = T(0);
 #pragma unroll
-        for (int e = 0; e < SS; ++e) t += xf[e] * zb[int64_t(s) * plane + int64_t(nbx[e]) * nv];
-        acc[q][s] += t;
+      for (int e = 0; e < SS; ++e) {
+        T zz[R];
+        load_slices<T, R>(zb + int64_t(nbx[e]) * nv * R, zz);
+#pragma unroll
+        for (int s = 0; s < R; ++s) t[s] += xf[e] * zz[s];
       }
+#pragma unroll
+      for (int s = 0; s < R; ++s) acc[q][s] += t[s];
     }
   }
 #pragma unroll
@@ -525,11 +548,18 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q < C.B ? b0 + q : b0;
+      const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g];
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + int64_t(s) * plane;
+      for (int j = 0; j < KS; ++j) {
+        T zz[R];
+        if (goff[j] >= 0) {
+          load_slices<T, R>(zb + int64_t(goff[j]) * R, zz);
+        } else {
 #pragma unroll
-        for (int j = 0; j < KS; ++j) pre[q * R + s][j] = goff[j] >= 0 ? zb[goff[j]] : T(0);
+          for (int s = 0; s < R; ++s) zz[s] = T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < R; ++s) pre[q * R + s][j] = zz[s];
       }
     }
   };
