@@ -204,7 +204,6 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
 
   // ---------------- diagonal + lower partners, one V-group at a time -------
   const int gl = g - 1;  // lower grid holding Pt_g: (lx-1, lv)
-  const int64_t lplane = has_p ? int64_t(A.Gl.nx[gl]) * nv : 0;
   const int64_t ltotal = A.Gl.off[A.Gl.n];
   const int64_t po = has_p ? A.DX.par_off[lx - A.DX.lmin] : 0;
   for (int j = 0; j < op.nvg; ++j) {
@@ -213,7 +212,8 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
       T fvv[SS];
 #pragma unroll
       for (int e = 0; e < SS; ++e) fvv[e] = vf[e];
-      const T* pt = has_p ? C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + A.Gl.off[gl] + vi
+      const T* pt = has_p ? C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + A.Gl.off[gl] +
+                                int64_t(vi) * R
                           : nullptr;
       for (int r = rg; r < nxh; r += nrg) {
         const int xi = xh_node[r];
@@ -226,9 +226,9 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
             for (int e = 0; e < SS; ++e) z += fvv[e] * urow[dvh[e]];
             if (has_p) {
               const int64_t pp = po + 2 * int64_t(xi);
-              const T* pr = pt + int64_t(s) * lplane;
-              z += T(A.DX.parw[pp]) * pr[int64_t(A.DX.par[pp]) * nv] +
-                   T(A.DX.parw[pp + 1]) * pr[int64_t(A.DX.par[pp + 1]) * nv];
+              const T* pr = pt + s;
+              z += T(A.DX.parw[pp]) * pr[int64_t(A.DX.par[pp]) * nv * R] +
+                   T(A.DX.parw[pp + 1]) * pr[int64_t(A.DX.par[pp + 1]) * nv * R];
             }
           }
           stg[(s * nxh + r) * nvb + col] = z;
@@ -270,7 +270,6 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
   // ---------------- upper partners, one X-group at a time ------------------
   if (has_q) {
     const int nvl = A.Gl.nv[g];  // lower grid g: (lx, lv-1)
-    const int64_t qplane = int64_t(nx) * nvl;
     const int64_t vpo = A.DV.par_off[lv - A.DV.lmin];
     const int nst = nxb * nvh;
     for (int m = 0; m < op.nxg; ++m) {
@@ -284,8 +283,8 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
           T z = T(0);
           if (vn >= 0) {
             const int64_t pp = vpo + 2 * int64_t(vn);
-            const T* qr = qt + int64_t(s) * qplane + int64_t(xi) * nvl;
-            z = T(A.DV.parw[pp]) * qr[A.DV.par[pp]] + T(A.DV.parw[pp + 1]) * qr[A.DV.par[pp + 1]];
+            const T* qr = qt + int64_t(xi) * nvl * R + s;
+            z = T(A.DV.parw[pp]) * qr[int64_t(A.DV.par[pp]) * R] + T(A.DV.parw[pp + 1]) * qr[int64_t(A.DV.par[pp + 1]) * R];
           }
           stg[(s * nxb + r) * nvh + c] = z;
         }
@@ -388,19 +387,18 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         ch[c] = A.DV.tchi[co + int64_t(c) * nvt];
         cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvt]);
       }
-      const int64_t splane = int64_t(nxs) * nvs;
       for (int j = g0; j < g1; ++j)
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(s) * splane + int64_t(xc) * nvs;
+          const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(xc) * nvs * R + s;
           T acc = T(0);
 #pragma unroll
-          for (int c = 0; c < SS; ++c) acc += cw[c] * row[ch[c]];
-          Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(s) * n + e] = acc;
+          for (int c = 0; c < SS; ++c) acc += cw[c] * row[int64_t(ch[c]) * R];
+          Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + e * R + s] = acc;
         }
     } else {
       // Rx_l[xc][vq] = sum_c chiw_c(xc) Qt_{l+1}[chi_c(xc)][vq], xc on the target's x-level
-      const int nxt = L.nx[lg], nxs = L.nx[lg + 1], nvs = L.nv[lg + 1];
+      const int nxt = L.nx[lg], nvs = L.nv[lg + 1];
       const int64_t n = int64_t(nxt) * nvs;
       const int64_t e = si.start + threadIdx.x;
       if (e >= n) return;
@@ -414,15 +412,14 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         ch[c] = A.DX.tchi[co + int64_t(c) * nxt];
         cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxt]);
       }
-      const int64_t splane = int64_t(nxs) * nvs;
       for (int m = g0; m < g1; ++m)
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(s) * splane + vq;
+          const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(vq) * R + s;
           T acc = T(0);
 #pragma unroll
-          for (int c = 0; c < SS; ++c) acc += cw[c] * col[int64_t(ch[c]) * nvs];
-          Rxb[int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(s) * n + e] = acc;
+          for (int c = 0; c < SS; ++c) acc += cw[c] * col[int64_t(ch[c]) * nvs * R];
+          Rxb[int64_t(m) * A.rx_len + A.rxo[lg] + e * R + s] = acc;
         }
     }
     return;
@@ -445,14 +442,12 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
     const bool has_p = src > 0;
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
-    int64_t rn = 0;
     if (has_p) {
       const int64_t po = A.DX.par_off[G.lx[src] - A.DX.lmin] + 2 * int64_t(x);
       p0 = A.DX.par[po];
       p1 = A.DX.par[po + 1];
       w0 = T(A.DX.parw[po]);
       w1 = T(A.DX.parw[po + 1]);
-      rn = int64_t(L.nx[src - 1]) * nvl;
     }
     for (int s0 = 0; s0 < R; s0 += RS) {
       T un[RS][W];
@@ -474,10 +469,10 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
           if (has_p) {
-            const T* rvp = Rvb + int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(s) * rn + v;
-            acc += w0 * rvp[int64_t(p0) * nvl] + w1 * rvp[int64_t(p1) * nvl];
+            const T* rvp = Rvb + int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(v) * R + s;
+            acc += w0 * rvp[int64_t(p0) * nvl * R] + w1 * rvp[int64_t(p1) * nvl * R];
           }
-          Ptb[int64_t(j) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
+          Ptb[int64_t(j) * ltotal + L.off[lg] + pt * R + s] = acc;
         }
       }
     }
@@ -494,7 +489,6 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
     int nvq = 0;
-    int64_t rn = 0;
     if (has_q) {
       const int64_t po = A.DV.par_off[G.lv[src] - A.DV.lmin] + 2 * int64_t(v);
       p0 = A.DV.par[po];
@@ -502,7 +496,6 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       w0 = T(A.DV.parw[po]);
       w1 = T(A.DV.parw[po + 1]);
       nvq = L.nv[src];
-      rn = int64_t(nxl) * nvq;
     }
     for (int s0 = 0; s0 < R; s0 += RS) {
       T un[RS][W];
@@ -524,10 +517,10 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
           if (has_q) {
-            const T* rxp = Rxb + int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(s) * rn + int64_t(x) * nvq;
-            acc += w0 * rxp[p0] + w1 * rxp[p1];
+            const T* rxp = Rxb + int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(x) * nvq * R + s;
+            acc += w0 * rxp[int64_t(p0) * R] + w1 * rxp[int64_t(p1) * R];
           }
-          Qtb[int64_t(m) * ltotal + L.off[lg] + int64_t(s) * lplane + pt] = acc;
+          Qtb[int64_t(m) * ltotal + L.off[lg] + pt * R + s] = acc;
         }
       }
     }

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const bool has_p = !A.diag_only && g > 0;
   int32_t px0 = 0, px1 = 0;
   T wx0 = 0, wx1 = 0;
-  int64_t lo = 0, lplane = 0;
+  int64_t lo = 0;
   if (has_p) {
     const int64_t pp = A.DX.par_off[lx - A.DX.lmin] + 2 * int64_t(x);
     px0 = A.DX.par[pp];
@@ -106,7 +106,6 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
     wx0 = T(A.DX.parw[pp]);
     wx1 = T(A.DX.parw[pp + 1]);
     lo = A.Gl.off[g - 1];
-    lplane = int64_t(A.Gl.nx[g - 1]) * nv;
   }
   const int64_t total = A.G.off[A.G.n];
   const int64_t ltotal = A.Gl.off[A.Gl.n];
@@ -136,11 +135,19 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q < C.B ? b0 + q : b0;
-      const T* pt = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + v;
+      const T* pt = C.Pt + int64_t(b) * C.pt_bstride + A.pt_off + int64_t(j) * ltotal + lo + int64_t(v) * R;
+      T a0[R], a1[R];
+      if (has_p) {
+        load_slices<T, R>(pt + int64_t(px0) * nv * R, a0);
+        load_slices<T, R>(pt + int64_t(px1) * nv * R, a1);
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) a0[s2] = a1[s2] = T(0);
+      }
 #pragma unroll
       for (int s2 = 0; s2 < R; ++s2) {
-        pv[q][s2][0] = has_p ? pt[int64_t(s2) * lplane + int64_t(px0) * nv] : T(0);
-        pv[q][s2][1] = has_p ? pt[int64_t(s2) * lplane + int64_t(px1) * nv] : T(0);
+        pv[q][s2][0] = a0[s2];
+        pv[q][s2][1] = a1[s2];
       }
     }
   };
@@ -242,7 +249,6 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
   const bool has_q = !A.diag_only && g + 1 < A.G.n;
   if (has_q) {
     const int nvl = A.Gl.nv[g];  // lower grid g: (lx, lv - 1)
-    const int64_t qplane = int64_t(nx) * nvl;
     const int64_t ltotal = A.Gl.off[A.Gl.n];
     // Either the prolongated stencils V_k E^v on 3^d coarse slots (d <= 2), or,
     // for d = 3 where 27 slots cost more than 2 parents of 15 neighbours,
@@ -309,31 +315,31 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
       // range of group m + 1 is fetched into registers while group m is
       // computed, so one barrier per group and no exposed fetch latency.
       const int qn = it.qn;
-      T pre[BC * R][kQlIters];
+      T pre[BC][R * kQlIters];
+      // the range is qn R contiguous values per vector (slices fastest)
+      const int qnr = qn * R;
       auto fetch = [&](int m) {
-        const T* qm = C.Qt + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g] + it.q0;
+        const T* qm = C.Qt + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g] + it.q0 * R;
 #pragma unroll
         for (int q = 0; q < BC; ++q) {
           const int b = b0 + q < C.B ? b0 + q : b0;
 #pragma unroll
-          for (int s = 0; s < R; ++s)
-#pragma unroll
-            for (int j = 0; j < kQlIters; ++j) {
-              const int i = int(threadIdx.x) + j * kSB;
-              if (i < qn) pre[q * R + s][j] = qm[int64_t(b) * C.qt_bstride + int64_t(s) * qplane + i];
-            }
+          for (int j = 0; j < R * kQlIters; ++j) {
+            const int i = int(threadIdx.x) + j * kSB;
+            if (i < qnr) pre[q][j] = qm[int64_t(b) * C.qt_bstride + i];
+          }
         }
       };
       fetch(0);
       const int qo = int(int64_t(x) * nvl - it.q0);  // every slot of the item lies in the range (host)
       for (int m = 0; m < op.nxg; ++m) {
-        T* cur = sq + (m & 1) * (BC * R * qn);
+        T* cur = sq + (m & 1) * (BC * qnr);
 #pragma unroll
-        for (int t = 0; t < BC * R; ++t)
+        for (int q = 0; q < BC; ++q)
 #pragma unroll
-          for (int j = 0; j < kQlIters; ++j) {
+          for (int j = 0; j < R * kQlIters; ++j) {
             const int i = int(threadIdx.x) + j * kSB;
-            if (i < qn) cur[t * qn + i] = pre[t][j];
+            if (i < qnr) cur[q * qnr + i] = pre[q][j];
           }
         const int ka = op.xg_start[m], kb = op.xg_start[m + 1];
         T vf[NS];
@@ -345,9 +351,12 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
 #pragma unroll
           for (int q = 0; q < BC; ++q)
 #pragma unroll
-            for (int s = 0; s < R; ++s)
+            for (int e = 0; e < NS; ++e) {
+              T a[R];
+              load_slices<T, R>(cur + q * qnr + (qo + i0[e]) * R, a);
 #pragma unroll
-              for (int e = 0; e < NS; ++e) qv[q][s][e] = cur[(q * R + s) * qn + qo + i0[e]];
+              for (int s = 0; s < R; ++s) qv[q][s][e] = a[s];
+            }
           term(op.xg_terms[ka], vf, qv);
           for (int kk = ka + 1; kk < kb; ++kk) {
             factors(op.xg_terms[kk], vf);
@@ -363,14 +372,15 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
 #pragma unroll
         for (int q = 0; q < BC; ++q) {
           const int b = b0 + q < C.B ? b0 + q : b0;
-          const T* qb = qm + int64_t(b) * C.qt_bstride + int64_t(x) * nvl;
+          const T* qb = qm + int64_t(b) * C.qt_bstride + int64_t(x) * nvl * R;
 #pragma unroll
-          for (int s = 0; s < R; ++s)
+          for (int e = 0; e < NS; ++e) {
+            T a0[R], a1[R];
+            load_slices<T, R>(qb + int64_t(i0[e]) * R, a0);
+            if (!kPro) load_slices<T, R>(qb + int64_t(i1[e]) * R, a1);
 #pragma unroll
-            for (int e = 0; e < NS; ++e) {
-              const T* row = qb + int64_t(s) * qplane;
-              qv[q][s][e] = kPro ? row[i0[e]] : w0[e] * row[i0[e]] + w1[e] * row[i1[e]];
-            }
+            for (int s = 0; s < R; ++s) qv[q][s][e] = kPro ? a0[s] : w0[e] * a0[s] + w1[e] * a1[s];
+          }
         }
         for (int kk = op.xg_start[m]; kk < op.xg_start[m + 1]; ++kk) {
           T vf[NS];
