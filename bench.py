@@ -16,6 +16,9 @@ Prints one JSON line (rank 0).  Also reports, beside the headline number:
   * batched: independent 4D problems with levels drawn from {5,6,7}, applied
     and solved in lockstep (FP32 applies inside FP64 refinement) against the
     same problems solved one at a time in plain FP64;
+  * apply_6d: the 6D phase-space problem (d=3, L=6) applied in FP64 and FP32;
+  * apply_2d: the 2D phase-space problem (d=1, L=6) applied to a batch, and
+    its 8-strip march with CT-preconditioned FGMRES to 1e-10;
   * cpu_baseline: the CPU oracle timed on a bounded sample.
 """
 import argparse
@@ -48,6 +51,7 @@ def parse():
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
     ap.add_argument("--c3-level", type=int, default=6, help="level of the 6D apply leg (0 = skip)")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed loop, copy a 512 MiB buffer once (calibrates HBM byte counters)")
@@ -221,6 +225,8 @@ def main():
         out["batched"] = batched_leg(dev, a.batched)
     if a.c3_level > 0:
         out["apply_6d"] = apply_6d_leg(dev, a.c3_level)
+    if not a.no_2d:
+        out["apply_2d"] = apply_2d_leg(dev)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, value)
     print(json.dumps(out), flush=True)
@@ -368,6 +374,54 @@ def apply_6d_leg(dev, L, steps=5):
         el = (time.perf_counter() - t0) / steps
         out[name] = {"ms": round(el * 1e3, 3), "dof_applies_per_s": ops.ndof / el, "launch_config": tuned}
         _log(f"6d leg: {name} {out[name]}")
+    ops.close()
+    return out
+
+
+def apply_2d_leg(dev, batch=64, steps=20):
+    """2D phase space (d=1, c1): apply throughput for `batch` vectors in FP64, and the
+    plain method's 8-strip march (CT-preconditioned FGMRES to 1e-10 per strip)."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c1, gauss_legendre_times, random_vector, sample_on_grids
+    w = config_c1()
+    ops = sgdg.SparseGridOps(w)
+    out = {"workload": f"2D phase space d=1, r={w.r}, sparse grid L={w.L} (c1), full SD-DG operator",
+           "dofs": ops.ndof, "grids": len(ops.upper), "batch": batch}
+    u = torch.tensor(random_vector(ops.ndof, 0, batch=batch), device=dev)
+    y = torch.empty_like(u)
+    tuned = ops.tune("f64", batch=batch, reps=3)
+    ops.apply(u, y, batch=batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ops.apply(u, y, batch=batch)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    out["apply_f64"] = {"ms": round(el * 1e3, 4), "dof_applies_per_s": batch * ops.ndof / el, "launch_config": tuned}
+    # the march: u_0 interpolated, then per strip rhs (jump + inflow data) and solve
+    u_prev = _interp_u0(ops, w, dev)
+    prev_slices = 1
+    nq = w.r + 2
+    opts = sgdg.default_solve_opts(rtol=1e-10, maxit=150)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for j in range(1, w.nstrips + 1):
+        tq, _ = gauss_legendre_times((j - 1) * w.dt, w.dt, nq)
+        g = None
+        if w.g is not None:
+            g = torch.tensor(np.stack([np.concatenate([sample_on_grids(w, _grids(ops.upper), w.g, t),
+                                                       sample_on_grids(w, _grids(ops.lower), w.g, t)]) for t in tq]),
+                             device=dev)
+        b = ops.rhs(u_prev, prev_slices, None, g)
+        x, st = ops.solve_strip(b, torch.zeros_like(b), opts, raise_on_noconv=False)
+        iters.append(st.outer_iters)
+        u_prev, prev_slices = x, ops.R
+    torch.cuda.synchronize()
+    out["march"] = {"strips": w.nstrips, "seconds": round(time.perf_counter() - t0, 4), "outer_iters": iters,
+                    "last_rel_residual": st.rel_residual, "note": "includes the host sampling of the inflow data"}
+    _log(f"2d leg: {out}")
     ops.close()
     return out
 
