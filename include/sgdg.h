@@ -333,6 +333,15 @@ typedef struct {
   int from_cache;   /* 1 if taken from the tuning cache without measuring */
 } sgdg_tune_result;
 
+/* Environment, read when a handle's (or batch's) application state is first
+ * created; the tuner and sgdg_set_launch override the launch settings:
+ *   SGDG_APPLY_VARIANT  split | fused | split_tiled: initial variant (split)
+ *   SGDG_SPLIT_BC       1, 2 or 4: initial vectors per thread (2; 1 for d = 3)
+ *   SGDG_SPLIT_XCD      1: initial block map XCD-contiguous (0)
+ *   SGDG_SPLIT_ORDER    1: split items ordered v-block first (0: x-node first)
+ *   SGDG_SCAN_CHUNKS    n >= 1: blocks sharing the factor groups of a scan item (1)
+ *   SGDG_TUNE_CACHE     path of the tuning cache (see sgdg_tune) */
+
 /* Times every candidate configuration of the full operator application for
  * `batch` vectors of dtype t on stream s (reps timed applications each, after
  * one warm-up), keeps the fastest for this handle, and records it in the

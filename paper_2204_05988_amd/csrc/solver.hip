@@ -176,6 +176,7 @@ static KindData& kind(Batch& B, int k) {
   int64_t off = 0, pt = 0, qt = 0, zo = 0, rvb = 0, rxb = 0;
   std::vector<SplitItem> sitems;
   std::vector<TileItem> titems;
+  const bool vmajor = split_vmajor();
   bool tiles_ok = true;  // tiles address a grid plane with 32-bit offsets
   for (size_t p = 0; p < B.P.size(); ++p) {
     sgdg_ops o = B.P[p];
@@ -227,7 +228,7 @@ static KindData& kind(Batch& B, int k) {
         for (int bit = 0; bit < 16; ++bit)
           for (int a = 0; a < B.d; ++a) key |= uint64_t((c[a] >> bit) & 1) << (bit * B.d + a);
         const uint64_t vb = uint64_t((p0 % nvg) / split_points_per_item());
-        keyed.push_back({split_vmajor() ? (vb << 40) | key : (key << 24) | vb, p0});
+        keyed.push_back({vmajor ? (vb << 40) | key : (key << 24) | vb, p0});
       }
       std::stable_sort(keyed.begin(), keyed.end());
       const bool upper = !D.diag_only && gi + 1 < D.G.n && B.d <= 2;
