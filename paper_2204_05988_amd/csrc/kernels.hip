@@ -215,35 +215,18 @@ __global__ void __launch_bounds__(kBlock) k_gmres_start(int nseg, GmresState st,
   st.inv[g] = act ? 1.0 / beta : 0.0;
 }
 
-// one block per segment; thread i < nv owns projection coefficient i, the
-// block's waves split the chunks and are combined in a fixed order
+// one block per (segment, projection coefficient i): the block's threads
+// stride over the segment's chunk partials, then a fixed-order block sum
 __global__ void __launch_bounds__(kBlock) k_gmres_proj(int nseg, GmresState st, const SegInfo* __restrict__ segs,
                                                        const double* __restrict__ partial, int j) {
-  constexpr int kWaves = kBlock / 64;
-  __shared__ double sh[kWaves][64];
-  const int g = blockIdx.x;
-  const int nv = j + 1;
+  __shared__ double sh[kBlock / 64];
+  const int g = blockIdx.x, i = blockIdx.y;
   const int m = st.m;
-  const SegInfo& S = segs[g];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const bool act = st.active[g] == 1;
-  for (int i0 = 0; i0 < nv; i0 += 64) {
-    const int i = i0 + lane;
-    double a = 0;
-    if (i < nv)
-      for (int c = wv; c < S.nchunk; c += kWaves) a += partial[int64_t(S.chunk0 + c) * nv + i];
-    sh[wv][lane] = a;
-    __syncthreads();
-    if (wv == 0 && i < nv) {
-      double t = 0;
-#pragma unroll
-      for (int q = 0; q < kWaves; ++q) t += sh[q][lane];
-      if (!act) t = 0.0;
-      st.hcol[int64_t(g) * (m + 1) + i] = t;
-      st.H[int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1) + i] += t;
-    }
-    __syncthreads();
-  }
+  const double a = seg_chunk_sum(segs[g], partial, j + 1, i, sh);
+  if (threadIdx.x != 0) return;
+  const double t = st.active[g] == 1 ? a : 0.0;
+  st.hcol[int64_t(g) * (m + 1) + i] = t;
+  st.H[int64_t(g) * (m + 1) * m + int64_t(j) * (m + 1) + i] += t;
 }
 
 // one block per segment: the norm of the new direction from the chunk
@@ -513,7 +496,7 @@ void gmres_start(int nseg, const GmresState& st, const SegInfo* segs, const doub
 }
 void gmres_add_proj(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, hipStream_t s) {
   if (nseg == 0) return;
-  hipLaunchKernelGGL(k_gmres_proj, dim3(nseg), dim3(kBlock), 0, s, nseg, st, segs, partial, j);
+  hipLaunchKernelGGL(k_gmres_proj, dim3(nseg, j + 1), dim3(kBlock), 0, s, nseg, st, segs, partial, j);
   LAUNCH_CHECK();
 }
 void gmres_givens(int nseg, const GmresState& st, const SegInfo* segs, const double* partial, int j, double tol,
