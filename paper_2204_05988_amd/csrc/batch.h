@@ -100,6 +100,7 @@ struct SplitCall {
   const T* Qt;
   T* Z;                    // [b][problem: X-group m][grid layout] staged v-stage W^m
   int max_qn;              // largest SplitItem::qn (LDS of the upper-partner pass)
+  int x_assign;            // 1: no upper-partner pass ran (block-diagonal kinds), pass 3 writes y
   const TileItem* tiles;   // x-stencil pass on LDS tiles (ntiles = 0: per-point items)
   int ntiles;
   int max_tile;            // largest (t + 2)^d vb of a tile

@@ -521,7 +521,13 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   S.xcd = B.split_xcd;
   // one vector per thread for single vectors (the solvers); tuned otherwise
   const int bc = nb == 1 ? 1 : (B.split_bc > 0 ? B.split_bc : split_default_bc(B.d));
-  for (int stage = 0; stage < 3; ++stage) timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
+  // without any partner coupling (block-diagonal kinds) the upper-partner pass
+  // would only zero y: pass 3 writes y instead
+  S.x_assign = K.any_scan ? 0 : 1;
+  for (int stage = 0; stage < 3; ++stage) {
+    if (stage == 1 && S.x_assign) continue;
+    timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
+  }
 }
 
 // ---------------------------------------------------------- segments -----

@@ -458,7 +458,10 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
     if (b >= C.B) break;
     T* yb = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(R) * A.poff[g] + p;
 #pragma unroll
-    for (int s = 0; s < R; ++s) yb[int64_t(s) * plane] += acc[q][s];  // after the upper-partner pass
+    for (int s = 0; s < R; ++s) {
+      if (C.x_assign) yb[int64_t(s) * plane] = acc[q][s];  // no upper-partner pass ran
+      else yb[int64_t(s) * plane] += acc[q][s];            // after the upper-partner pass
+    }
   }
 }
 
@@ -671,7 +674,10 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
     if (b >= C.B) break;
     T* yb = C.y + int64_t(b) * C.y_bstride + A.y_off + int64_t(R) * A.poff[g] + p;
 #pragma unroll
-    for (int s = 0; s < R; ++s) yb[int64_t(s) * plane] += acc[q][s];  // after the upper-partner pass
+    for (int s = 0; s < R; ++s) {
+      if (C.x_assign) yb[int64_t(s) * plane] = acc[q][s];  // no upper-partner pass ran
+      else yb[int64_t(s) * plane] += acc[q][s];            // after the upper-partner pass
+    }
   }
 }
 
