@@ -247,6 +247,41 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   for (size_t i = 0; i < pv.size(); ++i) pv32[i] = float(pv[i]);
   d.pvals = upload(dd.pvals, pv);
   d.pvals32 = upload(dd.pvals32, pv32);
+  // slot-pair copies of the slot-major factor tables: [K/2][n][2] per level
+  auto pair_major = [&](const std::vector<double>& src, size_t nblocks, int64_t stride, int K, const int64_t* off,
+                        int64_t* qoff, int64_t& qstride, std::vector<double>& dst, std::vector<float>& dst32) {
+    const int K2 = K + (K & 1);
+    int64_t q = 0;
+    for (int l = D.lmin; l <= D.lmax; ++l) {
+      qoff[l - D.lmin] = q;
+      q += D.L(l).n * K2;
+    }
+    qstride = q;
+    dst.assign(nblocks * size_t(q), 0.0);
+    for (size_t bk = 0; bk < nblocks; ++bk)
+      for (int l = D.lmin; l <= D.lmax; ++l) {
+        const int64_t n = D.L(l).n, sb = int64_t(bk) * stride + off[l - D.lmin];
+        const int64_t qb = int64_t(bk) * q + qoff[l - D.lmin];
+        for (int e = 0; e < K; ++e)
+          for (int64_t i = 0; i < n; ++i) dst[qb + ((e >> 1) * n + i) * 2 + (e & 1)] = src[sb + int64_t(e) * n + i];
+      }
+    dst32.resize(dst.size());
+    for (size_t i = 0; i < dst.size(); ++i) dst32[i] = float(dst[i]);
+  };
+  {
+    std::vector<double> tq;
+    std::vector<float> tq32;
+    std::vector<double> t(nf * o);
+    slot_major(t, vals, nf, o, S, loff);
+    pair_major(t, nf, o, S, d.lev_off, d.qlev_off, d.qfac_stride, tq, tq32);
+    d.qvals = upload(dd.qvals, tq);
+    d.qvals32 = upload(dd.qvals32, tq32);
+    std::vector<double> pq;
+    std::vector<float> pq32;
+    pair_major(pv, nf, pof, PW, d.plev_off, d.qplev_off, d.qpstride, pq, pq32);
+    d.qpvals = upload(dd.qpvals, pq);
+    d.qpvals32 = upload(dd.qpvals32, pq32);
+  }
 }
 
 static void upload_op(OpDev& od) {

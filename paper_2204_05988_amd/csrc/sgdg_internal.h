@@ -172,6 +172,16 @@ struct DevDomain {
   const float* pvals32 = nullptr;
   int64_t pstride = 0;                // elements per factor
   int64_t rstride = 0;                // elements per factor
+  // slot-pair copies: slots 2p and 2p+1 of a node are adjacent ([S/2][n][2]
+  // per level, an odd last slot padded with 0), read with one 2-wide load
+  int64_t qlev_off[kMaxLevels] = {};  // start of level l in the pair stencil tables
+  const double* qvals = nullptr;      // [factor][levels [S/2][n][2]]
+  const float* qvals32 = nullptr;
+  int64_t qfac_stride = 0;            // elements per factor
+  int64_t qplev_off[kMaxLevels] = {}; // start of level l in the pair prolongated tables
+  const double* qpvals = nullptr;     // [factor][levels [PW/2][n][2]]
+  const float* qpvals32 = nullptr;
+  int64_t qpstride = 0;               // elements per factor
 };
 
 struct DevGrids {

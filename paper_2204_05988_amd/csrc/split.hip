@@ -46,6 +46,25 @@ template <> __device__ __forceinline__ const float* tmat<float>(const DevOp& op)
 // The staged W keeps the R slices of a point contiguous ([grid][x][v][R]), so
 // the x-stage reads a pair of slices with one 2-wide load (half the memory
 // instructions).
+// slot-pair factor tables ([S/2][n][2] per level): slots 2p, 2p+1 of a node
+// are adjacent and read with one 2-wide load
+template <class T> __device__ __forceinline__ const T* qvals(const DevDomain& D);
+template <> __device__ __forceinline__ const double* qvals<double>(const DevDomain& D) { return D.qvals; }
+template <> __device__ __forceinline__ const float* qvals<float>(const DevDomain& D) { return D.qvals32; }
+template <class T> __device__ __forceinline__ const T* qpvals(const DevDomain& D);
+template <> __device__ __forceinline__ const double* qpvals<double>(const DevDomain& D) { return D.qpvals; }
+template <> __device__ __forceinline__ const float* qpvals<float>(const DevDomain& D) { return D.qpvals32; }
+template <class T, int S>
+__device__ __forceinline__ void load_slot_pairs(const T* q, int64_t n, int64_t node, T (&f)[S]) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int p = 0; p < (S + 1) / 2; ++p) {
+    const T2 a = *reinterpret_cast<const T2*>(q + (int64_t(p) * n + node) * 2);
+    f[2 * p] = a.x;
+    if (2 * p + 1 < S) f[2 * p + 1] = a.y;
+  }
+}
+
 template <class T, int R>
 __device__ __forceinline__ void load_slices(const T* p, T (&v)[R]) {
   typedef T T2 __attribute__((ext_vector_type(2)));
@@ -109,7 +128,6 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   }
   const int64_t total = A.G.off[A.G.n];
   const int64_t ltotal = A.Gl.off[A.Gl.n];
-  const T* vv = vals<T>(A.DV);
   const T* tm = tmat<T>(op);
   T un[BC][R][SS];
 #pragma unroll
@@ -128,9 +146,8 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const int nt = op.xg_start[op.nxg];
   auto load = [&](int kk, T (&f)[SS], T (&pv)[BC][R][2]) {
     const int k = op.xg_terms[kk];
-    const T* fp = vv + int64_t(op.term_vf[k]) * A.DV.fac_stride + vlo + v;
-#pragma unroll
-    for (int e = 0; e < SS; ++e) f[e] = fp[int64_t(e) * nv];
+    load_slot_pairs<T, SS>(qvals<T>(A.DV) + int64_t(op.term_vf[k]) * A.DV.qfac_stride + A.DV.qlev_off[lv - A.DV.lmin],
+                           nv, v, f);
     const int j = op.term_vg[k];
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
@@ -306,9 +323,15 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
         }
     };
     auto factors = [&](int k, T (&vf)[NS]) {
-      const T* f = fvals + int64_t(op.term_vf[k]) * fstride + fbase;
+      if constexpr (kPro) {
+        load_slot_pairs<T, NS>(qpvals<T>(A.DV) + int64_t(op.term_vf[k]) * A.DV.qpstride +
+                                   A.DV.qplev_off[lv - A.DV.lmin],
+                               nv, v, vf);
+      } else {
+        const T* f = fvals + int64_t(op.term_vf[k]) * fstride + fbase;
 #pragma unroll
-      for (int e = 0; e < NS; ++e) vf[e] = f[int64_t(e) * nv];
+        for (int e = 0; e < NS; ++e) vf[e] = f[int64_t(e) * nv];
+      }
     };
     if constexpr (ql) {
       // Software pipeline over the X-groups with two LDS buffers: the coarse
@@ -418,7 +441,6 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   const int lx = A.G.lx[g];
   const int64_t xlo = A.DX.lev_off[lx - A.DX.lmin];
   const DevOp& op = A.op;
-  const T* xv = vals<T>(A.DX);
   const int64_t total = A.G.off[A.G.n];
   int32_t nbx[SS];
 #pragma unroll
@@ -430,10 +452,9 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
   // diagonal + lower partners: one x-stencil per X-group on the staged W
   for (int m = 0; m < op.nxg; ++m) {
-    const T* f = xv + int64_t(op.xg_fac[m]) * A.DX.fac_stride + xlo + x;
     T xf[SS];
-#pragma unroll
-    for (int e = 0; e < SS; ++e) xf[e] = f[int64_t(e) * nx];
+    load_slot_pairs<T, SS>(qvals<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.qfac_stride + A.DX.qlev_off[lx - A.DX.lmin],
+                           nx, x, xf);
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q < C.B ? b0 + q : b0;
@@ -612,7 +633,7 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
     if constexpr (kFacLds) {
 #pragma unroll
       for (int j = 0; j < kTileFacIters; ++j) fpre[j] = fidx[j] >= 0 ? fp[fidx[j]] : T(0);
-    } else {
+    } else {  // slot-major direct loads: the pair loads measured slower here (one wave less per SIMD)
 #pragma unroll
       for (int e = 0; e < SS; ++e) fpre[e] = fp[int64_t(e) * nx + x];
     }
