@@ -61,10 +61,10 @@ struct FusedCall {
   int64_t u_bstride, y_bstride, pt_bstride, qt_bstride;  // batch strides
   const T* u;
   T* y;
-  T* Pt;
-  T* Qt;
+  T* Pt;                   // [b][problem: V-group j][lower grids: nx][nv][R]
+  T* Qt;                   // [b][problem: X-group m][lower grids: nx][nv][R]
   int64_t rv_bstride, rx_bstride;
-  T* Rv;
+  T* Rv;                   // restrictions of the previous scan step, same slice order
   T* Rx;
 };
 
@@ -98,7 +98,7 @@ struct SplitCall {
   T* y;
   const T* Pt;
   const T* Qt;
-  T* Z;                    // [b][problem: X-group m][grid layout] staged v-stage W^m
+  T* Z;                    // [b][problem: X-group m][grid: nx][nv][R] staged v-stage W^m
   int max_qn;              // largest SplitItem::qn (LDS of the upper-partner pass)
   int x_assign;            // 1: no upper-partner pass ran (block-diagonal kinds), pass 3 writes y
   const TileItem* tiles;   // x-stencil pass on LDS tiles (ntiles = 0: per-point items)

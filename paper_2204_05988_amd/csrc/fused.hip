@@ -19,6 +19,9 @@
 // stages E^v Qt on the v-box plus halo and applies the v-factors.  Halo nodes
 // are addressed by unwrapped box coordinates, so periodic wrap only appears
 // when the staged values are fetched.
+//
+// The partner arrays Pt, Qt and their restrictions Rv, Rx keep the R slices
+// of a node contiguous ([group][lower grid: n_x][n_v][R]).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,5 +1,5 @@
-// Split operator application for gfx950: two streaming passes over the points
-// of every upper grid, with a v-stage kept in HBM between them.
+// Split operator application for gfx950: three streaming passes over the
+// points of every upper grid, with a v-stage kept in HBM between them.
 //
 // With X-groups m (terms sharing an x-factor X_m) and the V-group j(k) of each
 // term, the block row of upper grid i is (Sect. 4.2, with the embedding
@@ -10,13 +10,16 @@
 //
 // Pass 1 (k_vstage) computes W for every X-group: the v-stencils of u (v is
 // the fastest axis, so the neighbour gathers stay in L1/L2), the x-prolonged
-// lower-partner scan arrays and the time-block mixing.  Pass 2 (k_xstage)
-// applies one x-stencil per X-group to W (rows x +- 1 are nv apart: one
-// coalesced row per neighbour) and adds the upper-partner part, prolonging Qt
-// in v on the fly.  Grouping by x-factor makes the number of staged arrays and
-// of x-stencil passes the number of distinct x-factors.  One thread owns one
-// point and BC vectors of the batch; the stencil indices, parent tables and
-// factor values of its point are loaded once and reused across them.
+// lower-partner scan arrays and the time-block mixing.  Pass 1b (k_ustage)
+// writes the upper-partner part into y with the prolongated stencils V_k E^v.
+// Pass 2 (k_xstage per point, k_xtile on LDS tiles) adds one x-stencil per
+// X-group applied to W.  Grouping by x-factor makes the number of staged
+// arrays and of x-stencil passes the number of distinct x-factors.  One
+// thread owns one point and BC vectors of the batch; the stencil indices,
+// parent tables and factor values of its point are loaded once and reused
+// across them.  What bounds these passes is the vector-memory instruction
+// rate of a CU, so the layouts below let one load move two values and the
+// tiled forms serve reused values from LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
