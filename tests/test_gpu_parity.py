@@ -164,6 +164,29 @@ def test_apply_c2_full_size(dev):
     assert _rel(yt.cpu().numpy(), y_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("launch", [("split_tiled", 2, 8, 1), ("split", 2, 8, 0)], ids=["tiled2x", "split2"])
+def test_apply_c2_full_size_batch16(dev, launch):
+    """c2 at full size in the benchmark's launch configuration family (batch 16,
+    two vectors per thread, tiled x-stage, XCD block map): three of the sixteen
+    vectors, first, middle and last, against the oracle."""
+    w, P, ops = _problem("c2", config_c2)
+    B = 16
+    u = random_vector(P.ndof, 0, batch=B)
+    ops.set_launch(*launch)
+    try:
+        ut = torch.tensor(u, device=dev)
+        yt = torch.empty_like(ut)
+        _say(f"apply parity c2 full size, batch {B}, launch {launch}")
+        ops.apply(ut, yt, batch=B)
+        torch.cuda.synchronize()
+        for b in (0, B // 2, B - 1):
+            err = _rel(yt[b].cpu().numpy(), P.apply(u[b]))
+            _say(f"  vector {b}: rel err {err:.2e}")
+            assert err <= 1e-10
+    finally:
+        ops.set_launch("split", 2, 8, 0)
+
+
 def test_combine_parity(dev):
     w, P, ops = _problem("tiny_d2", CASES["tiny_d2"])
     R = 2
