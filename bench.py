@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
     ap.add_argument("--c3-level", type=int, default=6, help="level of the 6D apply leg (0 = skip)")
-    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calib-copy", action="store_true",
