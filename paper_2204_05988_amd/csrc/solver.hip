@@ -113,10 +113,7 @@ Batch& self_batch(sgdg_ops o) {
     if (const char* v = getenv("SGDG_APPLY_VARIANT"))
       b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
     if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
-  b->split_xcd = split_xcd();
-  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
     b->split_xcd = split_xcd();
-  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
     if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
     o->self.reset(b);
   }
