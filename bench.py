@@ -13,6 +13,8 @@ Prints one JSON line (rank 0).  Also reports, beside the headline number:
     r=0): (r, P_CT r) pairs recorded from CT-preconditioned solves of strips
     1-8, the per-grid networks trained on them, then strips 9-10 solved to 1e-8
     with CT, with the learned preconditioner, and learned + mixed precision;
+    its "network" entry is the forward rate of the trained network against
+    the bf16 matrix-core peak (--network-only: that rate alone, untrained);
   * batched: independent 4D problems with levels drawn from {5,6,7}, applied
     and solved in lockstep (FP32 applies inside FP64 refinement) against the
     same problems solved one at a time in plain FP64;
@@ -33,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 157.3  # non-packed FP32: twice the FP64 lane rate
 
@@ -51,6 +54,8 @@ def parse():
     ap.add_argument("--batched", type=int, default=64, help="problems of the batched leg (0 = skip)")
     ap.add_argument("--c3-level", type=int, default=6, help="level of the 6D apply leg (0 = skip)")
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--network-only", action="store_true",
+                    help="learned leg reduced to the network's forward rate (freshly initialised weights)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calib-copy", action="store_true",
@@ -219,7 +224,9 @@ def main():
     if not a.no_solve:
         out["strip_solve"] = solve_times(ops, w, dev)
         _log(f"strip solves: {out['strip_solve']}")
-    if not a.no_learned:
+    if a.network_only:
+        out["network"] = network_leg(dev)
+    elif not a.no_learned:
         out["learned"] = learned_leg(dev, a.train_steps)
     if a.batched > 0:
         out["batched"] = batched_leg(dev, a.batched)
@@ -322,6 +329,8 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
            "record_solve_s": round(rec_time, 3),
            "train": {"steps": ts.steps, "batch": 8, "seconds": round(ts.seconds, 3),
                      "loss_first": ts.loss_first, "loss_last": ts.loss_last}, "strips": []}
+    out["network"] = network_rate(net, ops, dev)
+    _log(f"learned leg: network {out['network']}")
     learned = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(net=net))
     learned_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True, pc=sgdg.default_precond_opts(net=net))
     # inexact grid problems (10 GMRES iterations each): the combination technique
@@ -347,6 +356,45 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
     net.close()
     ops.close()
     return out
+
+
+def network_leg(dev, L=7):
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c5
+    ops = sgdg.SparseGridOps(config_c5(L=L))
+    net = sgdg.LearnedPreconditioner(ops, seed=0)
+    out = dict(network_rate(net, ops, dev), workload=f"c5 L={L}, one residual, all grids")
+    _log(f"network: {out}")
+    net.close()
+    ops.close()
+    return out
+
+
+def network_rate(net, ops, dev, reps=20):
+    """Forward of the trained network on one residual-sized input (all grids,
+    channels-last [points][R] FP32), timed with events on the launching stream.
+    MFMA work issued: 8 convolutions x 9 taps x 32 x 32 channels x 2 flops per
+    point (the padded input and output channels included)."""
+    import torch
+    R = ops.R
+    x = torch.randn(ops.ndof, dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(3))
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        net.forward(x, y, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(x, y, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    points = ops.ndof // R
+    flops = 8 * 9 * 32 * 32 * 2 * points
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"points": points, "forward_ms": round(ms, 4), "mfma_flops": flops, "bound": "mfma",
+            "achieved": round(tf, 2), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 5)}
 
 
 def apply_6d_leg(dev, L, steps=5):

@@ -30,7 +30,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 struct NetGrid {
   int mx, mv;       // nodes per axis of the x- and v-lattices (2D each)
   int64_t poff;     // first point of the grid in the concatenated point order
-  int64_t np;       // points mx^2 mv^2
+  int64_t np;       // points mx^2 mv^2 (below 2^24)
+  float rmx, rmv, rnv;  // 1/mx, 1/mv, 1/mv^2 (FP32, for qdiv)
 };
 
 struct NetGeom {
@@ -54,24 +55,34 @@ __device__ __forceinline__ bool nbr_ok(int& n, int m, int per) {
   return n >= 0 && n < m;
 }
 
+// floor(n / m) for 0 <= n < 2^24, m >= 1, rm = 1/m in FP32: the FP32 product is
+// within one of the quotient there (relative error below 2^-22 on a quotient
+// below 2^23, exact for m = 1), and one correction each way makes it exact.
+__device__ __forceinline__ int qdiv(int n, int m, float rm) {
+  int q = int(float(n) * rm);
+  q -= int(q * m > n);
+  q += int((q + 1) * m <= n);
+  return q;
+}
+
 // Neighbour point of p for tap (a, b) in the x-plane (plane 0) or v-plane (1); -1 outside.
-__device__ __forceinline__ int64_t neighbour(int64_t p, int a, int b, int plane, const NetGrid& G, int xper,
-                                             int vper) {
-  const int64_t nv = int64_t(G.mv) * G.mv;
-  const int64_t xi = p / nv;
-  const int64_t vi = p - xi * nv;
+// 32-bit index arithmetic: points of a grid number below 2^24.
+__device__ __forceinline__ int neighbour(int p, int a, int b, int plane, const NetGrid& G, int xper, int vper) {
+  const int nv = G.mv * G.mv;
+  const int xi = qdiv(p, nv, G.rnv);
+  const int vi = p - xi * nv;
   if (plane == 0) {
-    int x1 = int(xi / G.mx), x2 = int(xi - int64_t(x1) * G.mx);
+    int x1 = qdiv(xi, G.mx, G.rmx), x2 = xi - x1 * G.mx;
     x1 += a;
     x2 += b;
     if (!nbr_ok(x1, G.mx, xper) || !nbr_ok(x2, G.mx, xper)) return -1;
-    return (int64_t(x1) * G.mx + x2) * nv + vi;
+    return (x1 * G.mx + x2) * nv + vi;
   }
-  int v1 = int(vi / G.mv), v2 = int(vi - int64_t(vi / G.mv) * G.mv);
+  int v1 = qdiv(vi, G.mv, G.rmv), v2 = vi - v1 * G.mv;
   v1 += a;
   v2 += b;
   if (!nbr_ok(v1, G.mv, vper) || !nbr_ok(v2, G.mv, vper)) return -1;
-  return xi * nv + int64_t(v1) * G.mv + v2;
+  return xi * nv + v1 * G.mv + v2;
 }
 
 __device__ __forceinline__ bf16x8 zero8() {
@@ -107,17 +118,29 @@ __global__ void __launch_bounds__(64) k_conv(const ConvItem* __restrict__ items,
     for (int j = 0; j < 4; ++j) bv[h][j] = bias ? bias[int64_t(it.g) * bstride + h * 16 + kq * 4 + j] : 0.0f;
   const int64_t base = (int64_t(it.s) * geo.Ptot + G.poff) * NC;
   const int steps = (it.np + 15) / 16;
+  // the 9 neighbour fragments of step st; the next step's are in flight
+  // while the current step's products run
+  auto gather = [&](int st, bf16x8 (&f)[NTAP]) {
+    const int loc = st * 16 + col;
+    const bool valid = loc < it.np;
+    const int p = int(it.p0) + loc;
+#pragma unroll
+    for (int t = 0; t < NTAP; ++t) {
+      const int a = (t / 3 - 1) * sign, b = (t % 3 - 1) * sign;
+      const int q = valid ? neighbour(p, a, b, plane, G, geo.xper, geo.vper) : -1;
+      f[t] = q >= 0 ? *reinterpret_cast<const bf16x8*>(in + base + int64_t(q) * NC + kq * 8) : zero8();
+    }
+  };
+  bf16x8 bn[NTAP];
+  if (steps > 0) gather(0, bn);
   for (int st = 0; st < steps; ++st) {
     const int loc = st * 16 + col;
     const bool valid = loc < it.np;
     const int64_t p = it.p0 + loc;
     bf16x8 bo[NTAP];
 #pragma unroll
-    for (int t = 0; t < NTAP; ++t) {
-      const int a = (t / 3 - 1) * sign, b = (t % 3 - 1) * sign;
-      const int64_t q = valid ? neighbour(p, a, b, plane, G, geo.xper, geo.vper) : -1;
-      bo[t] = q >= 0 ? *reinterpret_cast<const bf16x8*>(in + base + q * NC + kq * 8) : zero8();
-    }
+    for (int t = 0; t < NTAP; ++t) bo[t] = bn[t];
+    if (st + 1 < steps) gather(st + 1, bn);
     f32x4 acc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -206,8 +229,8 @@ __global__ void __launch_bounds__(64) k_wgrad(const ConvItem* __restrict__ items
         const int loc = ch * 32 + pt;
         bf16x8 v = zero8();
         if (loc < it.np) {
-          const int64_t q = neighbour(it.p0 + loc, a, b, plane, G, geo.xper, geo.vper);
-          if (q >= 0) v = *reinterpret_cast<const bf16x8*>(x + base + q * NC + q4 * 8);
+          const int q = neighbour(int(it.p0) + loc, a, b, plane, G, geo.xper, geo.vper);
+          if (q >= 0) v = *reinterpret_cast<const bf16x8*>(x + base + int64_t(q) * NC + q4 * 8);
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) xT[(q4 * 8 + e) * kLdsRow + pt] = v[e];
@@ -659,6 +682,10 @@ extern "C" sgdg_status sgdg_net_create(sgdg_ops o, uint64_t seed, sgdg_net* out)
     G.mv = g->v.axis_nodes(g->up[i].lv);
     G.np = int64_t(G.mx) * G.mx * G.mv * G.mv;
     require(G.np == g->up[i].nx * g->up[i].nv, "grid lattice mismatch");
+    require(G.np < (int64_t(1) << 24), "a component grid of the learned preconditioner exceeds 2^24 points");
+    G.rmx = 1.0f / float(G.mx);
+    G.rmv = 1.0f / float(G.mv);
+    G.rnv = 1.0f / float(int64_t(G.mv) * G.mv);
     G.poff = po;
     po += G.np;
   }

@@ -877,7 +877,9 @@ static std::vector<double> seg_norms(Batch& B, const SegTab& ST, const double* v
 // Flexible GMRES on every problem of the batch in lockstep (one segment per
 // problem, FP64 Arnoldi), stopping per problem at ||b - A u|| <= tol ||b||.
 // monitor(iterations, largest relative residual estimate, largest relative residual at entry)
-using Monitor = std::function<void(int, double, double)>;
+// called after every FGMRES iteration with (iteration, residual estimate, residual at
+// entry); true ends the current cycle (restart from the true residual)
+using Monitor = std::function<bool(int, double, double)>;
 static FgmresResult fgmres(Batch& B, const std::function<void(const double*, double*)>& A,
                            const std::function<void(const double*, double*)>& P, const double* b, double* x,
                            double tol, int m, int maxit, hipStream_t s, const Monitor* monitor = nullptr) {
@@ -956,12 +958,12 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
         if (bn[i] > 0) est = std::max(est, beta[i] / bn[i]);
       }
       if (verbose) fprintf(stderr, "[sgdg fgmres] it %d  est %.3e\n", res.iters + j + 1, est);
-      if (monitor) (*monitor)(res.iters + j + 1, est, rel0);
+      const bool restart = monitor && (*monitor)(res.iters + j + 1, est, rel0);
       if (bad) {
         res.nan = true;
         return res;
       }
-      if (!any) {
+      if (!any || restart) {
         ++j;
         break;
       }
@@ -995,8 +997,11 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
   const double fb_drop = pc.fallback_drop > 1 ? pc.fallback_drop : 10.0;
   sgdg_net rec = B.owned_by_ops ? B.P[0]->recorder : nullptr;
   std::vector<double> est_hist;  // residual estimate after each learned iteration (index 0: at entry)
+  // At the switch the cycle ends: the combination technique then starts a
+  // fresh Krylov space from the true residual instead of extending the basis
+  // the network built.
   const Monitor monitor = [&](int it, double est, double rel0) {
-    if (use_ct) return;
+    if (use_ct) return false;
     if (est_hist.empty()) est_hist.push_back(rel0);
     est_hist.push_back(est);
     (void)it;
@@ -1004,7 +1009,9 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
     if (k >= size_t(fb_iters) && est > est_hist[k - fb_iters] / fb_drop) {
       use_ct = true;  // no drop by fb_drop over the last fb_iters iterations
       fell_back = true;
+      return true;
     }
+    return false;
   };
   auto A64 = [&](const double* in, double* out) { apply<double>(B, K_FULL, in, out, 1, s); };
   auto P64 = [&](const double* in, double* out) {
