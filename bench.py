@@ -14,7 +14,8 @@ Prints one JSON line (rank 0).  Also reports, beside the headline number:
     1-8, the per-grid networks trained on them, then strips 9-10 solved to 1e-8
     with CT, with the learned preconditioner, and learned + mixed precision;
     its "network" entry is the forward rate of the trained network against
-    the bf16 matrix-core peak (--network-only: that rate alone, untrained);
+    the HBM roofline, with its matrix-core utilisation (--network-only: that
+    rate alone, freshly initialised);
   * batched: independent 4D problems with levels drawn from {5,6,7}, applied
     and solved in lockstep (FP32 applies inside FP64 refinement) against the
     same problems solved one at a time in plain FP64;
@@ -391,10 +392,18 @@ def network_rate(net, ops, dev, reps=20):
     ms = e0.elapsed_time(e1) / reps
     points = ops.ndof // R
     flops = 8 * 9 * 32 * 32 * 2 * points
+    # HBM bytes of the 8 convolutions: each reads its bf16 input (64 B per point)
+    # once and writes 64 B (the last, FP32, 128 B); 4.0 GFLOP per 28 MB is
+    # 144 flop/B, below the bf16 ridge point (2500 / 8 = 312 flop/B), so the
+    # convolutions are HBM-bound and the matrix-core fraction is the utilisation
+    nbytes = points * (7 * 128 + 64 + 128)
     tf = flops / (ms * 1e-3) / 1e12
-    return {"points": points, "forward_ms": round(ms, 4), "mfma_flops": flops, "bound": "mfma",
-            "achieved": round(tf, 2), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 5)}
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"points": points, "forward_ms": round(ms, 4), "mfma_flops": flops, "bytes": nbytes,
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "mfma": {"achieved": round(tf, 2), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "utilisation": round(tf / BF16_MFMA_PEAK_TFLOPS, 5)}}
 
 
 def apply_6d_leg(dev, L, steps=5):

@@ -22,6 +22,7 @@ constexpr int NCONV = 8;
 constexpr int NTAP = 9;
 constexpr int CONV_PARAMS = NTAP * NC * NC + NC;  // weights then bias
 constexpr int WFRAG = NTAP * 2 * 64;              // bf16x8 fragments per convolution
+constexpr int kConvWaves = 4, kConvThreads = 64 * kConvWaves;  // k_conv block
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -92,25 +93,23 @@ __device__ __forceinline__ bf16x8 zero8() {
   return z;
 }
 
-// out = act(bias + sum_t W_t in[nbr(p, sign * t)]) on a tile of points, one wave per block.
+// out = act(bias + sum_t W_t in[nbr(p, sign * t)]) on a tile of points, one item per block.
 // sign = -1 with the transposed fragments computes the adjoint convolution.
 // mask (optional): out *= (mask > 0) (the ReLU derivative of the layer below).
 template <bool OUT_F32>
-__global__ void __launch_bounds__(64) k_conv(const ConvItem* __restrict__ items, NetGeom geo,
-                                             const bf16x8* __restrict__ W, int64_t wstride,
-                                             const float* __restrict__ bias, int64_t bstride, int plane, int sign,
-                                             int relu, const __bf16* __restrict__ in, void* __restrict__ out,
-                                             const __bf16* __restrict__ mask) {
+__global__ void __launch_bounds__(kConvThreads) k_conv(const ConvItem* __restrict__ items, NetGeom geo,
+                                                       const bf16x8* __restrict__ W, int64_t wstride,
+                                                       const float* __restrict__ bias, int64_t bstride, int plane,
+                                                       int sign, int relu, const __bf16* __restrict__ in,
+                                                       void* __restrict__ out, const __bf16* __restrict__ mask) {
+  // the item's weight fragments, shared by the block's waves
+  __shared__ bf16x8 wl[NTAP * 2 * 64];
   const ConvItem it = items[blockIdx.x];
   const NetGrid G = geo.g[it.g];
-  const int lane = threadIdx.x;
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
   const int col = lane & 15, kq = lane >> 4;
   const bf16x8* Wg = W + int64_t(it.g) * wstride;
-  bf16x8 wr[NTAP][2];
-#pragma unroll
-  for (int t = 0; t < NTAP; ++t)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) wr[t][h] = Wg[(t * 2 + h) * 64 + lane];
+  for (int i = int(threadIdx.x); i < NTAP * 2 * 64; i += kConvThreads) wl[i] = Wg[i];
   float bv[2][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -118,7 +117,7 @@ __global__ void __launch_bounds__(64) k_conv(const ConvItem* __restrict__ items,
     for (int j = 0; j < 4; ++j) bv[h][j] = bias ? bias[int64_t(it.g) * bstride + h * 16 + kq * 4 + j] : 0.0f;
   const int64_t base = (int64_t(it.s) * geo.Ptot + G.poff) * NC;
   const int steps = (it.np + 15) / 16;
-  // the 9 neighbour fragments of step st; the next step's are in flight
+  // the 9 neighbour fragments of step st; the wave's next step is in flight
   // while the current step's products run
   auto gather = [&](int st, bf16x8 (&f)[NTAP]) {
     const int loc = st * 16 + col;
@@ -132,22 +131,27 @@ __global__ void __launch_bounds__(64) k_conv(const ConvItem* __restrict__ items,
     }
   };
   bf16x8 bn[NTAP];
-  if (steps > 0) gather(0, bn);
-  for (int st = 0; st < steps; ++st) {
+  if (wave < steps) gather(wave, bn);
+  __syncthreads();  // wl complete
+  // the block's waves take the item's 16-point steps in turn
+  for (int st = wave; st < steps; st += kConvWaves) {
     const int loc = st * 16 + col;
     const bool valid = loc < it.np;
     const int64_t p = it.p0 + loc;
     bf16x8 bo[NTAP];
 #pragma unroll
     for (int t = 0; t < NTAP; ++t) bo[t] = bn[t];
-    if (st + 1 < steps) gather(st + 1, bn);
+    if (st + kConvWaves < steps) gather(st + kConvWaves, bn);
+    // weight fragments are read from LDS at each use (not held in registers)
+    __asm__ volatile("" ::: "memory");
     f32x4 acc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < NTAP; ++t)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[t][h], bo[t], acc[h], 0, 0, 0);
+      for (int h = 0; h < 2; ++h)
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[(t * 2 + h) * 64 + lane], bo[t], acc[h], 0, 0, 0);
     if (!valid) continue;
     const int64_t o = base + p * NC;
 #pragma unroll
@@ -514,10 +518,10 @@ void conv(Net& N, const Net::Tab& T, int c, bool transposed, int relu, const __b
   const int64_t bstride = int64_t(NCONV) * CONV_PARAMS;
   const int sign = transposed ? -1 : 1;
   if (out_f32)
-    hipLaunchKernelGGL(k_conv<true>, dim3(T.n), dim3(64), 0, s, ptr<ConvItem>(T.items), N.geo, W, wstride, bias,
+    hipLaunchKernelGGL(k_conv<true>, dim3(T.n), dim3(kConvThreads), 0, s, ptr<ConvItem>(T.items), N.geo, W, wstride, bias,
                        bstride, plane, sign, relu, in, out, mask);
   else
-    hipLaunchKernelGGL(k_conv<false>, dim3(T.n), dim3(64), 0, s, ptr<ConvItem>(T.items), N.geo, W, wstride, bias,
+    hipLaunchKernelGGL(k_conv<false>, dim3(T.n), dim3(kConvThreads), 0, s, ptr<ConvItem>(T.items), N.geo, W, wstride, bias,
                        bstride, plane, sign, relu, in, out, mask);
   NET_CHECK();
 }
