@@ -352,12 +352,17 @@ __global__ void k_unpack(NetGeom geo, const float* __restrict__ y, const float* 
 }
 
 // raw tensors [p][R] <-> [p][32]
+// one point per thread: R channels, zero padding, four 16-byte stores (R <= 8)
 __global__ void k_raw_in(int64_t P, int R, const float* __restrict__ x, __bf16* __restrict__ h) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= P * NC) return;
-  const int64_t p = i / NC;
-  const int c = int(i - p * NC);
-  h[i] = __bf16(c < R ? x[p * R + c] : 0.0f);
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  bf16x8 out[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = zero8();
+  for (int c = 0; c < R; ++c) out[0][c] = __bf16(x[p * R + c]);
+  bf16x8* dst = reinterpret_cast<bf16x8*>(h + p * NC);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = out[q];
 }
 __global__ void k_raw_out(int64_t P, int R, const float* __restrict__ y, float* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -938,7 +943,7 @@ extern "C" sgdg_status sgdg_net_forward(sgdg_net n, const float* x_dev, float* y
   Net& N = *n;
   const Net::Tab& T = conv_tab(N, 1, per_item(N, 1, 2048));
   ensure_act(N, 1);
-  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot * NC)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, x_dev,
+  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, x_dev,
                      actbuf(N, 1, 0));
   NET_CHECK();
   forward(N, T, 1, s);
@@ -956,11 +961,11 @@ extern "C" sgdg_status sgdg_net_backward(sgdg_net n, const float* x_dev, const f
   Net& N = *n;
   const Net::Tab& T = conv_tab(N, 1, per_item(N, 1, 2048));
   ensure_act(N, 1);
-  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot * NC)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, x_dev,
+  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, x_dev,
                      actbuf(N, 1, 0));
   NET_CHECK();
   forward(N, T, 1, s);
-  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot * NC)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, dy_dev,
+  hipLaunchKernelGGL(k_raw_in, dim3(nb(N.geo.Ptot)), dim3(256), 0, s, N.geo.Ptot, N.geo.R, dy_dev,
                      ptr<__bf16>(N.D0));
   NET_CHECK();
   backward(N, T, 1, s);
