@@ -85,6 +85,7 @@ struct TileItem {
   int prob, grid;
   int x0[3];
   int v0, t, vb;
+  uint64_t gmask;  // bit m: X-group m has a nonzero row among the tile's x-nodes (groups >= 64: always)
 };
 
 template <class T>

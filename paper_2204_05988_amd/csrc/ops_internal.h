@@ -94,14 +94,16 @@ struct sgdg_grid_s {
 
 struct DomDev {
   DevBuf nbr, tnbr, par, parw, chi, chiw, tchi, tchiw, vals, vals32, tvals, tvals32, wide, rvals, rvals32, twide,
-      trvals, trvals32, pidx, pvals, pvals32, qvals, qvals32, qpvals, qpvals32;
+      trvals, trvals32, pidx, pvals, pvals32, qvals, qvals32, qpvals, qpvals32, sup, fpartial;
   DevDomain d;
+  std::vector<uint8_t> hsup, hpartial;  // host copies of d.sup, d.fpartial
 };
 
 struct OpDev {
   TermList host;
-  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs;
+  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm;
   DevOp op;
+  std::vector<int> hxgf;  // host copy of op.xg_fac
 };
 
 // A batch of independent strip problems sharing dimension and time degree

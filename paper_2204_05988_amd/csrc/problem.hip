@@ -181,6 +181,43 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   d.vals = upload(dd.vals, vals);
   d.vals32 = upload(dd.vals32, v32);
   {
+    int64_t no = 0;
+    for (int l = D.lmin; l <= D.lmax; ++l) {
+      d.node_off[l - D.lmin] = no;
+      no += D.L(l).n;
+    }
+    d.node_stride = no;
+    dd.hsup.assign(nf * size_t(no), 0);
+    dd.hpartial.assign(nf, 0);
+    for (size_t f = 0; f < nf; ++f) {
+      uint8_t* sf = dd.hsup.data() + f * no;
+      for (int l = D.lmin; l <= D.lmax; ++l) {
+        const LevelTables& T = D.L(l);
+        const auto& val = D.values[f][l - D.lmin];
+        uint8_t* sl = sf + d.node_off[l - D.lmin];
+        for (int64_t i = 0; i < T.n; ++i)
+          for (int e = 0; e < S; ++e)
+            if (val[size_t(i) * S + e] != 0.0) {
+              sl[i] |= 1;
+              sl[T.nbr[size_t(i) * S + e]] |= 2;
+            }
+      }
+      // bit 2: the node is a stencil neighbour of a nonzero row (read by
+      // the x-stencil of a row that has a nonzero)
+      for (int l = D.lmin; l <= D.lmax; ++l) {
+        const LevelTables& T = D.L(l);
+        uint8_t* sl = sf + d.node_off[l - D.lmin];
+        for (int64_t i = 0; i < T.n; ++i)
+          if (sl[i] & 1)
+            for (int e = 0; e < S; ++e) sl[T.nbr[size_t(i) * S + e]] |= 4;
+      }
+      for (int64_t i = 0; i < no; ++i)
+        if ((sf[i] & 3) != 3) dd.hpartial[f] = 1;
+    }
+    d.sup = upload(dd.sup, dd.hsup);
+    d.fpartial = upload(dd.fpartial, dd.hpartial);
+  }
+  {
     std::vector<double> t;
     slot_major(t, vals, nf, o, S, loff);
     std::vector<float> t32(t.size());
@@ -284,7 +321,7 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   }
 }
 
-static void upload_op(OpDev& od) {
+static void upload_op(OpDev& od, const DomDev& dx) {
   const TermList& L = od.host;
   std::vector<int> xf, vf, vg, xg, vgf, xgf;
   std::vector<double> tm;
@@ -340,6 +377,22 @@ static void upload_op(OpDev& od) {
   op.term_tm32 = upload(od.tm32, tm32);
   op.vg_fac = upload(od.vgf, vgf);
   op.xg_fac = upload(od.xgf, xgf);
+  od.hxgf = xgf;
+  // per x-node masks of the X-groups (bit m for m < 64): the node's row of
+  // the group's factor has a nonzero; the x-stencil of such a row reads the node
+  const int64_t no = dx.d.node_stride;
+  std::vector<uint64_t> rowm(size_t(no), 0), readm(size_t(no), 0);
+  for (size_t m = 0; m < xgf.size() && m < 64; ++m) {
+    const size_t f = size_t(xgf[m]);
+    const uint64_t bit = uint64_t(1) << m;
+    for (int64_t i = 0; i < no; ++i) {
+      const uint8_t sp = dx.hsup[f * size_t(no) + size_t(i)];
+      if (!dx.hpartial[f] || (sp & 1)) rowm[size_t(i)] |= bit;
+      if (!dx.hpartial[f] || (sp & 4)) readm[size_t(i)] |= bit;
+    }
+  }
+  op.xrow_mask = upload(od.xrowm, rowm);
+  op.xread_mask = upload(od.xreadm, readm);
 }
 
 static void invert_small(int R, const double* A, double* inv) {
@@ -427,7 +480,7 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   o->dv.d.mass_fac = mfv;
   for (int k = 0; k < 4; ++k) {
     o->ops[k].host = tl[k];
-    upload_op(o->ops[k]);
+    upload_op(o->ops[k], o->dx);
   }
   // inner preconditioner time block (Tt + delta Ct + Gt)^-1
   const int R = g->R;

@@ -182,6 +182,14 @@ struct DevDomain {
   const double* qpvals = nullptr;     // [factor][levels [PW/2][n][2]]
   const float* qpvals32 = nullptr;
   int64_t qpstride = 0;               // elements per factor
+  // support of each factor matrix per node: bit 0 its row has a nonzero,
+  // bit 1 it is the column of a nonzero, bit 2 it is a stencil neighbour of a
+  // row with a nonzero; a factor is partial when some node lacks bit 0 or 1
+  // (face masses: only the face's nodes)
+  int64_t node_off[kMaxLevels] = {};  // first node of level l in the per-node tables
+  int64_t node_stride = 0;            // nodes of all levels (per factor)
+  const uint8_t* sup = nullptr;       // [factor][nodes]
+  const uint8_t* fpartial = nullptr;  // [factor]
 };
 
 struct DevGrids {
@@ -205,6 +213,10 @@ struct DevOp {
   const int* vg_start = nullptr;     // [nvg + 1]
   const int* xg_terms = nullptr;     // term indices ordered by X group
   const int* xg_start = nullptr;     // [nxg + 1]
+  // per x-node (the x-domain's node_off layout), bit m for X-group m < 64:
+  // row of the group's factor has a nonzero / read by the x-stencil of such a row
+  const uint64_t* xrow_mask = nullptr;
+  const uint64_t* xread_mask = nullptr;
 };
 
 // Device buffer helper.

@@ -272,6 +272,36 @@ static KindData& kind(Batch& B, int k) {
           }
           ti.t = t;
           ti.vb = vb;
+          // X-groups whose factor has a nonzero row on the tile (a face term
+          // only on tiles that touch its face)
+          {
+            const DomDev& dx = o->dx;
+            const std::vector<int>& xgf = o->ops[opidx].hxgf;
+            const int lxg = D.G.lx[gi];
+            const int64_t noff = dx.d.node_off[lxg - dx.d.lmin];
+            ti.gmask = 0;
+            for (size_t m = 0; m < xgf.size() && m < 64; ++m) {
+              bool need = dx.hpartial[size_t(xgf[m])] == 0;
+              const uint8_t* sp = dx.hsup.data() + size_t(xgf[m]) * size_t(dx.d.node_stride) + noff;
+              int nt = 1;
+              for (int a = 0; a < B.d; ++a) nt *= t;
+              for (int xi = 0; xi < nt && !need; ++xi) {
+                int rr = xi, node = 0;
+                bool in = true;
+                int c[3] = {0, 0, 0};
+                for (int a = B.d - 1; a >= 0; --a) {
+                  c[a] = ti.x0[a] + rr % t;
+                  rr /= t;
+                }
+                for (int a = 0; a < B.d; ++a) {
+                  in = in && c[a] < mxg2;
+                  node = node * mxg2 + c[a];
+                }
+                need = in && (sp[node] & 1);
+              }
+              if (need) ti.gmask |= uint64_t(1) << m;
+            }
+          }
           int halo = 1;
           for (int a = 0; a < B.d; ++a) halo *= t + 2;
           K.max_tile = std::max(K.max_tile, halo * vb);

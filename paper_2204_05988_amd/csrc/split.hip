@@ -97,6 +97,16 @@ __device__ __forceinline__ void block_coords(const SplitCall<T>& C, int& item, i
   item = L - vg * int(gridDim.x);
 }
 
+// X-groups whose factor's stencil rows with a nonzero read x-node x of level
+// lx (read_needs), or whose factor has a nonzero in row x (row_needs); bit m
+// for group m < 64 (groups beyond are always taken)
+__device__ __forceinline__ uint64_t read_needs(const DevDomain& DX, const DevOp& op, int lx, int x) {
+  return op.xread_mask[DX.node_off[lx - DX.lmin] + x];
+}
+__device__ __forceinline__ uint64_t row_needs(const DevDomain& DX, const DevOp& op, int lx, int x) {
+  return op.xrow_mask[DX.node_off[lx - DX.lmin] + x];
+}
+
 template <class T, int D, int R, int BC>
 __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
@@ -132,6 +142,12 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const int64_t total = A.G.off[A.G.n];
   const int64_t ltotal = A.Gl.off[A.Gl.n];
   const T* tm = tmat<T>(op);
+  // W^m is read only by the x-stencils of the rows where X-group m's factor
+  // has a nonzero: a face term's W is needed on its face's x-nodes and their
+  // stencil neighbours alone; elsewhere its terms are skipped and nothing is
+  // stored (the x-stage skips the rows that would read it there)
+  const uint64_t need = read_needs(A.DX, op, lx, x);
+  auto needs = [&](int m) { return m >= 64 || ((need >> m) & 1); };
   T un[BC][R][SS];
 #pragma unroll
   for (int q = 0; q < BC; ++q) {
@@ -149,6 +165,15 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   const int nt = op.xg_start[op.nxg];
   auto load = [&](int kk, T (&f)[SS], T (&pv)[BC][R][2]) {
     const int k = op.xg_terms[kk];
+    if (!needs(op.term_xg[k])) {
+#pragma unroll
+      for (int e = 0; e < SS; ++e) f[e] = T(0);
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) pv[q][s2][0] = pv[q][s2][1] = T(0);
+      return;
+    }
     load_slot_pairs<T, SS>(qvals<T>(A.DV) + int64_t(op.term_vf[k]) * A.DV.qfac_stride + A.DV.qlev_off[lv - A.DV.lmin],
                            nv, v, f);
     const int j = op.term_vg[k];
@@ -177,10 +202,11 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
 #pragma unroll
     for (int s = 0; s < R; ++s) w[q][s] = T(0);
   auto store = [&](int m) {
+    const bool nm = needs(m);
 #pragma unroll
     for (int q = 0; q < BC; ++q) {
       const int b = b0 + q;
-      if (b < C.B) {
+      if (b < C.B && nm) {
         // W is read once, by the x-stage pass: stream it past the caches (a
         // 2-wide store of the slice pair measured slower than two scalar ones)
         T* zb = C.Z + int64_t(b) * C.z_bstride + A.z_off + int64_t(m) * total + A.G.off[g] + p * R;
@@ -214,6 +240,10 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
       load(kk, fc, pc);
     }
     while (kk >= op.xg_start[m + 1]) store(m++);  // empty groups before this term's
+    if (!needs(m)) {
+      if (kk + 1 == op.xg_start[m + 1]) store(m++);
+      continue;
+    }
     const T* tk = tm + int64_t(op.xg_terms[kk]) * R * R;
     T tkv[R * R];
 #pragma unroll
@@ -453,8 +483,13 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
   for (int q = 0; q < BC; ++q)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
-  // diagonal + lower partners: one x-stencil per X-group on the staged W
+  // diagonal + lower partners: one x-stencil per X-group on the staged W.
+  // A group whose factor row is zero here is skipped (its W^m is staged only
+  // around the rows with a nonzero); so are a partial group's zero slots.
+  const uint64_t need = row_needs(A.DX, op, lx, x);
   for (int m = 0; m < op.nxg; ++m) {
+    if (m < 64 && !((need >> m) & 1)) continue;
+    const bool part = A.DX.fpartial[op.xg_fac[m]] != 0;
     T xf[SS];
     load_slot_pairs<T, SS>(qvals<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.qfac_stride + A.DX.qlev_off[lx - A.DX.lmin],
                            nx, x, xf);
@@ -467,6 +502,7 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
       for (int s = 0; s < R; ++s) t[s] = T(0);
 #pragma unroll
       for (int e = 0; e < SS; ++e) {
+        if (part && xf[e] == T(0)) continue;
         T zz[R];
         load_slices<T, R>(zb + int64_t(nbx[e]) * nv * R, zz);
 #pragma unroll
@@ -646,9 +682,22 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
   for (int q = 0; q < BC; ++q)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
-  fetch(0);
-  ffetch(0);
-  for (int m = 0; m < op.nxg; ++m) {
+  // the tile's groups (it.gmask: groups with a nonzero factor row on the
+  // tile); within one, a thread whose row of the factor is zero adds nothing
+  // (the staged W^m of a partial group is valid only around its nonzero rows)
+  const uint64_t rneed = act ? row_needs(A.DX, op, lx, x) : 0;
+  auto gnext = [&](int m) {
+    ++m;
+    while (m < op.nxg && m < 64 && !((it.gmask >> m) & 1)) ++m;
+    return m;
+  };
+  int m = gnext(-1);
+  if (m < op.nxg) {
+    fetch(m);
+    ffetch(m);
+  }
+  while (m < op.nxg) {
+    const int mn = gnext(m);
     __syncthreads();  // the previous group's reads are done
 #pragma unroll
     for (int i = 0; i < BC * R; ++i)
@@ -668,12 +717,12 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
 #pragma unroll
       for (int e = 0; e < SS; ++e) xc[e] = fpre[e];
     }
-    if (m + 1 < op.nxg) {
-      fetch(m + 1);
-      ffetch(m + 1);
+    if (mn < op.nxg) {
+      fetch(mn);
+      ffetch(mn);
     }
     __syncthreads();
-    if (act) {
+    if (act && (m >= 64 || ((rneed >> m) & 1))) {
       if constexpr (kFacLds) {
 #pragma unroll
         for (int e = 0; e < SS; ++e) xc[e] = sf[e * tn + xl];
@@ -689,6 +738,7 @@ __global__ void __launch_bounds__(kSB) k_xtile(SplitCall<T> C) {
           acc[q][s] += a;
         }
     }
+    m = mn;
   }
   if (!act) return;
   const int64_t p = int64_t(x) * nv + v;
