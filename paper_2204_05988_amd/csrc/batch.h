@@ -72,6 +72,9 @@ struct FusedCall {
 struct SplitItem {
   int prob, grid;
   int64_t p0;  // first point (x * nv + v) of the block
+  // upper-partner pass: bit m, Qt^m can be nonzero on one of the block's
+  // x-rows (groups >= 64: always)
+  uint64_t gmask;
   // upper-partner pass (d <= 2): the in-lattice prolongation slots of the
   // block's points, as x * nvl + coarse node on the lower grid, lie in
   // [q0, q0 + qn); qn = 0 when the grid has no upper partner

@@ -101,9 +101,10 @@ struct DomDev {
 
 struct OpDev {
   TermList host;
-  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm;
+  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm, xqtm;
   DevOp op;
-  std::vector<int> hxgf;  // host copy of op.xg_fac
+  std::vector<int> hxgf;       // host copy of op.xg_fac
+  std::vector<uint64_t> hxqtm;  // host copy of op.xqt_mask
 };
 
 // A batch of independent strip problems sharing dimension and time degree

@@ -321,7 +321,7 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   }
 }
 
-static void upload_op(OpDev& od, const DomDev& dx) {
+static void upload_op(OpDev& od, const DomainData& X, const DomDev& dx) {
   const TermList& L = od.host;
   std::vector<int> xf, vf, vg, xg, vgf, xgf;
   std::vector<double> tm;
@@ -391,8 +391,23 @@ static void upload_op(OpDev& od, const DomDev& dx) {
       if (!dx.hpartial[f] || (sp & 4)) readm[size_t(i)] |= bit;
     }
   }
+  // the upper-partner arrays Qt^m at x-level l restrict the level-(l+1)
+  // product X_m u and Qt^m of level l + 1: they can be nonzero only at the
+  // embedding parents of the level-(l+1) nodes where either can be
+  std::vector<uint64_t> qm(size_t(no), 0);
+  for (int l = X.lmax - 1; l >= X.lmin; --l) {
+    const LevelTables& F = X.L(l + 1);
+    const int64_t fo = dx.d.node_off[l + 1 - X.lmin], co = dx.d.node_off[l - X.lmin];
+    for (int64_t f = 0; f < F.n; ++f) {
+      const uint64_t src = rowm[size_t(fo + f)] | qm[size_t(fo + f)];
+      for (int j = 0; j < 2; ++j)
+        if (F.parw[size_t(f) * 2 + j] != 0.0) qm[size_t(co + F.par[size_t(f) * 2 + j])] |= src;
+    }
+  }
   op.xrow_mask = upload(od.xrowm, rowm);
   op.xread_mask = upload(od.xreadm, readm);
+  op.xqt_mask = upload(od.xqtm, qm);
+  od.hxqtm = qm;
 }
 
 static void invert_small(int R, const double* A, double* inv) {
@@ -480,7 +495,7 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   o->dv.d.mass_fac = mfv;
   for (int k = 0; k < 4; ++k) {
     o->ops[k].host = tl[k];
-    upload_op(o->ops[k], o->dx);
+    upload_op(o->ops[k], o->X, o->dx);
   }
   // inner preconditioner time block (Tt + delta Ct + Gt)^-1
   const int R = g->R;

@@ -217,6 +217,8 @@ struct DevOp {
   // row of the group's factor has a nonzero / read by the x-stencil of such a row
   const uint64_t* xrow_mask = nullptr;
   const uint64_t* xread_mask = nullptr;
+  // per x-node, bit m: the upper-partner array Qt^m can be nonzero there
+  const uint64_t* xqt_mask = nullptr;
 };
 
 // Device buffer helper.

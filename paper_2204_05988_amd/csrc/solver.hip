@@ -230,7 +230,19 @@ static KindData& kind(Batch& B, int k) {
       std::stable_sort(keyed.begin(), keyed.end());
       const bool upper = !D.diag_only && gi + 1 < D.G.n && B.d <= 2;
       for (const auto& kp : keyed) {
-        SplitItem it{int(p), gi, kp.second, 0, 0};
+        SplitItem it{};
+        it.prob = int(p);
+        it.grid = gi;
+        it.p0 = kp.second;
+        it.gmask = ~uint64_t(0);
+        if (upper) {
+          // X-groups whose Qt can be nonzero on the block's x-rows
+          const std::vector<uint64_t>& qm = o->ops[opidx].hxqtm;
+          const int64_t noff = o->dx.d.node_off[D.G.lx[gi] - o->dx.d.lmin];
+          const int64_t pend = std::min<int64_t>(kp.second + split_points_per_item(), plane);
+          it.gmask = 0;
+          for (int64_t xr = kp.second / nvg; xr <= (pend - 1) / nvg; ++xr) it.gmask |= qm[size_t(noff + xr)];
+        }
         if (upper) {
           // the prolongation slots of every point, from the level's slot table
           const std::vector<int32_t>& ptab = o->V.pro_idx[D.G.lv[gi] - o->V.lmin];

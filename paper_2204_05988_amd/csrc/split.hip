@@ -386,10 +386,20 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
           }
         }
       };
-      fetch(0);
+      // only the X-groups whose Qt^m can be nonzero on the block's rows
+      // (it.gmask), and per thread on its own row (face terms off the face)
+      const uint64_t rneed = act ? op.xqt_mask[A.DX.node_off[A.G.lx[g] - A.DX.lmin] + x] : 0;
+      auto gnext = [&](int m) {
+        ++m;
+        while (m < op.nxg && m < 64 && !((it.gmask >> m) & 1)) ++m;
+        return m;
+      };
+      int m = gnext(-1);
+      if (m < op.nxg) fetch(m);
       const int qo = int(int64_t(x) * nvl - it.q0);  // every slot of the item lies in the range (host)
-      for (int m = 0; m < op.nxg; ++m) {
-        T* cur = sq + (m & 1) * (BC * qnr);
+      for (int n = 0; m < op.nxg; ++n) {
+        const int mn = gnext(m);
+        T* cur = sq + (n & 1) * (BC * qnr);
 #pragma unroll
         for (int q = 0; q < BC; ++q)
 #pragma unroll
@@ -398,11 +408,12 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
             if (i < qnr) cur[q * qnr + i] = pre[q][j];
           }
         const int ka = op.xg_start[m], kb = op.xg_start[m + 1];
+        const bool use = act && ka < kb && (m >= 64 || ((rneed >> m) & 1));
         T vf[NS];
-        if (ka < kb) factors(op.xg_terms[ka], vf);
-        if (m + 1 < op.nxg) fetch(m + 1);
+        if (use) factors(op.xg_terms[ka], vf);
+        if (mn < op.nxg) fetch(mn);
         __syncthreads();  // cur is complete; the buffer written next was last read before this barrier
-        if (act && ka < kb) {
+        if (use) {
           T qv[BC][R][NS];
 #pragma unroll
           for (int q = 0; q < BC; ++q)
@@ -419,10 +430,12 @@ __global__ void __launch_bounds__(kSB) k_ustage(SplitCall<T> C) {
             term(op.xg_terms[kk], vf, qv);
           }
         }
+        m = mn;
       }
     } else {
+      const uint64_t rneed = act ? op.xqt_mask[A.DX.node_off[A.G.lx[g] - A.DX.lmin] + x] : 0;
       for (int m = 0; m < op.nxg; ++m) {
-        if (!act) continue;
+        if (!act || (m < 64 && !((rneed >> m) & 1))) continue;
         const T* qm = C.Qt + A.qt_off + int64_t(m) * ltotal + A.Gl.off[g];
         T qv[BC][R][NS];
 #pragma unroll
