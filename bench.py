@@ -83,6 +83,11 @@ def kernel_work(ops, B, R, elem_bytes):
                 flops nvg R (2S + 4) + nt R (2S + 2R) [+ nxg R 4 + nt R (2S + 2R) if i < n-1];
                 bytes u (R) + y (R) + Pt, Qt (nvg R / 2^d, nxg R / 2^d)
     The partner scan arrays live on the lower diagonal, 2^d times smaller.
+    Face masses vanish off their face: in the split passes the X-group counts
+    and the terms above are the per-x-node averages of where each group can
+    contribute (sgdg_op_support): W^m staged where a nonzero row's stencil
+    reads it (v-stage work, x-stage W reads), rows with a nonzero (x-stage
+    flops), and where Qt^m can be nonzero (upper-partner pass).
     """
     info = ops.op_info()
     nt, nvg, nxg = info["nterms"], info["nvg"], info["nxg"]
@@ -90,19 +95,23 @@ def kernel_work(ops, B, R, elem_bytes):
     S = {1: 3, 2: 7, 3: 15}[d]
     n = len(ops.upper)
     work = {k: [0.0, 0.0] for k in ("vstage", "ustage", "xstage", "fused")}
-    for gi, (_, _, nx, nv) in enumerate(ops.upper):
+    for gi, (lx, _, nx, nv) in enumerate(ops.upper):
         pts = nx * nv * B
         hp, hq = gi > 0, gi + 1 < n
+        sup = ops.op_support(lx)
+        rt, rg = sup["read_terms"] / sup["nodes"], sup["read_groups"] / sup["nodes"]
+        wg = sup["row_groups"] / sup["nodes"]
+        qg, qtt = sup["qt_groups"] / sup["nodes"], sup["qt_terms"] / sup["nodes"]
 
         def add(k, fl, by):
             work[k][0] += pts * fl
             work[k][1] += pts * by * elem_bytes
-        add("vstage", nt * R * 2 * S + nt * 2 * R * R + (nt * R * 4 if hp else 0),
-            R + nxg * R + (nt * R / 2 ** d if hp else 0))
-        uf = nt * (R * 2 * 3 ** d + 2 * R * R) if d <= 2 else nxg * S * R * 4 + nt * (R * 2 * S + 2 * R * R)
+        add("vstage", rt * R * 2 * S + rt * 2 * R * R + (rt * R * 4 if hp else 0),
+            R + rg * R + (rt * R / 2 ** d if hp else 0))
+        uf = qtt * (R * 2 * 3 ** d + 2 * R * R) if d <= 2 else qg * S * R * 4 + qtt * (R * 2 * S + 2 * R * R)
         add("ustage", uf if hq else 0,
-            (nxg * R / 2 ** d if hq else 0) + R)
-        add("xstage", nxg * R * 2 * S, nxg * R + 2 * R)
+            (qg * R / 2 ** d if hq else 0) + R)
+        add("xstage", wg * R * 2 * S, rg * R + 2 * R)
         add("fused", nvg * R * (2 * S + 4) + nt * R * (2 * S + 2 * R) + ((nxg * R * 4 + nt * R * (2 * S + 2 * R)) if hq else 0),
             2 * R + (nvg * R / 2 ** d if hp else 0) + (nxg * R / 2 ** d if hq else 0))
     return work

@@ -376,6 +376,17 @@ sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64_t* launche
  * sizes of the two domains and the time slices in/out. */
 sgdg_status sgdg_op_info(sgdg_ops o, int kind, int* nterms, int* nvg, int* nxg, int* Sx, int* Sv, int* Rin,
                          int* Rout);
+/* Host-only: where the X-factors of operator `kind` can contribute on x-level
+ * lx (Sect. 4.2's factors are sparse; face masses live on their face alone).
+ * counts (6 entries, caller-owned) = { x-nodes of the level;
+ * (node, X-group) pairs whose staged W^m is read by the x-stencil of a row
+ * where the group's factor has a nonzero (the v-stage computes exactly
+ * these); the Kronecker terms of those pairs; (node, X-group) pairs whose
+ * factor row has a nonzero (the x-stage applies exactly these); (node,
+ * X-group) pairs where the upper-partner array Qt^m can be nonzero; the terms
+ * of those pairs }.  Groups beyond the 64th count everywhere.  SGDG_E_ARG for
+ * a null handle or array, an unknown kind or a level outside the hierarchy. */
+sgdg_status sgdg_op_support(sgdg_ops o, int kind, int lx, int64_t* counts);
 
 /* Host-only: dense block (row_grid, col_grid) of the operator `kind` (FULL,
  * MASS, DATA_F or DATA_G; not BLOCKDIAG) assembled from the host factor

@@ -103,8 +103,8 @@ struct OpDev {
   TermList host;
   DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm, xqtm;
   DevOp op;
-  std::vector<int> hxgf;       // host copy of op.xg_fac
-  std::vector<uint64_t> hxqtm;  // host copy of op.xqt_mask
+  std::vector<int> hxgf, hxgs;                 // host copies of op.xg_fac, op.xg_start
+  std::vector<uint64_t> hxrowm, hxreadm, hxqtm;  // host copies of the per-node group masks
 };
 
 // A batch of independent strip problems sharing dimension and time degree

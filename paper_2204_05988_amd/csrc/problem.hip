@@ -407,7 +407,10 @@ static void upload_op(OpDev& od, const DomainData& X, const DomDev& dx) {
   op.xrow_mask = upload(od.xrowm, rowm);
   op.xread_mask = upload(od.xreadm, readm);
   op.xqt_mask = upload(od.xqtm, qm);
+  od.hxrowm = rowm;
+  od.hxreadm = readm;
   od.hxqtm = qm;
+  od.hxgs = xgs;
 }
 
 static void invert_small(int R, const double* A, double* inv) {

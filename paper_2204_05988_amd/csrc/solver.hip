@@ -1563,6 +1563,35 @@ extern "C" sgdg_status sgdg_op_info(sgdg_ops o, int kind_, int* nterms, int* nvg
   API_END
 }
 
+extern "C" sgdg_status sgdg_op_support(sgdg_ops o, int kind_, int lx, int64_t* counts) {
+  API_BEGIN
+  require(o != nullptr && counts != nullptr && kind_ >= SGDG_OP_FULL && kind_ <= SGDG_OP_DATA_G, "bad arguments");
+  const DevDomain& dx = o->dx.d;
+  require(lx >= dx.lmin && lx <= dx.lmax, "x-level outside the hierarchy");
+  const int idx = kind_ == SGDG_OP_FULL || kind_ == SGDG_OP_BLOCKDIAG ? 0 : kind_ - 1;
+  const OpDev& od = o->ops[idx];
+  const int nxg = od.op.nxg;
+  const int64_t n = dx.lev_n[lx - dx.lmin], no = dx.node_off[lx - dx.lmin];
+  for (int i = 0; i < 6; ++i) counts[i] = 0;
+  counts[0] = n;
+  for (int64_t x = 0; x < n; ++x)
+    for (int m = 0; m < nxg; ++m) {
+      const int64_t nt = od.hxgs[size_t(m) + 1] - od.hxgs[size_t(m)];
+      const bool all = m >= 64;
+      const uint64_t bit = all ? 0 : uint64_t(1) << m;
+      if (all || (od.hxreadm[size_t(no + x)] & bit)) {
+        counts[1] += 1;
+        counts[2] += nt;
+      }
+      if (all || (od.hxrowm[size_t(no + x)] & bit)) counts[3] += 1;
+      if (all || (od.hxqtm[size_t(no + x)] & bit)) {
+        counts[4] += 1;
+        counts[5] += nt;
+      }
+    }
+  API_END
+}
+
 extern "C" sgdg_status sgdg_tune(sgdg_ops o, sgdg_dtype t, int batch, int reps, int force, sgdg_tune_result* out,
                                  hipStream_t s) {
   API_BEGIN

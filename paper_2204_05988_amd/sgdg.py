@@ -22,7 +22,7 @@ EXPORTS = [
     "sgdg_last_error", "sgdg_build_sparse_grid", "sgdg_grid_info", "sgdg_grid_destroy",
     "sgdg_assemble_1d_factors", "sgdg_ops_destroy", "sgdg_apply_operator", "sgdg_combine",
     "sgdg_precondition", "sgdg_rhs", "sgdg_solve_strip", "sgdg_debug_dense_block",
-    "sgdg_profile", "sgdg_profile_read", "sgdg_op_info",
+    "sgdg_profile", "sgdg_profile_read", "sgdg_op_info", "sgdg_op_support",
     "sgdg_batch_create", "sgdg_batch_layout", "sgdg_batch_apply", "sgdg_batch_solve", "sgdg_batch_destroy",
     "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
@@ -118,6 +118,7 @@ def lib():
     L.sgdg_profile.argtypes = [vp, C.c_int]
     L.sgdg_profile_read.argtypes = [vp, C.c_int, dp, i64p]
     L.sgdg_op_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip, ip, ip]
+    L.sgdg_op_support.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int64)]
     L.sgdg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
     L.sgdg_batch_layout.argtypes = [vp, i64p]
     L.sgdg_batch_apply.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -317,6 +318,12 @@ class SparseGridOps:
         v = [C.c_int() for _ in range(7)]
         _check(lib().sgdg_op_info(self.ops, kind, *[C.byref(x) for x in v]))
         return dict(zip(["nterms", "nvg", "nxg", "Sx", "Sv", "Rin", "Rout"], [x.value for x in v]))
+
+    def op_support(self, lx, kind=OP_FULL):
+        """Per x-level support counts of the X-factors (see sgdg_op_support)."""
+        c = (C.c_int64 * 6)()
+        _check(lib().sgdg_op_support(self.ops, kind, lx, c))
+        return dict(zip(["nodes", "read_groups", "read_terms", "row_groups", "qt_groups", "qt_terms"], list(c)))
 
     def tune(self, dtype="f64", batch=1, reps=3, force=False, stream=None):
         """Pick the fastest launch configuration of the full apply (cached on disk)."""
