@@ -66,6 +66,9 @@ struct FusedCall {
   int64_t rv_bstride, rx_bstride;
   T* Rv;                   // restrictions of the previous scan step, same slice order
   T* Rx;
+  // 1: the scans fill the partner arrays only where the split passes read
+  // them (the op's xpt_mask / xqt_mask); 0: everywhere (the box-tiled kernel)
+  int sparse_partners;
 };
 
 // Split application: one block of points of one grid of one problem.

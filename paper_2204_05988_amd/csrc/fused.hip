@@ -383,6 +383,8 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       const int xc = int(e / nvt), vc = int(e - int64_t(e / nvt) * nvt);
       const int lvc = G.lv[lg] - 1 - A.DV.lmin;
       const int64_t co = A.DV.lev_off[lvc] + vc;
+      // Pt_{t-1} holds values only on the rows where it is read
+      const uint64_t need = C.sparse_partners ? op.xpt_mask[A.DX.node_off[G.lx[lg - 1] - A.DX.lmin] + xc] : ~uint64_t(0);
       int32_t ch[SS];
       T cw[SS];
 #pragma unroll
@@ -390,7 +392,8 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         ch[c] = A.DV.tchi[co + int64_t(c) * nvt];
         cw[c] = T(A.DV.tchiw[co + int64_t(c) * nvt]);
       }
-      for (int j = g0; j < g1; ++j)
+      for (int j = g0; j < g1; ++j) {
+        if (j < 64 && !((need >> j) & 1)) continue;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(xc) * nvs * R + s;
@@ -399,6 +402,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
           for (int c = 0; c < SS; ++c) acc += cw[c] * row[int64_t(ch[c]) * R];
           Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + e * R + s] = acc;
         }
+      }
     } else {
       // Rx_l[xc][vq] = sum_c chiw_c(xc) Qt_{l+1}[chi_c(xc)][vq], xc on the target's x-level
       const int nxt = L.nx[lg], nvs = L.nv[lg + 1];
@@ -443,6 +447,8 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
     for (int o = 0; o < W; ++o) wi[o] = A.DV.twide[A.DV.wlev_off[lvc] + int64_t(o) * nvl + v];
     const bool has_p = src > 0;
+    // Pt^j is computed only where it is read (v-groups of face terms: near the x-faces)
+    const uint64_t need = C.sparse_partners ? op.xpt_mask[A.DX.node_off[G.lx[src] - A.DX.lmin] + x] : ~uint64_t(0);
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
     if (has_p) {
@@ -461,6 +467,7 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         for (int o = 0; o < W; ++o) un[q][o] = us[wi[o]];
       }
       for (int j = g0; j < g1; ++j) {
+        if (j < 64 && !((need >> j) & 1)) continue;
         const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + v;
         T rr[W];
 #pragma unroll

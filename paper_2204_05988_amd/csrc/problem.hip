@@ -404,9 +404,30 @@ static void upload_op(OpDev& od, const DomainData& X, const DomDev& dx) {
         if (F.parw[size_t(f) * 2 + j] != 0.0) qm[size_t(co + F.par[size_t(f) * 2 + j])] |= src;
     }
   }
+  // the lower-partner arrays Pt^j at x-level l are read by the v-stage at the
+  // embedding parents of the level-(l+1) rows that stage a term of v-group j,
+  // and by the next scan step at the parents of its own rows: they are needed
+  // only at the parents of the nodes where either holds
+  std::vector<uint64_t> rj(size_t(no), 0), pm(size_t(no), 0);
+  for (size_t k = 0; k < vg.size(); ++k) {
+    if (vg[k] >= 64) continue;
+    const uint64_t bj = uint64_t(1) << vg[k];
+    for (int64_t i = 0; i < no; ++i)
+      if (xg[k] >= 64 || ((readm[size_t(i)] >> xg[k]) & 1)) rj[size_t(i)] |= bj;
+  }
+  for (int l = X.lmax - 1; l >= X.lmin; --l) {
+    const LevelTables& F = X.L(l + 1);
+    const int64_t fo = dx.d.node_off[l + 1 - X.lmin], co = dx.d.node_off[l - X.lmin];
+    for (int64_t f = 0; f < F.n; ++f) {
+      // both parent slots, a zero-weight one included: the readers load both
+      const uint64_t src = rj[size_t(fo + f)] | pm[size_t(fo + f)];
+      for (int j = 0; j < 2; ++j) pm[size_t(co + F.par[size_t(f) * 2 + j])] |= src;
+    }
+  }
   op.xrow_mask = upload(od.xrowm, rowm);
   op.xread_mask = upload(od.xreadm, readm);
   op.xqt_mask = upload(od.xqtm, qm);
+  op.xpt_mask = upload(od.xptm, pm);
   od.hxrowm = rowm;
   od.hxreadm = readm;
   od.hxqtm = qm;

@@ -219,6 +219,8 @@ struct DevOp {
   const uint64_t* xread_mask = nullptr;
   // per x-node, bit m: the upper-partner array Qt^m can be nonzero there
   const uint64_t* xqt_mask = nullptr;
+  // per x-node, bit j of V-group j < 64: the lower-partner array Pt^j is read there
+  const uint64_t* xpt_mask = nullptr;
 };
 
 // Device buffer helper.

@@ -513,6 +513,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   C.u_bstride = C.y_bstride = K.total;
   C.u = u;
   C.y = y;
+  C.sparse_partners = B.variant == 1 ? 0 : 1;
   if (K.any_scan) {
     w.Pt.ensure(sizeof(T) * size_t(K.pt_bstride) * nb);
     w.Qt.ensure(sizeof(T) * size_t(K.qt_bstride) * nb);
