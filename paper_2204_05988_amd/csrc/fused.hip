@@ -496,6 +496,10 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
     for (int o = 0; o < W; ++o) wi[o] = A.DX.twide[A.DX.wlev_off[lxc] + int64_t(o) * nxl + x];
     const bool has_q = src + 1 < G.n;
+    // Qt^m is computed only where it can be nonzero (face terms: near the
+    // x-faces); elsewhere it is exactly zero and stored as such, for the
+    // restriction of the next step reads every child
+    const uint64_t need = C.sparse_partners ? op.xqt_mask[A.DX.node_off[G.lx[lg] - A.DX.lmin] + x] : ~uint64_t(0);
     int32_t p0 = 0, p1 = 0;
     T w0 = 0, w1 = 0;
     int nvq = 0;
@@ -516,6 +520,11 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         for (int o = 0; o < W; ++o) un[q][o] = us[int64_t(wi[o]) * nv];
       }
       for (int m = g0; m < g1; ++m) {
+        if (m < 64 && !((need >> m) & 1)) {
+#pragma unroll
+          for (int q = 0; q < RS; ++q) Qtb[int64_t(m) * ltotal + L.off[lg] + pt * R + s0 + q] = T(0);
+          continue;
+        }
         const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + x;
         T rr[W];
 #pragma unroll
