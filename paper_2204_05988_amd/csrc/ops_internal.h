@@ -101,7 +101,7 @@ struct DomDev {
 
 struct OpDev {
   TermList host;
-  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm, xqtm, xptm;
+  DevBuf xf, vf, vg, xg, tm, tm32, vgf, xgf, vgt, vgs, xgt, xgs, xrowm, xreadm, xqtm, xptm, xgk;
   DevOp op;
   std::vector<int> hxgf, hxgs;                 // host copies of op.xg_fac, op.xg_start
   std::vector<uint64_t> hxrowm, hxreadm, hxqtm;  // host copies of the per-node group masks

@@ -359,7 +359,11 @@ static void upload_op(OpDev& od, const DomainData& X, const DomDev& dx) {
       if (xg[k] == int(m)) xgt.push_back(int(k));
   }
   xgs[xgf.size()] = int(xgt.size());
+  std::vector<int> xgk(xgt.size());  // X-group of the term at each position of the X-group order
+  for (size_t m = 0; m < xgf.size(); ++m)
+    for (int kk = xgs[m]; kk < xgs[m + 1]; ++kk) xgk[size_t(kk)] = int(m);
   DevOp& op = od.op;
+  op.xg_of = upload(od.xgk, xgk);
   op.vg_terms = upload(od.vgt, vgt);
   op.vg_start = upload(od.vgs, vgs);
   op.xg_terms = upload(od.xgt, xgt);

@@ -213,6 +213,7 @@ struct DevOp {
   const int* vg_start = nullptr;     // [nvg + 1]
   const int* xg_terms = nullptr;     // term indices ordered by X group
   const int* xg_start = nullptr;     // [nxg + 1]
+  const int* xg_of = nullptr;        // X-group of position kk of xg_terms
   // per x-node (the x-domain's node_off layout), bit m for X-group m < 64:
   // row of the group's factor has a nonzero / read by the x-stencil of such a row
   const uint64_t* xrow_mask = nullptr;

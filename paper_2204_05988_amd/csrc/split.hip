@@ -146,8 +146,11 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   // has a nonzero: a face term's W is needed on its face's x-nodes and their
   // stencil neighbours alone; elsewhere its terms are skipped and nothing is
   // stored (the x-stage skips the rows that would read it there)
-  const uint64_t need = read_needs(A.DX, op, lx, x);
-  auto needs = [&](int m) { return m >= 64 || ((need >> m) & 1); };
+  // (pipelined form only: with one vector per thread the branches cost more
+  // than the skipped terms save, measured; W is then staged everywhere)
+  constexpr bool kSkip = D <= 2 && BC > 1;
+  const uint64_t need = kSkip ? read_needs(A.DX, op, lx, x) : ~uint64_t(0);
+  auto needs = [&](int m) { return !kSkip || m >= 64 || ((need >> m) & 1); };
   T un[BC][R][SS];
 #pragma unroll
   for (int q = 0; q < BC; ++q) {
@@ -164,8 +167,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   // store 0).
   const int nt = op.xg_start[op.nxg];
   auto load = [&](int kk, T (&f)[SS], T (&pv)[BC][R][2]) {
-    const int k = op.xg_terms[kk];
-    if (!needs(op.term_xg[k])) {
+    if (!needs(op.xg_of[kk])) {
 #pragma unroll
       for (int e = 0; e < SS; ++e) f[e] = T(0);
 #pragma unroll
@@ -174,6 +176,7 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
         for (int s2 = 0; s2 < R; ++s2) pv[q][s2][0] = pv[q][s2][1] = T(0);
       return;
     }
+    const int k = op.xg_terms[kk];
     load_slot_pairs<T, SS>(qvals<T>(A.DV) + int64_t(op.term_vf[k]) * A.DV.qfac_stride + A.DV.qlev_off[lv - A.DV.lmin],
                            nv, v, f);
     const int j = op.term_vg[k];
@@ -498,11 +501,10 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
     for (int s = 0; s < R; ++s) acc[q][s] = T(0);
   // diagonal + lower partners: one x-stencil per X-group on the staged W.
   // A group whose factor row is zero here is skipped (its W^m is staged only
-  // around the rows with a nonzero); so are a partial group's zero slots.
+  // around the rows with a nonzero, which covers every slot of such a row).
   const uint64_t need = row_needs(A.DX, op, lx, x);
   for (int m = 0; m < op.nxg; ++m) {
     if (m < 64 && !((need >> m) & 1)) continue;
-    const bool part = A.DX.fpartial[op.xg_fac[m]] != 0;
     T xf[SS];
     load_slot_pairs<T, SS>(qvals<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.qfac_stride + A.DX.qlev_off[lx - A.DX.lmin],
                            nx, x, xf);
@@ -515,7 +517,6 @@ __global__ void __launch_bounds__(kSB) k_xstage(SplitCall<T> C) {
       for (int s = 0; s < R; ++s) t[s] = T(0);
 #pragma unroll
       for (int e = 0; e < SS; ++e) {
-        if (part && xf[e] == T(0)) continue;
         T zz[R];
         load_slices<T, R>(zb + int64_t(nbx[e]) * nv * R, zz);
 #pragma unroll
