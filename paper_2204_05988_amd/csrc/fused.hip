@@ -344,6 +344,23 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
 template <class T> __device__ __forceinline__ const T* rv(const DevDomain& D);
 template <> __device__ __forceinline__ const double* rv<double>(const DevDomain& D) { return D.trvals; }
 template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D) { return D.trvals32; }
+// slot-pair copies ([W/2][n][2] per level): slots 2p and 2p+1 of a coarse node
+// adjacent, the pair read with one 2-wide load
+template <class T> __device__ __forceinline__ const T* qrv(const DevDomain& D);
+template <> __device__ __forceinline__ const double* qrv<double>(const DevDomain& D) { return D.qrvals; }
+template <> __device__ __forceinline__ const float* qrv<float>(const DevDomain& D) { return D.qrvals32; }
+// FP64 reads the pairs (fewer load instructions); FP32 single slots measured faster
+template <class T> constexpr bool kScanPairs = sizeof(T) == 8;
+template <class T, int S>
+__device__ __forceinline__ void load_rpairs(const T* q, int64_t n, int64_t node, T (&f)[S]) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int p = 0; p < (S + 1) / 2; ++p) {
+    const T2 a = *reinterpret_cast<const T2*>(q + (int64_t(p) * n + node) * 2);
+    f[2 * p] = a.x;
+    if (2 * p + 1 < S) f[2 * p + 1] = a.y;
+  }
+}
 
 // One launch of the partner scans.  Mode 0 (a step): the restricted-stencil
 // part from u plus the recursion term, which acts on the previous step's array
@@ -468,10 +485,14 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       }
       for (int j = g0; j < g1; ++j) {
         if (j < 64 && !((need >> j) & 1)) continue;
-        const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + v;
         T rr[W];
+        if constexpr (kScanPairs<T>) {
+          load_rpairs<T, W>(qrv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.qrstride + A.DV.qrlev_off[lvc], nvl, v, rr);
+        } else {
+          const T* r = rv<T>(A.DV) + int64_t(op.vg_fac[j]) * A.DV.rstride + A.DV.wlev_off[lvc] + v;
 #pragma unroll
-        for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nvl];
+          for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nvl];
+        }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
           const int s = s0 + q;
@@ -525,10 +546,14 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
           for (int q = 0; q < RS; ++q) Qtb[int64_t(m) * ltotal + L.off[lg] + pt * R + s0 + q] = T(0);
           continue;
         }
-        const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + x;
         T rr[W];
+        if constexpr (kScanPairs<T>) {
+          load_rpairs<T, W>(qrv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.qrstride + A.DX.qrlev_off[lxc], nxl, x, rr);
+        } else {
+          const T* r = rv<T>(A.DX) + int64_t(op.xg_fac[m]) * A.DX.rstride + A.DX.wlev_off[lxc] + x;
 #pragma unroll
-        for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nxl];
+          for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nxl];
+        }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
           const int s = s0 + q;

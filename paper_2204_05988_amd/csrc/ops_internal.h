@@ -94,7 +94,7 @@ struct sgdg_grid_s {
 
 struct DomDev {
   DevBuf nbr, tnbr, par, parw, chi, chiw, tchi, tchiw, vals, vals32, tvals, tvals32, wide, rvals, rvals32, twide,
-      trvals, trvals32, pidx, pvals, pvals32, qvals, qvals32, qpvals, qpvals32, sup, fpartial;
+      trvals, trvals32, pidx, pvals, pvals32, qvals, qvals32, qpvals, qpvals32, qrvals, qrvals32, sup, fpartial;
   DevDomain d;
   std::vector<uint8_t> hsup, hpartial;  // host copies of d.sup, d.fpartial
 };

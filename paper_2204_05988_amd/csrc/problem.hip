@@ -318,6 +318,11 @@ static void upload_domain(DomainData& D, DomDev& dd) {
     pair_major(pv, nf, pof, PW, d.plev_off, d.qplev_off, d.qpstride, pq, pq32);
     d.qpvals = upload(dd.qpvals, pq);
     d.qpvals32 = upload(dd.qpvals32, pq32);
+    std::vector<double> rq;
+    std::vector<float> rq32;
+    pair_major(trv, nf, wo, W, d.wlev_off, d.qrlev_off, d.qrstride, rq, rq32);
+    d.qrvals = upload(dd.qrvals, rq);
+    d.qrvals32 = upload(dd.qrvals32, rq32);
   }
 }
 

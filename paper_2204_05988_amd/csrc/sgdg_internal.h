@@ -182,6 +182,10 @@ struct DevDomain {
   const double* qpvals = nullptr;     // [factor][levels [PW/2][n][2]]
   const float* qpvals32 = nullptr;
   int64_t qpstride = 0;               // elements per factor
+  int64_t qrlev_off[kMaxLevels] = {}; // start of level l in the pair restricted tables
+  const double* qrvals = nullptr;     // [factor][levels [W/2][n][2]] (slot pairs of trvals)
+  const float* qrvals32 = nullptr;
+  int64_t qrstride = 0;               // elements per factor
   // support of each factor matrix per node: bit 0 its row has a nonzero,
   // bit 1 it is the column of a nonzero, bit 2 it is a stencil neighbour of a
   // row with a nonzero; a factor is partial when some node lacks bit 0 or 1

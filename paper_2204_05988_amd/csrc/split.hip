@@ -146,9 +146,9 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
   // has a nonzero: a face term's W is needed on its face's x-nodes and their
   // stencil neighbours alone; elsewhere its terms are skipped and nothing is
   // stored (the x-stage skips the rows that would read it there)
-  // (pipelined form only: with one vector per thread the branches cost more
-  // than the skipped terms save, measured; W is then staged everywhere)
-  constexpr bool kSkip = D <= 2 && BC > 1;
+  // (not for d <= 2 with one vector per thread: there the branches cost more
+  // than the skipped terms save, measured, and W is staged everywhere)
+  constexpr bool kSkip = D == 3 || BC > 1;
   const uint64_t need = kSkip ? read_needs(A.DX, op, lx, x) : ~uint64_t(0);
   auto needs = [&](int m) { return !kSkip || m >= 64 || ((need >> m) & 1); };
   T un[BC][R][SS];
