@@ -154,7 +154,7 @@ def roofline(fl, by, ms, valu_peak):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU execution is not implemented",
+        print(json.dumps({"error": "the benchmark runs on one GPU; execution across several GPUs is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
