@@ -12,7 +12,9 @@ Prints one JSON line (rank 0).  Also reports, beside the headline number:
   * learned: the 4D Vlasov-type step (x periodic, frozen random E(x), L=7,
     r=0): (r, P_CT r) pairs recorded from CT-preconditioned solves of strips
     1-8, the per-grid networks trained on them, then strips 9-10 solved to 1e-8
-    with CT, with the learned preconditioner, and learned + mixed precision;
+    with CT, with the learned preconditioner, and learned + mixed precision,
+    and again with inexact CT grid solves (10 GMRES iterations) as CT and as
+    the learned preconditioner's fallback, in FP64 and in mixed precision;
     its "network" entry is the forward rate of the trained network against
     the HBM roofline, with its matrix-core utilisation (--network-only: that
     rate alone, freshly initialised);
@@ -348,6 +350,8 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
     ct_inexact = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(inner_maxit=10))
     learned_inexact = sgdg.default_solve_opts(rtol=1e-8, maxit=400,
                                               pc=sgdg.default_precond_opts(net=net, inner_maxit=10))
+    learned_inexact_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                                    pc=sgdg.default_precond_opts(net=net, inner_maxit=10))
     for j in range(record_strips + 1, record_strips + test_strips + 1):
         b = ops.rhs(u, prev)
         row = {"strip": j}
@@ -356,10 +360,11 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
         _, row["learned_mixed"] = _timed_solve(ops, b, learned_mixed)
         _, row["ct_inexact_fp64"] = _timed_solve(ops, b, ct_inexact)
         _, row["learned_inexact_fallback_fp64"] = _timed_solve(ops, b, learned_inexact)
+        _, row["learned_inexact_fallback_mixed"] = _timed_solve(ops, b, learned_inexact_mixed)
         t0 = row["ct_fp64"]["seconds"]
         row["gain_vs_ct_fp64"] = {k: round(t0 / row[k]["seconds"], 3)
                                   for k in ("learned_fp64", "learned_mixed", "ct_inexact_fp64",
-                                            "learned_inexact_fallback_fp64")}
+                                            "learned_inexact_fallback_fp64", "learned_inexact_fallback_mixed")}
         out["strips"].append(row)
         _log(f"learned leg: {row}")
         u = x
