@@ -349,6 +349,19 @@ template <> __device__ __forceinline__ const float* rv<float>(const DevDomain& D
 template <class T> __device__ __forceinline__ const T* qrv(const DevDomain& D);
 template <> __device__ __forceinline__ const double* qrv<double>(const DevDomain& D) { return D.qrvals; }
 template <> __device__ __forceinline__ const float* qrv<float>(const DevDomain& D) { return D.qrvals32; }
+// the R slices of one node, adjacent in memory: 2-wide loads
+template <class T, int R>
+__device__ __forceinline__ void load_slices_f(const T* p, T (&v)[R]) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  int s = 0;
+#pragma unroll
+  for (; s + 2 <= R; s += 2) {
+    const T2 a = *reinterpret_cast<const T2*>(p + s);
+    v[s] = a.x;
+    v[s + 1] = a.y;
+  }
+  if (s < R) v[s] = p[s];
+}
 // FP64 reads the pairs (fewer load instructions); FP32 single slots measured faster
 template <class T> constexpr bool kScanPairs = sizeof(T) == 8;
 template <class T, int S>
@@ -411,14 +424,20 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
       }
       for (int j = g0; j < g1; ++j) {
         if (j < 64 && !((need >> j) & 1)) continue;
+        // the R slices of a child with one 2-wide load
+        const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(xc) * nvs * R;
+        T acc[R];
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const T* row = Ptb + int64_t(j) * ltotal + L.off[lg - 1] + int64_t(xc) * nvs * R + s;
-          T acc = T(0);
+        for (int s = 0; s < R; ++s) acc[s] = T(0);
 #pragma unroll
-          for (int c = 0; c < SS; ++c) acc += cw[c] * row[int64_t(ch[c]) * R];
-          Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + e * R + s] = acc;
+        for (int c = 0; c < SS; ++c) {
+          T a[R];
+          load_slices_f<T, R>(row + int64_t(ch[c]) * R, a);
+#pragma unroll
+          for (int s = 0; s < R; ++s) acc[s] += cw[c] * a[s];
         }
+#pragma unroll
+        for (int s = 0; s < R; ++s) Rvb[int64_t(j) * A.rv_len + A.rvo[lg] + e * R + s] = acc[s];
       }
     } else {
       // Rx_l[xc][vq] = sum_c chiw_c(xc) Qt_{l+1}[chi_c(xc)][vq], xc on the target's x-level
@@ -436,15 +455,21 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
         ch[c] = A.DX.tchi[co + int64_t(c) * nxt];
         cw[c] = T(A.DX.tchiw[co + int64_t(c) * nxt]);
       }
-      for (int m = g0; m < g1; ++m)
+      for (int m = g0; m < g1; ++m) {
+        const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(vq) * R;
+        T acc[R];
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const T* col = Qtb + int64_t(m) * ltotal + L.off[lg + 1] + int64_t(vq) * R + s;
-          T acc = T(0);
+        for (int s = 0; s < R; ++s) acc[s] = T(0);
 #pragma unroll
-          for (int c = 0; c < SS; ++c) acc += cw[c] * col[int64_t(ch[c]) * nvs * R];
-          Rxb[int64_t(m) * A.rx_len + A.rxo[lg] + e * R + s] = acc;
+        for (int c = 0; c < SS; ++c) {
+          T a[R];
+          load_slices_f<T, R>(col + int64_t(ch[c]) * nvs * R, a);
+#pragma unroll
+          for (int s = 0; s < R; ++s) acc[s] += cw[c] * a[s];
         }
+#pragma unroll
+        for (int s = 0; s < R; ++s) Rxb[int64_t(m) * A.rx_len + A.rxo[lg] + e * R + s] = acc[s];
+      }
     }
     return;
   }
