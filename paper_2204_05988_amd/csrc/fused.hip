@@ -518,16 +518,20 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nvl];
         }
+        // the two x-parents' restricted values, all RS slices per 2-wide load
+        T ra[RS], rb[RS];
+        if (has_p) {
+          const T* rvp = Rvb + int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(v) * R + s0;
+          load_slices_f<T, RS>(rvp + int64_t(p0) * nvl * R, ra);
+          load_slices_f<T, RS>(rvp + int64_t(p1) * nvl * R, rb);
+        }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
           const int s = s0 + q;
           T acc = T(0);
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
-          if (has_p) {
-            const T* rvp = Rvb + int64_t(j) * A.rv_len + A.rvo[lg] + int64_t(v) * R + s;
-            acc += w0 * rvp[int64_t(p0) * nvl * R] + w1 * rvp[int64_t(p1) * nvl * R];
-          }
+          if (has_p) acc += w0 * ra[q] + w1 * rb[q];
           Ptb[int64_t(j) * ltotal + L.off[lg] + pt * R + s] = acc;
         }
       }
@@ -579,16 +583,20 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
 #pragma unroll
           for (int o = 0; o < W; ++o) rr[o] = r[int64_t(o) * nxl];
         }
+        // the two v-parents' restricted values, all RS slices per 2-wide load
+        T ra[RS], rb[RS];
+        if (has_q) {
+          const T* rxp = Rxb + int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(x) * nvq * R + s0;
+          load_slices_f<T, RS>(rxp + int64_t(p0) * R, ra);
+          load_slices_f<T, RS>(rxp + int64_t(p1) * R, rb);
+        }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
           const int s = s0 + q;
           T acc = T(0);
 #pragma unroll
           for (int o = 0; o < W; ++o) acc += rr[o] * un[q][o];
-          if (has_q) {
-            const T* rxp = Rxb + int64_t(m) * A.rx_len + A.rxo[lg] + int64_t(x) * nvq * R + s;
-            acc += w0 * rxp[int64_t(p0) * R] + w1 * rxp[int64_t(p1) * R];
-          }
+          if (has_q) acc += w0 * ra[q] + w1 * rb[q];
           Qtb[int64_t(m) * ltotal + L.off[lg] + pt * R + s] = acc;
         }
       }
