@@ -167,20 +167,25 @@ typedef struct {
   double inner_rtol;    /* relative residual of each grid problem (eq:Adeltall) */
   int inner_maxit;      /* iteration cap per grid problem */
   int inner_restart;    /* GMRES restart length of the grid problems */
-  int mass_sweeps;      /* reserved, must be 0 (Jacobi mass inverse) */
+  int mass_sweeps;      /* mass inverses of the grid-problem preconditioner (Sect. 4.3): 0 = diagonals of
+                           M^x and M^v; k = 1..64: k Chebyshev-Jacobi steps per mass factor (a fixed
+                           polynomial in D^-1 M, eigenvalues in [1/2, 1 + d/2]); -1 (d = 1 only): exact
+                           tridiagonal solves per grid line */
   sgdg_net net;         /* kind 1: the trained network of this problem */
   int fallback_iters;   /* kind 1: if over any fallback_iters consecutive FGMRES iterations (default 10) ... */
   double fallback_drop; /* ... the residual estimate drops by less than this factor (default 10), the
                            remaining iterations use kind 0 */
 } sgdg_precond_opts;
 
-/* z_dev = P_CT r_dev (one vector, batch must be 1 in this version).
+/* z_dev = P_CT r_dev for `batch` independent vectors ([batch][n_dof], 1..4096).
  * Restricts the residual to the lower diagonal, solves every grid problem
  * A_{l,l} dU_l = r_l by GMRES right-preconditioned with the inverse of
- * (Tt + delta Ct + Gt) (x) M^x (x) M^v (Sect. 4.3), and combines.  t = F64 runs
- * everything in FP64, t = F32 converts r to FP32 and runs the grid problems in
- * FP32 (z returned in the dtype t).  Grid problems that reach inner_maxit are
- * left at their best iterate (not an error). */
+ * (Tt + delta Ct + Gt) (x) M^x (x) M^v (Sect. 4.3; see mass_sweeps), and
+ * combines.  The grid problems of all vectors iterate in the same launches.
+ * r_dev and z_dev hold batch * n_dof elements of the dtype t: F64 runs
+ * everything in FP64, F32 runs the grid problems in FP32.  Grid problems
+ * that reach inner_maxit are left at their best iterate (not an error);
+ * SGDG_E_NAN if a grid problem's residual is not finite. */
 sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_dev, sgdg_dtype t, int batch,
                               const sgdg_precond_opts* po, hipStream_t s);
 
@@ -387,6 +392,33 @@ sgdg_status sgdg_op_info(sgdg_ops o, int kind, int* nterms, int* nvg, int* nxg, 
  * of those pairs }.  Groups beyond the 64th count everywhere.  SGDG_E_ARG for
  * a null handle or array, an unknown kind or a level outside the hierarchy. */
 sgdg_status sgdg_op_support(sgdg_ops o, int kind, int lx, int64_t* counts);
+
+/* Diagnostic: the grid-problem preconditioner alone, out = (Tt + delta Ct +
+ * Gt)^-1 (x) M^x^-1 (x) M^v^-1 in (mass inverses as selected by `sweeps`, see
+ * mass_sweeps) on the grid-problem layout: every upper grid, then every
+ * lower grid, each an [R][n_x][n_v] block; in_dev and out_dev hold that many
+ * elements of dtype t and must not overlap.  Queued on s. */
+sgdg_status sgdg_debug_grid_precond(sgdg_ops o, int sweeps, const void* in_dev, void* out_dev, sgdg_dtype t,
+                                    hipStream_t s);
+
+/* Number of captured grid-problem GMRES graphs that the next graph solve of
+ * o's own batch can replay.  A graph holds the device addresses it was
+ * captured with, so every (re)allocation of a work buffer or table (a larger
+ * batch, a tuning run, a rebuilt table) empties the cache on the next graph
+ * solve; this returns 0 once such a change has happened.  SGDG_E_ARG on a null
+ * argument. */
+sgdg_status sgdg_graph_cache_size(sgdg_ops o, int* count);
+
+/* Host-only: the learned preconditioner's fallback rule applied to a recorded
+ * sequence of n FGMRES iterations.  call[i] numbers the FGMRES call of
+ * iteration i (mixed precision runs one call per refinement step; the history
+ * restarts with each call), rel0[i] is that call's relative residual at entry
+ * and est[i] the residual estimate after the iteration, both relative to the
+ * call's right-hand side.  *switch_at = index of the iteration after which the
+ * solve switches to the combination technique (no drop by `drop` over `iters`
+ * consecutive iterations of one call), or -1.  Touches no device. */
+sgdg_status sgdg_debug_fallback(int iters, double drop, int n, const int* call, const double* rel0,
+                                const double* est, int* switch_at);
 
 /* Host-only: dense block (row_grid, col_grid) of the operator `kind` (FULL,
  * MASS, DATA_F or DATA_G; not BLOCKDIAG) assembled from the host factor

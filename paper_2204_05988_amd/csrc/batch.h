@@ -137,6 +137,11 @@ struct SegInfo {
   const double* mvd;    // v mass factor rows of level lv ([nv][Sv])
   int Sx, Sv;
   double pinv[kMaxR * kMaxR];
+  // exact or polynomial mass inverses of the grid-problem preconditioner
+  const int32_t* xnbr;  // x stencil neighbours of level lx ([nx][Sx], self outside the box)
+  const int32_t* vnbr;  // v stencil neighbours of level lv ([nv][Sv])
+  int xper, vper;       // periodic domains
+  int sm, sp;           // d = 1: stencil slots of the offsets -1 and +1
 };
 
 struct BlockRef {  // one block of a segmented launch

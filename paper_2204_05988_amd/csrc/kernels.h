@@ -27,6 +27,20 @@ struct KernelsT {
   static void ct_gather(const SegTable& S, const T* r, T* b, hipStream_t s);
   static void ct_combine(const SegTable& S, const T* ct, T* z, hipStream_t s);
   static void minv(const SegTable& S, const T* x, T* y, hipStream_t s);
+  // y = (Tt + delta Ct + Gt)^-1 x per point (time blocks only, no mass factor)
+  static void tinv(const SegTable& S, const T* x, T* y, hipStream_t s);
+  // one Chebyshev step of the Jacobi-preconditioned mass solve M_axis z = b
+  // along axis 0 (x) or 1 (v) of every segment (see mass_cheb_coefs):
+  //   d_out = cd * d + cr * D^-1 (b - M x),  x_out = x + d_out
+  // first = 1: x = d = 0 (not read).  tinv = 1: x_out is mapped by the time
+  // blocks (Tt + delta Ct + Gt)^-1 before it is stored.
+  static void mass_cheb(const SegTable& S, int axis, double cd, double cr, int first, int tinv, const T* b,
+                        const T* x, const T* d, T* x_out, T* d_out, hipStream_t s);
+  // exact tridiagonal (d = 1) mass solve along axis 0 or 1 of every segment,
+  // one thread per grid line (Thomas; cyclic lines by Sherman-Morrison).
+  // y may equal b; cbuf, zbuf: scratch of the segment layout's size.
+  static void mass_thomas(const SegTable& S, int axis, int max_lines, const T* b, T* y, T* cbuf, T* zbuf,
+                          hipStream_t s);
   static void axpby(int64_t n, T a, const T* x, T b, T* y, hipStream_t s);
   static void copy(int64_t n, const T* x, T* y, hipStream_t s);
   static void fill(int64_t n, T v, T* y, hipStream_t s);

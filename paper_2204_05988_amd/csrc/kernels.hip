@@ -8,9 +8,10 @@
 //    estimates, convergence and breakdown flags, back substitution).
 //  * The transfers of the combination technique (Algorithm 1): restriction of
 //    the residual in x to the lower diagonal, the combination step, and the
-//    preconditioner of the grid problems, the inverse of
-//    (Tt + delta Ct + Gt) (x) M^x (x) M^v with the mass matrices replaced by
-//    their diagonals.
+//    preconditioner of the grid problems (Sect. 4.3), the inverse of
+//    (Tt + delta Ct + Gt) (x) M^x (x) M^v: the mass matrices replaced by their
+//    diagonals, inverted by fixed-degree Chebyshev-Jacobi steps along each
+//    axis, or (d = 1) inverted exactly by a tridiagonal solve per grid line.
 //  * Right-hand-side helpers of one strip.
 #include <hip/hip_runtime.h>
 
@@ -368,6 +369,180 @@ __global__ void __launch_bounds__(kBlock) k_minv(const SegInfo* __restrict__ seg
   }
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_tinv(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                 const T* __restrict__ x, T* __restrict__ y) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t p = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (p >= plane) return;
+    T in[kMaxR];
+    for (int s = 0; s < S.R; ++s) in[s] = x[S.off + s * plane + p];
+    for (int s = 0; s < S.R; ++s) {
+      T a = 0;
+      for (int s2 = 0; s2 < S.R; ++s2) a += T(S.pinv[s * S.R + s2]) * in[s2];
+      y[S.off + s * plane + p] = a;
+    }
+  }
+}
+
+// One step of the Chebyshev semi-iteration for M z = b with the Jacobi
+// splitting D = diag(M), along one axis of a segment's [R][nx][nv] block (the
+// mass matrix of that axis acts on every line of the other axis and every
+// slice).  The diagonal is the true one: the sum of the stencil slots that
+// land on the row's own node (periodic lattices of 1 or 2 nodes wrap onto it).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mass_cheb(const SegInfo* __restrict__ segs,
+                                                      const BlockRef* __restrict__ blk, int axis, double cd,
+                                                      double cr, int first, int tinv, const T* __restrict__ b,
+                                                      const T* __restrict__ x, const T* __restrict__ d,
+                                                      T* __restrict__ x_out, T* __restrict__ d_out) {
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  const int Sn = axis == 0 ? S.Sx : S.Sv;
+  const double* rows = axis == 0 ? S.mxd : S.mvd;
+  const int32_t* nbr = axis == 0 ? S.xnbr : S.vnbr;
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t p = int64_t(br.chunk) * kChunk + int64_t(t) * kBlock + threadIdx.x;
+    if (p >= plane) return;
+    const int xi = int(p / S.nv), vi = int(p - int64_t(xi) * S.nv);
+    const int row = axis == 0 ? xi : vi;
+    double diag = 0;
+    for (int e = 0; e < Sn; ++e)
+      if (nbr[int64_t(row) * Sn + e] == row) diag += rows[int64_t(row) * Sn + e];
+    const double rdiag = 1.0 / diag;
+    T xn[kMaxR];
+    for (int s = 0; s < S.R; ++s) {
+      const int64_t base = S.off + s * plane;
+      const int64_t i = base + p;
+      double res = double(b[i]);
+      double dn;
+      if (first) {
+        dn = cr * rdiag * res;
+        xn[s] = T(dn);
+      } else {
+        for (int e = 0; e < Sn; ++e) {
+          const int64_t c = nbr[int64_t(row) * Sn + e];
+          const int64_t q = axis == 0 ? c * S.nv + vi : int64_t(xi) * S.nv + c;
+          res -= rows[int64_t(row) * Sn + e] * double(x[base + q]);
+        }
+        dn = cd * double(d[i]) + cr * rdiag * res;
+        xn[s] = T(double(x[i]) + dn);
+      }
+      if (d_out) d_out[i] = T(dn);
+    }
+    for (int s = 0; s < S.R; ++s) {
+      T a = xn[s];
+      if (tinv) {
+        a = 0;
+        for (int s2 = 0; s2 < S.R; ++s2) a += T(S.pinv[s * S.R + s2]) * xn[s2];
+      }
+      x_out[S.off + s * plane + p] = a;
+    }
+  }
+}
+
+// Exact solve of the 1D mass matrix along one axis, one thread per line of a
+// segment.  A line of n nodes carries the tridiagonal rows (lo_i, di_i, up_i)
+// of the stencil (offsets -1, 0, +1).  A periodic line of n >= 3 nodes is
+// cyclic: its corner entries are split off as a rank-one term u v^T and the
+// Sherman-Morrison formula combines two tridiagonal solves (right-hand side
+// and u); a periodic line of 2 nodes couples both slots to the other node, one
+// of 1 node to itself.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mass_thomas(const SegInfo* __restrict__ segs, int axis,
+                                                        const T* __restrict__ b, T* __restrict__ y,
+                                                        T* __restrict__ cbuf, T* __restrict__ zbuf) {
+  const SegInfo& S = segs[blockIdx.y];
+  const int64_t line = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int n = axis == 0 ? S.nx : S.nv;
+  const int other = axis == 0 ? S.nv : S.nx;
+  if (line >= int64_t(S.R) * other) return;
+  const int s = int(line / other), k = int(line - int64_t(s) * other);
+  const int64_t plane = int64_t(S.nx) * S.nv;
+  const int64_t base = S.off + s * plane + (axis == 0 ? k : int64_t(k) * S.nv);
+  const int64_t stride = axis == 0 ? S.nv : 1;
+  const int Sn = axis == 0 ? S.Sx : S.Sv;
+  const double* rows = axis == 0 ? S.mxd : S.mvd;
+  const int32_t* nbr = axis == 0 ? S.xnbr : S.vnbr;
+  const bool per = (axis == 0 ? S.xper : S.vper) != 0;
+  auto coef = [&](int i, double& lo, double& di, double& up) {
+    lo = di = up = 0;
+    for (int e = 0; e < Sn; ++e) {
+      const int c = nbr[int64_t(i) * Sn + e];
+      const double v = rows[int64_t(i) * Sn + e];
+      if (c == i) di += v;
+      else if (e == S.sm) lo += v;
+      else if (e == S.sp) up += v;
+    }
+  };
+  if (n == 1 || (per && n == 2)) {  // every slot lands on the line's own nodes: a dense 1x1 or 2x2 solve
+    double l0, d0, u0;
+    coef(0, l0, d0, u0);
+    if (n == 1) {
+      y[base] = T(double(b[base]) / d0);
+      return;
+    }
+    double l1, d1, u1;
+    coef(1, l1, d1, u1);
+    const double a01 = l0 + u0, a10 = l1 + u1, det = d0 * d1 - a01 * a10;
+    const double b0 = double(b[base]), b1 = double(b[base + stride]);
+    y[base] = T((d1 * b0 - a01 * b1) / det);
+    y[base + stride] = T((d0 * b1 - a10 * b0) / det);
+    return;
+  }
+  // A = T' + u v^T with u = (g, 0.., 0, alpha), v = (1, 0.., 0, beta / g) for a cyclic line
+  double lo0, di0, up0;
+  coef(0, lo0, di0, up0);
+  double loN, diN, upN;
+  coef(n - 1, loN, diN, upN);
+  const double beta = per ? lo0 : 0.0;   // row 0, column n-1
+  const double alpha = per ? upN : 0.0;  // row n-1, column 0
+  const double g = -di0;
+  // forward elimination of T' y = b and T' z = u (c' kept in cbuf, z's in zbuf)
+  double cprev = 0, dprev = 0, zprev = 0;
+  for (int i = 0; i < n; ++i) {
+    double lo, di, up;
+    coef(i, lo, di, up);
+    if (i == 0) lo = 0;
+    if (i == n - 1) up = 0;
+    if (per && i == 0) di -= g;
+    if (per && i == n - 1) di -= alpha * beta / g;
+    const double den = di - lo * cprev;
+    const double c = up / den;
+    const double dd = (double(b[base + i * stride]) - lo * dprev) / den;
+    const double ui = per ? (i == 0 ? g : (i == n - 1 ? alpha : 0.0)) : 0.0;
+    const double zz = (ui - lo * zprev) / den;
+    cbuf[base + i * stride] = T(c);
+    y[base + i * stride] = T(dd);
+    if (per) zbuf[base + i * stride] = T(zz);
+    cprev = c;
+    dprev = dd;
+    zprev = zz;
+  }
+  // back substitution
+  double ynext = 0, znext = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    const double c = double(cbuf[base + i * stride]);
+    const double yi = double(y[base + i * stride]) - c * ynext;
+    y[base + i * stride] = T(yi);
+    ynext = yi;
+    if (per) {
+      const double zi = double(zbuf[base + i * stride]) - c * znext;
+      zbuf[base + i * stride] = T(zi);
+      znext = zi;
+    }
+  }
+  if (!per) return;
+  const double y0 = double(y[base]), yN = double(y[base + (n - 1) * stride]);
+  const double z0 = double(zbuf[base]), zN = double(zbuf[base + (n - 1) * stride]);
+  const double f = (y0 + beta / g * yN) / (1.0 + z0 + beta / g * zN);
+  for (int i = 0; i < n; ++i) y[base + i * stride] = T(double(y[base + i * stride]) - f * double(zbuf[base + i * stride]));
+}
+
 // ------------------------------------------------------------- data / rhs --
 __global__ void k_project(int64_t n, int nq, int R, const double* __restrict__ wts, const double* __restrict__ samples,
                           double* __restrict__ out) {
@@ -454,6 +629,28 @@ template <class T>
 void KernelsT<T>::minv(const SegTable& S, const T* x, T* y, hipStream_t s) {
   if (S.nblk == 0) return;
   hipLaunchKernelGGL(k_minv<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, x, y);
+  LAUNCH_CHECK();
+}
+template <class T>
+void KernelsT<T>::tinv(const SegTable& S, const T* x, T* y, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_tinv<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, x, y);
+  LAUNCH_CHECK();
+}
+template <class T>
+void KernelsT<T>::mass_cheb(const SegTable& S, int axis, double cd, double cr, int first, int tinv, const T* b,
+                            const T* x, const T* d, T* x_out, T* d_out, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_mass_cheb<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, axis, cd, cr, first, tinv, b,
+                     x, d, x_out, d_out);
+  LAUNCH_CHECK();
+}
+template <class T>
+void KernelsT<T>::mass_thomas(const SegTable& S, int axis, int max_lines, const T* b, T* y, T* cbuf, T* zbuf,
+                              hipStream_t s) {
+  if (S.nseg == 0 || max_lines <= 0) return;
+  hipLaunchKernelGGL(k_mass_thomas<T>, dim3(unsigned((max_lines + kBlock - 1) / kBlock), unsigned(S.nseg)),
+                     dim3(kBlock), 0, s, S.segs, axis, b, y, cbuf, zbuf);
   LAUNCH_CHECK();
 }
 template <class T>

@@ -123,6 +123,9 @@ struct sgdg_ops_s {
   double pinv[kMaxR * kMaxR] = {};  // (Tt + delta Ct + Gt)^-1
   int device = 0;
   std::unique_ptr<Batch, BatchDeleter> self;  // this problem as a batch of one
+  // this problem replicated n times (n independent vectors in one lockstep
+  // preconditioner application), keyed by n
+  std::map<int, std::unique_ptr<Batch, BatchDeleter>> replicas;
   sgdg_net recorder = nullptr;                 // network recording (r, P_CT r) pairs of this problem
   std::vector<sgdg_net> nets;                  // networks created for this problem
 };
@@ -135,3 +138,5 @@ void net_detach(sgdg_net n);  // the problem is being destroyed
 
 // the problem as a batch of one (created on first use)
 Batch& self_batch(sgdg_ops o);
+// the problem replicated n times (created on first use, kept with the handle)
+Batch& replica_batch(sgdg_ops o, int n);

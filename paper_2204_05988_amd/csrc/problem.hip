@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,10 +22,17 @@ namespace sgdg {
 static thread_local std::string g_err = "no error";
 void set_error(const std::string& m) { g_err = m; }
 
+static std::atomic<uint64_t> g_alloc_epoch{0};
+uint64_t alloc_epoch() { return g_alloc_epoch.load(); }
+
 DevBuf::~DevBuf() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    (void)hipFree(p);
+    ++g_alloc_epoch;
+  }
 }
 void DevBuf::alloc(size_t b) {
+  ++g_alloc_epoch;
   if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;

@@ -228,6 +228,11 @@ struct DevOp {
   const uint64_t* xpt_mask = nullptr;
 };
 
+// Number of device allocations and frees made through DevBuf so far.  A
+// captured hipGraph bakes in device addresses; it stays valid only while
+// this count is unchanged since its capture.
+uint64_t alloc_epoch();
+
 // Device buffer helper.
 struct DevBuf {
   void* p = nullptr;

@@ -8,6 +8,7 @@
 #include <fstream>
 #include <limits>
 #include <sstream>
+#include <type_traits>
 
 #include "ops_internal.h"
 #include "split.h"
@@ -52,6 +53,7 @@ struct KindData {
 template <class T>
 struct BWork {
   DevBuf Pt, Qt, Rv, Rx, Z, ctb, ctx, ctw, cttmp, ctV, cvt_in, cvt_out;
+  DevBuf mU, mX0, mX1, mD0, mD1;  // mass-inverse stages of the grid-problem preconditioner
 };
 
 }  // namespace
@@ -77,9 +79,15 @@ struct sgdg_batch_s {
   int split_bc = 0;  // vectors per thread of the split passes (0: default for d)
   int split_xcd = 0;  // 1: XCD-contiguous block order in the split passes
   int scan_chunks = 1;  // blocks sharing the factor groups of a scan item
-  // graphs of grid-problem GMRES cycles
+  // graphs of grid-problem GMRES cycles, valid while alloc_epoch() equals
+  // graph_epoch (a reallocated work buffer or rebuilt table empties the cache)
   std::map<std::string, hipGraphExec_t> graphs;
+  uint64_t graph_epoch = 0;
   hipStream_t cap_stream = nullptr;
+  void clear_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
   // event timing: slot 0 level scans, 1 fused tiles, 2 grid-problem cycles,
   // 3/4/5 split v-stage, upper-partner and x-stage passes
   static constexpr int kSlots = 6;
@@ -96,7 +104,7 @@ struct sgdg_batch_s {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
     }
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    clear_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
@@ -118,6 +126,23 @@ Batch& self_batch(sgdg_ops o) {
     o->self.reset(b);
   }
   return *o->self;
+}
+
+Batch& replica_batch(sgdg_ops o, int n) {
+  if (n == 1) return self_batch(o);
+  auto it = o->replicas.find(n);
+  if (it != o->replicas.end()) return *it->second;
+  const Batch& S = self_batch(o);
+  Batch* b = new Batch;
+  b->P.assign(size_t(n), o);
+  b->d = S.d;
+  b->R = S.R;
+  b->variant = S.variant;
+  b->split_bc = S.split_bc;
+  b->split_xcd = S.split_xcd;
+  b->scan_chunks = S.scan_chunks;
+  o->replicas[n].reset(b);
+  return *b;
 }
 
 template <class T>
@@ -601,6 +626,16 @@ static void fill_domain_ptrs(sgdg_ops o, SegInfo& S) {
   S.xpar = X.par + X.par_off[S.lx - X.lmin];
   S.xparw = X.parw + X.par_off[S.lx - X.lmin];
   for (int i = 0; i < kMaxR * kMaxR; ++i) S.pinv[i] = o->pinv[i];
+  S.xnbr = X.nbr + X.lev_off[S.lx - X.lmin];
+  S.vnbr = V.nbr + V.lev_off[S.lv - V.lmin];
+  S.xper = o->grid->x.periodic ? 1 : 0;
+  S.vper = o->grid->v.periodic ? 1 : 0;
+  S.sm = S.sp = -1;
+  if (o->X.dom.d == 1) {
+    const int om[3] = {-1, 0, 0}, op[3] = {1, 0, 0};
+    S.sm = o->X.st.slot(om);
+    S.sp = o->X.st.slot(op);
+  }
 }
 
 // grid problems of the combination technique: upper then lower grids of each problem
@@ -804,9 +839,17 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
     const int mm = std::min(m, maxit - it);
     int j = 0;
     if (use_graph && mm == m) {
+      // a graph replays the device addresses it was captured with: any
+      // buffer or table reallocated since then invalidates every graph
+      if (B.graph_epoch != alloc_epoch()) {
+        SGDG_CHECK_HIP(hipStreamSynchronize(s));
+        B.clear_graphs();
+        B.graph_epoch = alloc_epoch();
+      }
       std::ostringstream key;
       key << sizeof(T) << '/' << m << '/' << total << '/' << (const void*)V << '/' << (const void*)w << '/'
-          << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b;
+          << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b
+          << '/' << B.variant << '/' << B.split_bc << '/' << B.split_xcd;
       auto g = B.graphs.find(key.str());
       if (g == B.graphs.end()) {
         // One eager application of M and A first: workspaces and item tables
@@ -815,6 +858,10 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
         M(V, tmp, s);
         A(tmp, w, s);
         SGDG_CHECK_HIP(hipStreamSynchronize(s));
+        if (B.graph_epoch != alloc_epoch()) {  // the warm-up allocated: older graphs may be stale
+          B.clear_graphs();
+          B.graph_epoch = alloc_epoch();
+        }
         // capture on a private stream (the caller's may be the null stream, which cannot be captured)
         if (!B.cap_stream) SGDG_CHECK_HIP(hipStreamCreate(&B.cap_stream));
         const bool prof = B.prof;
@@ -836,6 +883,8 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
         (void)hipGraphDestroy(graph);
         SGDG_CHECK_HIP(e);
         g = B.graphs.emplace(key.str(), exec).first;
+        // instantiation allocates no DevBuf: the epoch still matches the capture
+        require(B.graph_epoch == alloc_epoch(), "work buffers changed during graph capture");
       }
       timed(B, 2, s, [&] { SGDG_CHECK_HIP(hipGraphLaunch(g->second, s)); });
       j = m;
@@ -861,6 +910,84 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
   return it;
 }
 
+// ------------------------------------------- grid-problem preconditioner ---
+// Chebyshev semi-iteration coefficients for M z = b with the Jacobi splitting:
+// the eigenvalues of D^-1 M of the P1 mass matrix on Kuhn simplices lie in
+// [1/2, 1 + d/2] (element by element, the Jacobi-scaled element mass matrix
+// of a d-simplex has the eigenvalues 1/2 and 1 + d/2), so after k steps the
+// error is reduced by the Chebyshev factor of that interval.  Step 0 is
+// z_1 = D^-1 b / theta; step k >= 1 is d_k = rho_k rho_{k-1} d_{k-1} +
+// (2 rho_k / delta) D^-1 (b - M z_k), z_{k+1} = z_k + d_k, with
+// rho_k = 1 / (2 sigma - rho_{k-1}), rho_0 = 1 / sigma (Chebyshev
+// acceleration of a splitting, e.g. Saad's Iterative Methods, Sect. 12.3).
+static void mass_cheb_coefs(int d, int k, double* cd, double* cr) {
+  const double lmin = 0.5, lmax = 1.0 + 0.5 * d;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho_prev = 1.0 / sigma;
+  if (k == 0) {
+    *cd = 0;
+    *cr = 1.0 / theta;
+    return;
+  }
+  double rho = rho_prev;
+  for (int i = 1; i <= k; ++i) {
+    rho = 1.0 / (2 * sigma - rho_prev);
+    if (i < k) rho_prev = rho;
+  }
+  *cd = rho * rho_prev;
+  *cr = 2 * rho / delta;
+}
+
+static void check_mass(const sgdg_precond_opts& po, int d) {
+  require(po.mass_sweeps >= -1 && po.mass_sweeps <= 64, "mass_sweeps must be -1..64");
+  require(po.mass_sweeps != -1 || d == 1, "mass_sweeps = -1 (exact tridiagonal mass solves) needs d = 1");
+}
+
+// The preconditioner of the grid problems (Sect. 4.3): the inverse of
+// (Tt + delta Ct + Gt) (x) M^x (x) M^v on every segment.  sweeps 0: the mass
+// matrices replaced by their diagonals; k > 0: k Chebyshev-Jacobi steps per
+// mass factor (a fixed polynomial, so a fixed linear map); -1 (d = 1): the
+// mass factors inverted exactly, one tridiagonal solve per grid line.  The
+// mass factors act on different axes and commute with the time block, so the
+// x-solve, the v-solve and the time block run one after the other.
+template <class T>
+static void mass_precond(Batch& B, const SegTab& ST, int sweeps, const T* in, T* out, hipStream_t q) {
+  const SegTable& S = ST.t;
+  BWork<T>& w = work<T>(B);
+  if (sweeps == 0) {
+    KernelsT<T>::minv(S, in, out, q);
+    return;
+  }
+  if (sweeps < 0) {
+    int lx = 0, lv = 0;
+    for (const SegInfo& g : ST.host) {
+      lx = std::max(lx, g.R * g.nv);
+      lv = std::max(lv, g.R * g.nx);
+    }
+    T* c = ptr<T>(w.mX0);
+    T* z = ptr<T>(w.mX1);
+    KernelsT<T>::mass_thomas(S, 0, lx, in, out, c, z, q);
+    KernelsT<T>::mass_thomas(S, 1, lv, out, out, c, z, q);
+    KernelsT<T>::tinv(S, out, out, q);
+    return;
+  }
+  T* xs[2] = {ptr<T>(w.mX0), ptr<T>(w.mX1)};
+  T* ds[2] = {ptr<T>(w.mD0), ptr<T>(w.mD1)};
+  for (int axis = 0; axis < 2; ++axis) {
+    const T* b = axis == 0 ? in : ptr<T>(w.mU);
+    T* dst = axis == 0 ? ptr<T>(w.mU) : out;
+    for (int k = 0; k < sweeps; ++k) {
+      double cd, cr;
+      mass_cheb_coefs(B.d, k, &cd, &cr);
+      const bool last = k + 1 == sweeps;
+      T* xo = last ? dst : xs[k & 1];
+      T* dout = last ? nullptr : ds[k & 1];
+      KernelsT<T>::mass_cheb(S, axis, cd, cr, k == 0 ? 1 : 0, (last && axis == 1) ? 1 : 0, b,
+                             k == 0 ? nullptr : xs[(k - 1) & 1], k == 0 ? nullptr : ds[(k - 1) & 1], xo, dout, q);
+    }
+  }
+}
+
 // --------------------------------------------------- CT preconditioner ----
 template <class T>
 static void ct_apply(Batch& B, const T* r, T* z, const sgdg_precond_opts& po, bool use_graph, hipStream_t s,
@@ -874,11 +1001,19 @@ static void ct_apply(Batch& B, const T* r, T* z, const sgdg_precond_opts& po, bo
   w.ctw.ensure(sizeof(T) * nct);
   w.cttmp.ensure(sizeof(T) * nct);
   w.ctV.ensure(sizeof(T) * nct * (m + 1));
+  if (po.mass_sweeps != 0) {
+    w.mU.ensure(sizeof(T) * nct);
+    w.mX0.ensure(sizeof(T) * nct);
+    w.mX1.ensure(sizeof(T) * nct);
+    w.mD0.ensure(sizeof(T) * nct);
+    w.mD1.ensure(sizeof(T) * nct);
+  }
   T* b = ptr<T>(w.ctb);
   KernelsT<T>::ct_gather(ST.t, r, b, s);
   items(B, K_CT, int(sizeof(T)));  // tables exist before any capture
+  const int sweeps = po.mass_sweeps;
   auto A = [&](const T* in, T* out, hipStream_t q) { apply<T>(B, K_CT, in, out, 1, q); };
-  auto M = [&](const T* in, T* out, hipStream_t q) { KernelsT<T>::minv(ST.t, in, out, q); };
+  auto M = [&](const T* in, T* out, hipStream_t q) { mass_precond<T>(B, ST, sweeps, in, out, q); };
   B.inner_iters += batched_gmres<T>(B, ST, A, M, b, ptr<T>(w.ctx), ptr<T>(w.ctV), ptr<T>(w.ctw), ptr<T>(w.cttmp), m,
                                     po.inner_maxit, po.inner_rtol, use_graph, s, nan);
   KernelsT<T>::ct_combine(ST.t, ptr<T>(w.ctx), z, s);
@@ -1017,6 +1152,26 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
   }
 }
 
+// The learned preconditioner's fallback rule: over any `iters` consecutive
+// learned FGMRES iterations of one FGMRES call the residual estimate must drop
+// by the factor `drop`.  Estimates are relative to that call's right-hand side
+// (in mixed precision each refinement step solves for its own residual), so the
+// history restarts with every call.
+struct FallbackMonitor {
+  int iters;
+  double drop;
+  std::vector<double> hist;  // estimate at entry, then after each learned iteration
+  FallbackMonitor(int it, double dr) : iters(it), drop(dr) {}
+  void begin() { hist.clear(); }
+  // true: switch to the combination technique now
+  bool step(double est, double rel0) {
+    if (hist.empty()) hist.push_back(rel0);
+    hist.push_back(est);
+    const size_t k = hist.size() - 1;
+    return k >= size_t(iters) && est > hist[k - size_t(iters)] / drop;
+  }
+};
+
 static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const sgdg_solve_opts& so, hipStream_t s,
                                     bool* nan) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1039,18 +1194,15 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
   const int fb_iters = pc.fallback_iters > 0 ? pc.fallback_iters : 10;
   const double fb_drop = pc.fallback_drop > 1 ? pc.fallback_drop : 10.0;
   sgdg_net rec = B.owned_by_ops ? B.P[0]->recorder : nullptr;
-  std::vector<double> est_hist;  // residual estimate after each learned iteration (index 0: at entry)
+  FallbackMonitor fb(fb_iters, fb_drop);
   // At the switch the cycle ends: the combination technique then starts a
   // fresh Krylov space from the true residual instead of extending the basis
   // the network built.
   const Monitor monitor = [&](int it, double est, double rel0) {
-    if (use_ct) return false;
-    if (est_hist.empty()) est_hist.push_back(rel0);
-    est_hist.push_back(est);
     (void)it;
-    const size_t k = est_hist.size() - 1;  // learned iterations so far
-    if (k >= size_t(fb_iters) && est > est_hist[k - fb_iters] / fb_drop) {
-      use_ct = true;  // no drop by fb_drop over the last fb_iters iterations
+    if (use_ct) return false;
+    if (fb.step(est, rel0)) {
+      use_ct = true;
       fell_back = true;
       return true;
     }
@@ -1121,6 +1273,7 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
       }
       if (rel <= so.rtol || total >= so.maxit || steps >= 20) break;
       KernelsT<double>::fill(n, 0.0, e, s);
+      fb.begin();  // estimates of this correction solve are relative to its own right-hand side
       FgmresResult ri =
           fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s, learned ? &monitor : nullptr);
       total += std::max(ri.iters, 1);
@@ -1375,17 +1528,42 @@ extern "C" sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_
                                          const sgdg_precond_opts* po_in, hipStream_t s) {
   API_BEGIN
   require(o && r_dev && z_dev && r_dev != z_dev, "null or aliased argument");
-  require(batch == 1, "precondition supports batch == 1");
+  require(batch >= 1 && batch <= 4096, "batch must be 1..4096");
   const sgdg_precond_opts po = po_in ? *po_in : default_pc();
   require(po.kind == 0, "sgdg_precondition applies the combination technique (kind 0); see sgdg_net_apply");
   require(po.inner_rtol > 0 && po.inner_maxit >= 1 && po.inner_restart >= 1, "invalid inner solver options");
-  Batch& B = self_batch(o);
+  check_mass(po, o->X.dom.d);
+  // batch vectors [B][n_dof] are the layout of the problem replicated B times:
+  // every grid problem of every vector iterates in the same launches
+  Batch& B = replica_batch(o, batch);
   bool nan = false;
   if (t == SGDG_F64)
     ct_apply<double>(B, static_cast<const double*>(r_dev), static_cast<double*>(z_dev), po, false, s, &nan);
   else
     ct_apply<float>(B, static_cast<const float*>(r_dev), static_cast<float*>(z_dev), po, false, s, &nan);
   if (nan) throw Error{SGDG_E_NAN, "non-finite residual in a grid problem"};
+  API_END
+}
+
+extern "C" sgdg_status sgdg_debug_grid_precond(sgdg_ops o, int sweeps, const void* in_dev, void* out_dev,
+                                               sgdg_dtype t, hipStream_t s) {
+  API_BEGIN
+  require(o && in_dev && out_dev && in_dev != out_dev, "null or aliased argument");
+  require(t == SGDG_F64 || t == SGDG_F32, "dtype must be F64 or F32");
+  sgdg_precond_opts po = default_pc();
+  po.mass_sweeps = sweeps;
+  check_mass(po, o->X.dom.d);
+  Batch& B = self_batch(o);
+  SegTab& ST = ct_tab(B, B.R);
+  const int64_t nct = kind(B, K_CT).total;
+  auto run = [&](auto* tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    BWork<T>& w = work<T>(B);
+    for (DevBuf* b : {&w.mU, &w.mX0, &w.mX1, &w.mD0, &w.mD1}) b->ensure(sizeof(T) * nct);
+    mass_precond<T>(B, ST, sweeps, static_cast<const T*>(in_dev), static_cast<T*>(out_dev), s);
+  };
+  if (t == SGDG_F64) run(static_cast<double*>(nullptr));
+  else run(static_cast<float*>(nullptr));
   API_END
 }
 
@@ -1445,7 +1623,7 @@ static void check_solve_opts(const sgdg_solve_opts* so, const Batch& B) {
   require(so != nullptr, "null solver options");
   require(so->rtol > 0 && so->restart >= 1 && so->restart <= 64 && so->maxit >= 1, "invalid solver options");
   require(so->pc.kind == 0 || so->pc.kind == 1, "unknown preconditioner kind");
-  require(so->pc.mass_sweeps == 0, "mass_sweeps must be 0");
+  check_mass(so->pc, B.d);
   if (so->pc.kind == 1)
     require(so->pc.net != nullptr && B.P.size() == 1 && net_problem(so->pc.net) == B.P[0],
             "the learned preconditioner needs the network of this problem");
@@ -1545,6 +1723,31 @@ extern "C" sgdg_status sgdg_profile_read(sgdg_ops o, int slot, double* ms, int64
   drain_events(B);
   if (ms) *ms = B.prof_ms[slot];
   if (launches) *launches = B.prof_n[slot];
+  API_END
+}
+
+extern "C" sgdg_status sgdg_debug_fallback(int iters, double drop, int n, const int* call, const double* rel0,
+                                           const double* est, int* switch_at) {
+  API_BEGIN
+  require(iters >= 1 && drop > 1 && n >= 0 && (n == 0 || (call && rel0 && est)) && switch_at, "bad arguments");
+  FallbackMonitor fb(iters, drop);
+  *switch_at = -1;
+  for (int i = 0; i < n; ++i) {
+    if (i == 0 || call[i] != call[i - 1]) fb.begin();
+    if (fb.step(est[i], rel0[i])) {
+      *switch_at = i;
+      break;
+    }
+  }
+  API_END
+}
+
+extern "C" sgdg_status sgdg_graph_cache_size(sgdg_ops o, int* count) {
+  API_BEGIN
+  require(o != nullptr && count != nullptr, "null argument");
+  Batch& B = self_batch(o);
+  // a stale cache is emptied on the next graph solve; report what would survive it
+  *count = B.graph_epoch == alloc_epoch() ? int(B.graphs.size()) : 0;
   API_END
 }
 

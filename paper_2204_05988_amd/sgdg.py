@@ -27,6 +27,7 @@ EXPORTS = [
     "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
     "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune", "sgdg_set_launch",
+    "sgdg_graph_cache_size", "sgdg_debug_fallback", "sgdg_debug_grid_precond",
 ]
 
 
@@ -142,6 +143,9 @@ def lib():
     L.sgdg_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
     L.sgdg_batch_tune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneResult), vp]
     L.sgdg_set_launch.argtypes = [vp, C.POINTER(TuneResult)]
+    L.sgdg_graph_cache_size.argtypes = [vp, ip]
+    L.sgdg_debug_fallback.argtypes = [C.c_int, C.c_double, C.c_int, ip, dp, dp, ip]
+    L.sgdg_debug_grid_precond.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp]
     for name in EXPORTS:
         if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy",
                         "sgdg_net_destroy"):
@@ -202,6 +206,24 @@ class _ProblemHolder:
 
 
 def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _dev(t, name, numel, dtypes=("float64",)):
+    """Checks one device-buffer argument before any launch: a contiguous GPU
+    tensor of an accepted dtype holding exactly `numel` elements.  A wrong
+    buffer would otherwise become an out-of-bounds device access."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if str(t.dtype).replace("torch.", "") not in dtypes:
+        raise TypeError(f"{name}: dtype {t.dtype} not in {dtypes}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: has {t.numel()} elements, expected {numel}")
     return t.data_ptr()
 
 
@@ -274,36 +296,40 @@ class SparseGridOps:
     # ---- calls -------------------------------------------------------------------
     def apply(self, u, y, kind=OP_FULL, batch=1, stream=None):
         import torch
-        dt = F64 if u.dtype == torch.float64 else F32
-        assert u.is_cuda and y.is_cuda and u.is_contiguous() and y.is_contiguous() and u.dtype == y.dtype
         n = self.ndof // self.R if kind == OP_MASS else self.ndof
-        assert u.numel() == batch * n and y.numel() == batch * n, "shape mismatch"
-        _check(lib().sgdg_apply_operator(self.ops, kind, _ptr(u), _ptr(y), dt, batch, _stream(stream)))
+        pu = _dev(u, "u", batch * n, ("float64", "float32"))
+        py = _dev(y, "y", batch * n, (str(u.dtype).replace("torch.", ""),))
+        dt = F64 if u.dtype == torch.float64 else F32
+        _check(lib().sgdg_apply_operator(self.ops, kind, pu, py, dt, batch, _stream(stream)))
         return y
 
     def combine(self, nodal, coef, nslices, stream=None):
-        assert nodal.numel() == nslices * (self.npts_up + self.npts_low) and coef.numel() == nslices * self.npts_up
-        _check(lib().sgdg_combine(self.ops, _ptr(nodal), _ptr(coef), nslices, _stream(stream)))
+        pn = _dev(nodal, "nodal", nslices * (self.npts_up + self.npts_low))
+        pc = _dev(coef, "coef", nslices * self.npts_up)
+        _check(lib().sgdg_combine(self.ops, pn, pc, nslices, _stream(stream)))
         return coef
 
-    def precondition(self, r, z, opts: Optional[PrecondOpts] = None, stream=None):
+    def precondition(self, r, z, opts: Optional[PrecondOpts] = None, stream=None, batch=1):
         import torch
+        assert batch >= 1
+        pr = _dev(r, "r", batch * self.ndof, ("float64", "float32"))
+        pz = _dev(z, "z", batch * self.ndof, (str(r.dtype).replace("torch.", ""),))
         dt = F64 if r.dtype == torch.float64 else F32
-        assert r.numel() == self.ndof and z.numel() == self.ndof and r.dtype == z.dtype
         o = opts or default_precond_opts()
-        _check(lib().sgdg_precondition(self.ops, _ptr(r), _ptr(z), dt, 1, C.byref(o), _stream(stream)))
+        _check(lib().sgdg_precondition(self.ops, pr, pz, dt, batch, C.byref(o), _stream(stream)))
         return z
 
     def rhs(self, u_prev, prev_slices, f_nodal=None, g_nodal=None, b=None, stream=None):
         import torch
         if b is None:
             b = torch.empty(self.ndof, dtype=torch.float64, device=u_prev.device)
-        assert u_prev.numel() == prev_slices * self.npts_up
+        pu = _dev(u_prev, "u_prev", prev_slices * self.npts_up)
         nq = self.w.r + 2
-        for a in (f_nodal, g_nodal):
-            assert a is None or a.numel() == nq * (self.npts_up + self.npts_low)
-        _check(lib().sgdg_rhs(self.ops, _ptr(u_prev), prev_slices, _ptr(f_nodal) if f_nodal is not None else None,
-                              _ptr(g_nodal) if g_nodal is not None else None, _ptr(b), _stream(stream)))
+        nn = nq * (self.npts_up + self.npts_low)
+        pf = _dev(f_nodal, "f_nodal", nn) if f_nodal is not None else None
+        pg = _dev(g_nodal, "g_nodal", nn) if g_nodal is not None else None
+        pb = _dev(b, "b", self.ndof)
+        _check(lib().sgdg_rhs(self.ops, pu, prev_slices, pf, pg, pb, _stream(stream)))
         return b
 
     def profile(self, on: bool):
@@ -336,10 +362,28 @@ class SparseGridOps:
         r = TuneResult(VARIANTS.index(variant), vectors_per_thread, xbox, block_map, 0.0, 0)
         _check(lib().sgdg_set_launch(self.ops, C.byref(r)))
 
+    def grid_precond(self, x, y, sweeps=0, stream=None):
+        """Diagnostic: the grid-problem preconditioner on the layout of every
+        upper grid followed by every lower grid ([R][n_x][n_v] blocks)."""
+        import torch
+        n = self.R * (self.npts_up + self.npts_low)
+        px = _dev(x, "x", n, ("float64", "float32"))
+        py = _dev(y, "y", n, (str(x.dtype).replace("torch.", ""),))
+        _check(lib().sgdg_debug_grid_precond(self.ops, sweeps, px, py, F64 if x.dtype == torch.float64 else F32,
+                                             _stream(stream)))
+        return y
+
+    def graph_cache_size(self):
+        c = C.c_int()
+        _check(lib().sgdg_graph_cache_size(self.ops, C.byref(c)))
+        return c.value
+
     def solve_strip(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
+        pb = _dev(b, "b", self.ndof)
+        pu = _dev(u, "u", self.ndof)
         o = opts or default_solve_opts()
         st = SolveStats()
-        code = lib().sgdg_solve_strip(self.ops, _ptr(b), _ptr(u), C.byref(o), C.byref(st), _stream(stream))
+        code = lib().sgdg_solve_strip(self.ops, pb, pu, C.byref(o), C.byref(st), _stream(stream))
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return u, st
@@ -364,10 +408,10 @@ class SparseGridBatch:
 
     def apply(self, u, y, stream=None):
         import torch
+        pu = _dev(u, "u", self.ndof, ("float64", "float32"))
+        py = _dev(y, "y", self.ndof, (str(u.dtype).replace("torch.", ""),))
         dt = F64 if u.dtype == torch.float64 else F32
-        assert u.is_cuda and y.is_cuda and u.is_contiguous() and y.is_contiguous() and u.dtype == y.dtype
-        assert u.numel() == self.ndof and y.numel() == self.ndof, "shape mismatch"
-        _check(lib().sgdg_batch_apply(self.h, _ptr(u), _ptr(y), dt, _stream(stream)))
+        _check(lib().sgdg_batch_apply(self.h, pu, py, dt, _stream(stream)))
         return y
 
     def tune(self, dtype="f64", reps=3, force=False, stream=None):
@@ -377,10 +421,11 @@ class SparseGridBatch:
         return r.as_dict()
 
     def solve(self, b, u, opts: Optional[SolveOpts] = None, stream=None, raise_on_noconv=True):
-        assert b.numel() == self.ndof and u.numel() == self.ndof
+        pb = _dev(b, "b", self.ndof)
+        pu = _dev(u, "u", self.ndof)
         o = opts or default_solve_opts()
         st = SolveStats()
-        code = lib().sgdg_batch_solve(self.h, _ptr(b), _ptr(u), C.byref(o), C.byref(st), _stream(stream))
+        code = lib().sgdg_batch_solve(self.h, pb, pu, C.byref(o), C.byref(st), _stream(stream))
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return u, st
@@ -424,8 +469,10 @@ class LearnedPreconditioner:
                                          None if ss is None else ss.ctypes.data_as(C.POINTER(C.c_double))))
 
     def add_pairs(self, r, z, stream=None):
-        assert r.numel() == z.numel() and r.numel() % self.ops.ndof == 0
-        _check(lib().sgdg_net_add_pairs(self.h, _ptr(r), _ptr(z), r.numel() // self.ops.ndof, _stream(stream)))
+        assert r.numel() % self.ops.ndof == 0 and r.numel() > 0
+        pr = _dev(r, "r", r.numel())
+        pz = _dev(z, "z", r.numel())
+        _check(lib().sgdg_net_add_pairs(self.h, pr, pz, r.numel() // self.ops.ndof, _stream(stream)))
 
     def record(self, capacity):
         _check(lib().sgdg_net_record(self.h, capacity))
@@ -442,18 +489,22 @@ class LearnedPreconditioner:
         return st
 
     def apply(self, r, z, stream=None):
-        assert r.numel() == self.ops.ndof and z.numel() == self.ops.ndof
-        _check(lib().sgdg_net_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        pr = _dev(r, "r", self.ops.ndof)
+        pz = _dev(z, "z", self.ops.ndof)
+        _check(lib().sgdg_net_apply(self.h, pr, pz, _stream(stream)))
         return z
 
     def forward(self, x, y, stream=None):
-        assert x.numel() == self.ops.ndof and y.numel() == self.ops.ndof
-        _check(lib().sgdg_net_forward(self.h, _ptr(x), _ptr(y), _stream(stream)))
+        px = _dev(x, "x", self.ops.ndof, ("float32",))
+        py = _dev(y, "y", self.ops.ndof, ("float32",))
+        _check(lib().sgdg_net_forward(self.h, px, py, _stream(stream)))
         return y
 
     def backward(self, x, dy, grad, stream=None):
-        assert grad.numel() == self.n_params
-        _check(lib().sgdg_net_backward(self.h, _ptr(x), _ptr(dy), _ptr(grad), _stream(stream)))
+        px = _dev(x, "x", self.ops.ndof, ("float32",))
+        pd = _dev(dy, "dy", self.ops.ndof, ("float32",))
+        pg = _dev(grad, "grad", self.n_params, ("float32",))
+        _check(lib().sgdg_net_backward(self.h, px, pd, pg, _stream(stream)))
         return grad
 
     def close(self):
@@ -484,3 +535,17 @@ def debug_dense_block(w, kind, row_grid, col_grid, fields=None):
     _check(lib().sgdg_debug_dense_block(C.byref(dx), C.byref(dv), w.lmin, w.L, w.r, C.byref(holder.p), kind,
                                         row_grid, col_grid, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
+
+
+def debug_fallback(iters, drop, calls, rel0, est):
+    """Host-only: index of the FGMRES iteration after which the learned
+    preconditioner's fallback rule switches to the combination technique (-1: never)."""
+    n = len(est)
+    ca = np.ascontiguousarray(calls, dtype=np.int32)
+    ra = np.ascontiguousarray(rel0, dtype=np.float64)
+    ea = np.ascontiguousarray(est, dtype=np.float64)
+    out = C.c_int()
+    _check(lib().sgdg_debug_fallback(int(iters), float(drop), n, ca.ctypes.data_as(C.POINTER(C.c_int)),
+                                     ra.ctypes.data_as(C.POINTER(C.c_double)),
+                                     ea.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out)))
+    return out.value

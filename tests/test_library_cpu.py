@@ -79,3 +79,62 @@ def test_host_assembly_c1_cross_blocks():
         D = sgdg.debug_dense_block(w, sgdg.OP_FULL, i, j)
         O = P.assembled_block(P.terms, P.upper[i], P.upper[j]).toarray()
         assert np.abs(D - O).max() <= 1e-13 * np.abs(O).max()
+
+
+def test_fallback_rule_restarts_with_each_fgmres_call():
+    """The learned preconditioner's fallback rule measures each FGMRES call
+    against its own right-hand side: in mixed precision the second refinement
+    step starts at an estimate of O(1) again, which must not be compared with
+    the first step's small estimates."""
+    # call 0: the network drops the estimate by 10 every 5 iterations (no fallback)
+    est0 = [10.0 ** (-(k + 1) / 5) for k in range(12)]
+    # call 1 (next refinement step): the same healthy decay from 1 again
+    est1 = [10.0 ** (-(k + 1) / 5) for k in range(12)]
+    calls = [0] * 12 + [1] * 12
+    rel0 = [1.0] * 24
+    assert sgdg.debug_fallback(10, 10.0, calls, rel0, est0 + est1) == -1
+    # one shared history would compare call 1's O(1) estimates with call 0's 1e-2: a switch at once
+    assert sgdg.debug_fallback(10, 10.0, [0] * 24, rel0, est0 + est1) == 12
+    # a stagnating network falls back after `iters` learned iterations of its call
+    stall = [0.9] * 15
+    assert sgdg.debug_fallback(10, 10.0, [0] * 15, [1.0] * 15, stall) == 9
+    assert sgdg.debug_fallback(10, 10.0, [0] * 12 + [1] * 15, [1.0] * 27, est0 + stall) == 12 + 9
+
+
+def test_device_arguments_are_checked_before_any_launch():
+    """Every tensor handed to the C ABI is checked for device, contiguity,
+    dtype and size first; a wrong buffer must raise, never reach a kernel."""
+    torch = pytest.importorskip("torch")
+    x = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        sgdg._dev(x, "u", 10)
+    with pytest.raises(TypeError):
+        sgdg._dev(np.zeros(10), "u", 10)
+    # the checks after the device check, exercised on a stand-in that reports a GPU
+    class FakeCuda:
+        def __init__(self, t):
+            self.t = t
+            self.is_cuda = True
+            self.dtype = t.dtype
+
+        def is_contiguous(self):
+            return self.t.is_contiguous()
+
+        def numel(self):
+            return self.t.numel()
+
+        def data_ptr(self):
+            return self.t.data_ptr()
+
+    orig = torch.Tensor
+    try:
+        torch.Tensor = FakeCuda  # isinstance check sees the stand-in as a tensor
+        with pytest.raises(ValueError, match="contiguous"):
+            sgdg._dev(FakeCuda(torch.zeros(4, 4, dtype=torch.float64).t()), "u", 16)
+        with pytest.raises(TypeError, match="dtype"):
+            sgdg._dev(FakeCuda(torch.zeros(10, dtype=torch.float32)), "u", 10)
+        with pytest.raises(ValueError, match="elements"):
+            sgdg._dev(FakeCuda(torch.zeros(9, dtype=torch.float64)), "u", 10)
+        assert sgdg._dev(FakeCuda(torch.zeros(10, dtype=torch.float64)), "u", 10) != 0
+    finally:
+        torch.Tensor = orig
