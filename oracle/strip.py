@@ -14,8 +14,12 @@ the Kronecker form with those coefficient vectors.  The jump term uses the
 trace U_{j-1}(t_{j-1}^-) = sum_s u_s (Legendre values 1 at the right end) and
 w(t_{j-1}^+) = eta_s(-1) = (-1)^s.
 
-Parity: the data functionals are exact for the interpolated data (a
-definition); pinned end to end by the exact-solution and convergence tests.
+Parity: pinned by the tests.  A solution that lies in the discrete space
+(affine in x and v, degree <= r in time, r = 0, 1, 2, d = 1 and 2) with its own
+f and g as data is reproduced strip after strip to rounding, which fixes every
+term of the f functional (including delta (d_t w + d_beta w)), the inflow
+functional, the time projection with its (2s+1)/dt factor and the jump term;
+the forced c1 problem (reaction plus f = sigma u) converges with the level.
 """
 from __future__ import annotations
 

@@ -349,3 +349,132 @@ def test_table1_d1_r1_convergence():
     for Lp in range(3, 6):
         order = np.log2(errs[Lp - 1] / errs[Lp])
         assert abs(order - table[Lp][1]) < 0.05, (Lp, order)
+
+
+# --- data functionals: a solution in the discrete space is reproduced exactly --------------
+
+def _discrete_exact_workload(d, r, L, nstrips=2):
+    """u = p(x, v) + q t + e t^2 with p affine in (x, v), beta = (v, c(x)) with c affine and
+    positive (d = 1) or beta = (v, a) (d = 2), sigma constant.  Then u and the data
+    f = d_t u + beta.grad u + sigma u and g = u are affine in space (P1 on the coarsest
+    level, so every interpolant is exact) and of degree <= r in time.  By the consistency
+    of the streamline-diffusion weak form (eq:weak_form_j) and the uniqueness of the strip
+    solution (Thm 2) the discrete solution of every strip is u itself.  (A bilinear term
+    such as x v would not do: beta.grad u would then hold v^2, outside the P1 spaces.)"""
+    sig = 0.3
+    qt = 0.7 if r >= 1 else 0.0
+    et = -0.4 if r >= 2 else 0.0
+    if d == 1:
+        x = Domain(1, (0.0,), (1.0,))
+        v = Domain(1, (-1.0,), (1.0,))
+        c0, c1 = 0.5, 0.8                     # beta_v = c(x) = c0 + c1 x > 0: inflow on v = -1
+
+        def u(t, X, V):
+            xx, vv = X[..., 0], V[..., 0]
+            return 1.0 + 0.6 * xx - 0.9 * vv + qt * t + et * t * t
+
+        def f(t, X, V):
+            xx, vv = X[..., 0], V[..., 0]
+            return (qt + 2 * et * t) + vv * 0.6 + (c0 + c1 * xx) * (-0.9) + sig * u(t, X, V)
+
+        return Workload(name="exact_d1", x=x, v=v, lmin=1, L=L, r=r, dt=0.05, delta=0.04, nstrips=nstrips,
+                        beta=[(1.0, (), ("v0",)), (1.0, ("c",), ())], sigma=[(sig, (), ())],
+                        xfields={"c": lambda P: c0 + c1 * P[:, 0]}, vfields={"v0": lambda P: P[:, 0].copy()},
+                        u0=lambda X, V: u(0.0, X, V), f=f, g=u, exact=u)
+    x = Domain(2, (0.0, 0.0), (1.0, 1.0))
+    v = Domain(2, (-1.0, -1.0), (1.0, 1.0))
+    a = np.array([0.5, -0.3])
+    bx = np.array([0.4, -0.7])
+    cv = np.array([0.2, 0.5])
+
+    def u(t, X, V):
+        return 1.0 + X @ bx + V @ cv + qt * t + et * t * t
+
+    def f(t, X, V):
+        return (qt + 2 * et * t) + V @ bx + float(cv @ a) + sig * u(t, X, V)
+
+    return Workload(name="exact_d2", x=x, v=v, lmin=0, L=L, r=r, dt=0.05, delta=0.05, nstrips=nstrips,
+                    beta=[(1.0, (), ("v0",)), (1.0, (), ("v1",)), (float(a[0]), (), ()), (float(a[1]), (), ())],
+                    sigma=[(sig, (), ())], xfields={},
+                    vfields={"v0": lambda P: P[:, 0].copy(), "v1": lambda P: P[:, 1].copy()},
+                    u0=lambda X, V: u(0.0, X, V), f=f, g=u, exact=u)
+
+
+def _legendre_slices(P, fn, t0, dt, R):
+    """Spanning coefficients of the time slices of fn on [t0, t0 + dt] for fn of degree < R in t:
+    values at R distinct times, then the Legendre-Vandermonde system (no quadrature)."""
+    tau = np.cos(np.pi * (np.arange(R) + 0.5) / R)
+    Vd = np.polynomial.legendre.legvander(tau, R - 1)            # (R times, R slices)
+    Vinv = np.linalg.inv(Vd)
+    vals = [strip.interpolate(P, lambda X, V, t=t0 + 0.5 * dt * (tk + 1): fn(t, X, V)) for tk in tau]
+    slices = [sum(Vinv[s, k] * vals[k] for k in range(R)) for s in range(R)]
+    return slices
+
+
+@pytest.mark.parametrize("d,r,L", [(1, 0, 4), (1, 1, 4), (1, 2, 3), (2, 1, 2)])
+def test_discrete_exact_solution_is_reproduced(d, r, L):
+    """Pins the data functionals b_f (including delta (d_t w + d_beta w)), b_g, the time
+    projection of the data and the jump term: every strip must return u to rounding."""
+    w = _discrete_exact_workload(d, r, L)
+    P = Problem(w)
+    sols, st = strip.march(P, tol=1e-13, maxit=200)
+    assert all(s["rel"] <= 1e-12 for s in st)
+    for j, U in enumerate(sols, start=1):
+        ref = _legendre_slices(P, w.exact, (j - 1) * w.dt, w.dt, P.R)
+        blocks = P.split(U)
+        err2 = ref2 = 0.0
+        for s in range(P.R):
+            us = np.concatenate([b[s].ravel() for b in blocks])
+            e = us - ref[s]
+            err2 += abs(e @ P.apply_mass(e))
+            ref2 += abs(ref[s] @ P.apply_mass(ref[s]))
+        assert np.sqrt(err2 / ref2) < 1e-10, (j, np.sqrt(err2 / ref2))
+
+
+def test_discrete_exact_solution_needs_every_data_term():
+    """The exactness above is not automatic: dropping the streamline-diffusion part
+    delta (d_t w + d_beta w) of the f functional, or the f functional altogether,
+    moves the solution away from u."""
+    w = _discrete_exact_workload(1, 1, 4, nstrips=1)
+    P = Problem(w)
+    b_full = strip.rhs(P, 1, strip.initial_coefficients(P), 1)
+    f_part = P.apply(strip.project_in_time(P, w.f, 0.0), P.data_terms())
+    Mt = P.Mt
+    S = P.spatial_ops()
+    plain = [(c * Mt, X, V) for c, X, V in S["M"]]             # (f, w) only
+    f_plain = P.apply(strip.project_in_time(P, w.f, 0.0), plain)
+    ref = _legendre_slices(P, w.exact, 0.0, w.dt, P.R)
+    uref = np.concatenate([np.stack([ref[s][o:o + n] for s in range(P.R)]).ravel()
+                           for o, n in zip(np.cumsum([0] + [P.nx(a) * P.nv(b) for a, b in P.upper])[:-1],
+                                           [P.nx(a) * P.nv(b) for a, b in P.upper])])
+    assert np.linalg.norm(P.apply(uref) - b_full) < 1e-11 * np.linalg.norm(b_full)
+    for b_bad in (b_full - f_part + f_plain, b_full - f_part):
+        assert np.linalg.norm(P.apply(uref) - b_bad) > 1e-3 * np.linalg.norm(b_full)
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_forced_convergence_c1(r):
+    """c1 with a reaction sigma = 0.5 and the forcing f = sigma u that keeps
+    sin(2 pi (x - v t)) exp(-4 v^2) exact: the error at the final time falls
+    with every level (Thm 3: order r + 1/2 in the SD norm, less in L2 near the
+    time-step floor)."""
+    errs = []
+    for L in (4, 5, 6):
+        w = config_c1()
+        w.noise = 0.0
+        w.L = L
+        w.delta = 0.5 * min(1.0 / 2 ** L, 2.0 / 2 ** L)
+        w.r = r
+        w.sigma = [(0.5, (), ())]
+        ex = w.exact
+        w.f = lambda t, X, V, ex=ex: 0.5 * ex(t, X, V)
+        P = Problem(w)
+        sols, st = strip.march(P, tol=1e-11)
+        assert all(s["rel"] <= 1e-11 for s in st)
+        T = w.nstrips * w.dt
+        exT = strip.interpolate(P, lambda X, V: ex(T, X, V))
+        e = strip.trace_right(P, sols[-1], P.R) - exT
+        errs.append(np.sqrt(e @ P.apply_mass(e)) / np.sqrt(exT @ P.apply_mass(exT)))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[0] / errs[2] > 3.0, errs
+    assert errs[2] < 0.02, errs
