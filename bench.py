@@ -572,34 +572,110 @@ def _grids(shapes):
     return [(lx, lv) for lx, lv, _, _ in shapes]
 
 
-def cpu_baseline(w, gpu_value):
-    """The oracle (factored form, NumPy/SciPy FP64) on the host: single-vector applies."""
+_CPU_P = None   # the oracle problem shared with forked pool workers
+
+
+def _cpu_rows(idx):
+    """Worker: output blocks [A u]_l for the upper grids in idx (the blocks are independent)."""
+    P, u = _CPU_P
+    blocks = P.split(u)
+    out = []
+    for i in idx:
+        l = P.upper[i]
+        y = sum(P.block_apply(P.terms, l, l2, ub) for l2, ub in zip(P.upper, blocks))
+        out.append((i, y.ravel()))
+    return out
+
+
+def _cpu_info():
+    info = {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
     try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
+    except Exception:  # pragma: no cover
+        pass
+    return info
+
+
+def cpu_baseline(w, gpu_value, gpu_strips=None):
+    """The oracle (factored form, NumPy/SciPy FP64) on the host cores.
+
+    apply: single-vector applies of the headline operator on one core (BLAS
+    limited to one thread), and on all cores as a process pool over the output
+    grids (each block row [A u]_l = sum_l' A_{l,l'} u_l' is independent);
+    strips: FGMRES to 1e-8 with the oracle's combination technique (direct
+    grid solves) for the 8-strip 2D march and one strip of the 4D problems at
+    L = 5 (the L = 7 strips take minutes on the host)."""
+    global _CPU_P
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
     from oracle.operator import Problem
-    from workloads import random_vector
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
+    from oracle.ct import CTPreconditioner
+    from oracle.krylov import fgmres
+    from oracle import strip as ostrip
+    from workloads import config_c1, config_c2, config_c5, random_vector
+    info = _cpu_info()
+    ncores = info["affinity"]
+    out = {"kind": "oracle", "unit": "DOF-applies/s", "host": info}
+    with threadpool_limits(1):
         P = Problem(w)
         u = random_vector(P.ndof, 0)[0]
         t0 = time.perf_counter()
-        P.apply(u)   # first apply also builds the factor caches
+        P.apply(u)   # the first apply also builds the factor caches
         setup = time.perf_counter() - t0
         n = 0
         t0 = time.perf_counter()
-        while n < 3 or (time.perf_counter() - t0 < 8.0 and n < 20):
+        while n < 3 or (time.perf_counter() - t0 < 6.0 and n < 20):
             P.apply(u)
             n += 1
-        el = time.perf_counter() - t0
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    v = n * P.ndof / el
-    return {"value": v, "unit": "DOF-applies/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} single-vector applies of the same c2 operator after a {setup:.1f}s factor setup",
-            "gpu_over_cpu": gpu_value / v}
+        v1 = n * P.ndof / (time.perf_counter() - t0)
+        out["single_core"] = {"value": v1, "cores": 1, "sample": f"{n} single-vector applies after a {setup:.1f}s factor setup"}
+        # all cores: fork after the caches exist, one task per output grid, largest first
+        _CPU_P = (P, u)
+        order = sorted(range(len(P.upper)), key=lambda i: -P.sizes[i])
+        workers = max(1, min(ncores, len(order)))
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            pool.map(_cpu_rows, [[i] for i in order])
+            k = 0
+            t0 = time.perf_counter()
+            while k < 3 or (time.perf_counter() - t0 < 6.0 and k < 20):
+                pool.map(_cpu_rows, [[i] for i in order], chunksize=1)
+                k += 1
+            vall = k * P.ndof / (time.perf_counter() - t0)
+        _CPU_P = None
+        out.update(value=vall, cores=workers,
+                   sample=f"{k} single-vector applies of the c2 operator (L={w.L}, {P.ndof} DOFs), {workers} worker "
+                          f"processes over the {len(P.upper)} output grids, one BLAS thread each")
+        out["gpu_over_cpu"] = gpu_value / vall
+        strips = {}
+        for name, wk, nst, tol in (("c1_march", config_c1(), 8, 1e-10), ("c2_L5_strip1", config_c2(L=5), 1, 1e-8),
+                                   ("c5_L5_strip1", config_c5(L=5), 1, 1e-8)):
+            t0 = time.perf_counter()
+            Pk = Problem(wk)
+            ct = CTPreconditioner(Pk)
+            uprev, prev = ostrip.initial_coefficients(Pk), 1
+            its = []
+            for j in range(1, nst + 1):
+                b = ostrip.rhs(Pk, j, uprev, prev)
+                x, st = fgmres(Pk.apply, b, ct, tol=tol, restart=50, maxit=300)
+                its.append(st["iters"])
+                uprev, prev = x, Pk.R
+            strips[name] = {"seconds": round(time.perf_counter() - t0, 3), "dofs": Pk.ndof, "strips": nst,
+                            "outer_iters": its, "rtol": tol, "cores": 1}
+            if gpu_strips and name in gpu_strips:
+                strips[name]["gpu_seconds"] = gpu_strips[name]
+            _log(f"cpu baseline: {name} {strips[name]}")
+        out["strips"] = strips
+    return out
 
 
 if __name__ == "__main__":

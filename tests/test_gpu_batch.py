@@ -180,3 +180,46 @@ def test_graph_solve_on_fresh_handle(dev):
     assert res <= 2e-10
     ops.close()
 
+
+
+def test_batch_at_benchmark_levels(dev):
+    """Members at the benchmark's levels 5, 6 and 7 (the uneven batch's size
+    spread): the batched apply of each member equals the oracle to 1e-10 (FP64)
+    and 2e-5 (FP32) and the single-problem launch bit for bit; a batched mixed
+    solve of the three reaches 1e-8 under the oracle's operator."""
+    from paper_2204_05988_amd import sgdg
+    mem = [_member(i, L) for i, L in [(5, 5), (6, 6), (7, 7)]]
+    batch = sgdg.SparseGridBatch([m[2] for m in mem])
+    off = batch.offsets
+    u = random_vector(batch.ndof, 13)[0]
+    _say(f"batched apply of members at L = 5, 6, 7, n={batch.ndof}")
+    ut = torch.tensor(u, device=dev)
+    yt = torch.empty_like(ut)
+    batch.apply(ut, yt)
+    y32 = torch.empty(batch.ndof, dtype=torch.float32, device=dev)
+    batch.apply(ut.float(), y32)
+    torch.cuda.synchronize()
+    for k, (w, P, ops) in enumerate(mem):
+        a, b = off[k], off[k + 1]
+        ref = P.apply(u[a:b])
+        err = _rel(yt[a:b].cpu().numpy(), ref)
+        err32 = _rel(y32[a:b].double().cpu().numpy(), ref)
+        _say(f"  member L={w.L}: fp64 rel err {err:.2e}, fp32 {err32:.2e}")
+        assert err <= 1e-10
+        assert err32 <= 2e-5
+        ys = torch.empty(b - a, dtype=torch.float64, device=dev)
+        ops.apply(ut[a:b].contiguous(), ys)
+        torch.cuda.synchronize()
+        assert torch.equal(ys, yt[a:b])
+    bs = [P.apply(random_vector(P.ndof, 50 + k)[0]) for k, (_, P, _) in enumerate(mem)]
+    bt = torch.tensor(np.concatenate(bs), device=dev)
+    x = torch.zeros_like(bt)
+    _say("batched mixed solve of the L = 5, 6, 7 members")
+    x, st = batch.solve(bt, x, sgdg.default_solve_opts(rtol=1e-8, maxit=300, mixed=True))
+    _say(f"  outer {st.outer_iters}, refinements {st.refinement_steps}, inner {st.inner_iters_total}, "
+         f"{st.seconds:.3f}s, max rel residual {st.rel_residual:.2e}")
+    xs = x.cpu().numpy()
+    for k, (w, P, ops) in enumerate(mem):
+        res = np.linalg.norm(bs[k] - P.apply(xs[off[k]:off[k + 1]])) / np.linalg.norm(bs[k])
+        _say(f"  member L={w.L}: oracle residual {res:.2e}")
+        assert res <= 1e-8

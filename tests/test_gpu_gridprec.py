@@ -1,0 +1,201 @@
+"""GPU parity of the grid-problem preconditioner (Sect. 4.3) and of the
+combination-technique preconditioner built on it, through the C ABI.
+
+The grid problems are preconditioned with the inverse of
+(Tt + delta Ct + Gt) (x) M^x (x) M^v: with the mass diagonals (sweeps 0),
+k Chebyshev-Jacobi steps per mass factor (sweeps k) or exact tridiagonal
+mass solves (sweeps -1, d = 1).  Each form is a fixed linear map, so the
+kernels must reproduce the oracle's dense evaluation of it (FP64 to 1e-10,
+FP32 to 2e-5 relative, max norm).  Several vectors preconditioned in one
+call must each match the oracle's CT, and a captured grid-problem graph must
+never outlive the buffers it was captured with.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import config_c1, config_c2, config_c5, config_tiny, random_vector
+from oracle import gridprec
+from oracle.ct import CTPreconditioner
+from oracle.operator import Problem
+from oracle import strip as ostrip
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_05988_amd import sgdg
+    sgdg.lib()
+    return torch.device("cuda:0")
+
+
+_cache = {}
+
+CASES = {
+    "tiny_d1": lambda: config_tiny("d1"),
+    "tiny_d1p": lambda: config_tiny("d1p"),
+    "tiny_d2": lambda: config_tiny("d2"),
+    "tiny_d3": lambda: config_tiny("d3"),
+    "c1": config_c1,
+    "c2_L4": lambda: config_c2(L=4),
+    "c5_L4": lambda: config_c5(L=4),
+}
+
+
+def _problem(name):
+    if name not in _cache:
+        from paper_2204_05988_amd import sgdg
+        w = CASES[name]()
+        _cache[name] = (w, Problem(w), sgdg.SparseGridOps(w))
+    return _cache[name]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+GP_CASES = [("tiny_d1", -1), ("tiny_d1", 0), ("tiny_d1", 1), ("tiny_d1", 3), ("tiny_d1", 8),
+            ("tiny_d1p", -1), ("tiny_d1p", 4), ("tiny_d2", 0), ("tiny_d2", 1), ("tiny_d2", 3),
+            ("tiny_d2", 8), ("tiny_d3", 0), ("tiny_d3", 2), ("tiny_d3", 6), ("c1", -1), ("c1", 5),
+            ("c2_L4", 4), ("c5_L4", 4)]
+
+
+@pytest.mark.parametrize("case,sweeps", GP_CASES, ids=[f"{c}-s{s}" for c, s in GP_CASES])
+def test_grid_preconditioner_matches_oracle(dev, case, sweeps):
+    w, P, ops = _problem(case)
+    n = P.R * (ops.npts_up + ops.npts_low)
+    x = random_vector(n, 21)[0]
+    _say(f"grid preconditioner {case} sweeps={sweeps} n={n}")
+    ref = gridprec.grid_precond_all(P, x, sweeps)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.empty_like(xt)
+    ops.grid_precond(xt, yt, sweeps)
+    y32 = torch.empty(n, dtype=torch.float32, device=dev)
+    ops.grid_precond(xt.float(), y32, sweeps)
+    torch.cuda.synchronize()
+    e64 = _rel(yt.cpu().numpy(), ref)
+    e32 = _rel(y32.double().cpu().numpy(), ref)
+    _say(f"  fp64 rel err {e64:.2e}, fp32 {e32:.2e}")
+    assert e64 <= 1e-10
+    assert e32 <= 2e-5
+
+
+@pytest.mark.parametrize("case,sweeps", [("tiny_d1", -1), ("c1", -1), ("c1", 4), ("tiny_d2", 4), ("tiny_d3", 3)])
+def test_ct_with_mass_inverses_matches_oracle(dev, case, sweeps):
+    """With tight grid solves the CT does not depend on the grid preconditioner:
+    every form must give the oracle's CT with direct solves."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem(case)
+    r = random_vector(P.ndof, 9)[0]
+    _say(f"CT with mass sweeps {sweeps}: {case}")
+    z_ref = CTPreconditioner(P)(r)
+    rt = torch.tensor(r, device=dev)
+    zt = torch.empty_like(rt)
+    ops.precondition(rt, zt, sgdg.default_precond_opts(inner_rtol=1e-13, inner_maxit=2000, mass_sweeps=sweeps))
+    torch.cuda.synchronize()
+    assert _rel(zt.cpu().numpy(), z_ref) <= 1e-9
+
+
+def test_precondition_several_vectors_in_one_call(dev):
+    """batch > 1: every vector's grid problems iterate in the same launches; each
+    result equals the oracle's CT and the one-vector call."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem("c1")
+    B = 5
+    r = random_vector(P.ndof, 17, batch=B)
+    _say(f"CT on {B} vectors at once: c1")
+    po = sgdg.default_precond_opts(inner_rtol=1e-13, inner_maxit=2000, mass_sweeps=-1)
+    rt = torch.tensor(r, device=dev)
+    zt = torch.empty_like(rt)
+    ops.precondition(rt, zt, po, batch=B)
+    zt32 = torch.empty(rt.shape, dtype=torch.float32, device=dev)
+    ops.precondition(rt.float(), zt32, sgdg.default_precond_opts(inner_rtol=1e-6, inner_maxit=500), batch=B)
+    torch.cuda.synchronize()
+    ct = CTPreconditioner(P)
+    for b in range(B):
+        ref = ct(r[b])
+        z1 = torch.empty_like(rt[b])
+        ops.precondition(rt[b].contiguous(), z1, po)
+        torch.cuda.synchronize()
+        e = _rel(zt[b].cpu().numpy(), ref)
+        e1 = _rel(zt[b].cpu().numpy(), z1.cpu().numpy())
+        e32 = _rel(zt32[b].double().cpu().numpy(), ref)
+        _say(f"  vector {b}: vs oracle {e:.2e}, vs one-vector call {e1:.2e}, fp32 (inner 1e-6) {e32:.2e}")
+        assert e <= 1e-9 and e1 <= 1e-9
+        assert e32 <= 1e-4
+
+
+def test_mass_inverses_in_strip_solves(dev):
+    """c5 (periodic x, L = 4) and c2 (L = 4) strip solves with every mass form reach
+    the tolerance under the oracle's operator; the iteration counts are reported."""
+    from paper_2204_05988_amd import sgdg
+    for case in ("c2_L4", "c5_L4"):
+        w, P, ops = _problem(case)
+        u0 = ostrip.initial_coefficients(P)
+        b_ref = ostrip.rhs(P, 1, u0, 1)
+        b = torch.tensor(b_ref, device=dev)
+        for sweeps in (0, 2, 4, 8):
+            x = torch.zeros_like(b)
+            po = sgdg.default_precond_opts(mass_sweeps=sweeps)
+            _say(f"strip solve {case} mass sweeps {sweeps}")
+            x, st = ops.solve_strip(b, x, sgdg.default_solve_opts(rtol=1e-8, pc=po))
+            res = np.linalg.norm(b_ref - P.apply(x.cpu().numpy())) / np.linalg.norm(b_ref)
+            _say(f"  {st.outer_iters} outer, {st.inner_iters_total} inner iterations over "
+                 f"{st.pc_applications} CT applications, {st.seconds:.3f} s, oracle residual {res:.2e}")
+            assert res <= 1.2e-8
+
+
+def test_graph_cache_follows_buffer_reallocation(dev):
+    """A graph solve, then a batch-16 apply and a tuning run (both reallocate the
+    shared work buffers), then a graph solve again: the cache is emptied in
+    between and the second graph solve equals the eager solve."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem("c2_L4")
+    u0 = ostrip.initial_coefficients(P)
+    b_ref = ostrip.rhs(P, 1, u0, 1)
+    b = torch.tensor(b_ref, device=dev)
+    _say("graph solve / reallocation / graph solve on c2_L4")
+    xe = torch.zeros_like(b)
+    xe, ste = ops.solve_strip(b, xe, sgdg.default_solve_opts(rtol=1e-9))
+    xg = torch.zeros_like(b)
+    xg, stg = ops.solve_strip(b, xg, sgdg.default_solve_opts(rtol=1e-9, use_graph=True))
+    assert ops.graph_cache_size() >= 1
+    B = 16
+    u = torch.tensor(random_vector(P.ndof, 3, batch=B), device=dev)
+    y = torch.empty_like(u)
+    ops.apply(u, y, batch=B)
+    ops.tune("f64", batch=B, reps=1, force=True)
+    torch.cuda.synchronize()
+    ops.set_launch("split", 2, 8, 0)   # the configuration the eager solve ran with
+    assert ops.graph_cache_size() == 0
+    xg2 = torch.zeros_like(b)
+    xg2, stg2 = ops.solve_strip(b, xg2, sgdg.default_solve_opts(rtol=1e-9, use_graph=True))
+    _say(f"  eager {ste.outer_iters}/{ste.inner_iters_total}, graph {stg.outer_iters}/{stg.inner_iters_total}, "
+         f"graph after reallocation {stg2.outer_iters}/{stg2.inner_iters_total}")
+    xe_n = xe.cpu().numpy()
+    for xx in (xg, xg2):
+        xn = xx.cpu().numpy()
+        res = np.linalg.norm(b_ref - P.apply(xn)) / np.linalg.norm(b_ref)
+        dist = _fnorm(P, xn - xe_n) / _fnorm(P, xe_n)
+        _say(f"  oracle residual {res:.2e}, L2 distance to the eager solve {dist:.2e}")
+        assert res <= 2e-9
+        assert dist <= 1e-7
+
+
+def _fnorm(P, e):
+    tot = 0.0
+    blocks = P.split(e)
+    for s in range(P.R):
+        v = np.concatenate([blk[s].ravel() for blk in blocks])
+        tot += abs(v @ P.apply_mass(v))
+    return np.sqrt(tot)

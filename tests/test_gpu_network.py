@@ -215,3 +215,43 @@ def test_learned_preconditioner_trains_and_solves(dev):
          f"oracle residual {res:.2e}")
     assert res <= 1.5e-8
     net.close()
+
+
+def test_net_parity_at_benchmark_size(dev):
+    """c5 at L = 7, the size the benchmark trains and runs at: forward outputs and
+    weight gradients of the largest x-grid (7, 0) and the largest v-grid (0, 7)
+    against the oracle (1e-2 relative norm, as above).  The networks of different
+    grids share nothing, so each grid's slice of the full launch is checked alone."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _setup(7)
+    net = sgdg.LearnedPreconditioner(ops, seed=8)
+    theta, _ = net.get_params()
+    G, R = net.n_grids, P.R
+    thetas = theta.astype(np.float64).reshape(G, -1)
+    x = random_vector(P.ndof, 18)[0].astype(np.float32)
+    dy = random_vector(P.ndof, 19)[0].astype(np.float32)
+    _say(f"network parity c5 L=7: {G} grids, {P.ndof} points")
+    xt = torch.tensor(x, device=dev)
+    yt = torch.empty_like(xt)
+    net.forward(xt, yt)
+    grad = torch.zeros(net.n_params, dtype=torch.float32, device=dev)
+    net.backward(xt, torch.tensor(dy, device=dev), grad)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy().astype(np.float64)
+    gg = grad.cpu().numpy().astype(np.float64).reshape(G, onet.NCONV, onet.CONV_PARAMS)
+    xs = _grid_tensors(w, P, x.astype(np.float64), R)
+    ys = _grid_tensors(w, P, y, R)
+    dys = _grid_tensors(w, P, dy.astype(np.float64), R)
+    picks = [P.upper.index((w.L, w.lmin)), P.upper.index((w.lmin, w.L))]
+    for g in picks:
+        ref = onet.forward(thetas[g], xs[g], w.x.periodic, w.v.periodic, bf16_path=True)[..., :R]
+        e = _relnorm(ys[g], ref)
+        dyp = np.zeros(dys[g].shape[:4] + (onet.C,))
+        dyp[..., :R] = onet.bf16(dys[g])
+        gref, _ = onet.backward(thetas[g], xs[g], dyp, w.x.periodic, w.v.periodic, bf16_path=True)
+        gref = gref.reshape(onet.NCONV, onet.CONV_PARAMS)
+        eg = max(_relnorm(gg[g, c], gref[c]) for c in range(onet.NCONV))
+        _say(f"  grid {P.upper[g]}: forward {e:.2e}, worst convolution gradient {eg:.2e}")
+        assert e <= 1e-2
+        assert eg <= 1e-2
+    net.close()

@@ -46,8 +46,17 @@ def _problem(name, fn):
     return _cache[name]
 
 
+def _with_r(w, r):
+    """The same workload with time degree r (r = 2: three Legendre slices per strip)."""
+    w.r = r
+    w.name = f"{w.name}_r{r}"
+    return w
+
+
 CASES = {
     "tiny_d1": lambda: config_tiny("d1"),
+    "tiny_d1_r2": lambda: _with_r(config_tiny("d1"), 2),
+    "tiny_d2_r2": lambda: _with_r(config_tiny("d2"), 2),
     "tiny_d1p": lambda: config_tiny("d1p"),
     "tiny_d2": lambda: config_tiny("d2"),
     "tiny_d3": lambda: config_tiny("d3"),
@@ -108,7 +117,8 @@ LAUNCHES = [("split", 1, 8, 0), ("split", 2, 8, 0), ("split", 4, 8, 0), ("split"
             ("fused", 0, 4, 0), ("fused", 0, 8, 0), ("fused", 0, 16, 0)]
 
 
-@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1p", "tiny_d2", "tiny_d3", "c1", "c2_L5", "c5_L5"])
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1p", "tiny_d1_r2", "tiny_d2", "tiny_d2_r2", "tiny_d3", "c1",
+                                  "c2_L5", "c5_L5"])
 @pytest.mark.parametrize("launch", LAUNCHES,
                          ids=lambda l: f"{l[0]}{l[2] if l[0] == 'fused' else l[1]}{'x' if l[3] else ''}")
 def test_apply_launch_configs(dev, case, launch):
@@ -212,7 +222,7 @@ def _nodal_data(w, P, fn, j):
     return np.stack(rows)
 
 
-@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d2", "c1", "c2_L5"])
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1_r2", "tiny_d2", "tiny_d2_r2", "c1", "c2_L5"])
 def test_rhs_parity(dev, case):
     w, P, ops = _problem(case, CASES[case])
     j = 2
@@ -228,7 +238,7 @@ def test_rhs_parity(dev, case):
     assert _rel(b.cpu().numpy(), b_ref) <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d2", "c1"])
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1_r2", "tiny_d2", "tiny_d2_r2", "c1"])
 def test_ct_preconditioner_parity(dev, case):
     """CT with tightly solved grid problems equals the oracle's CT with direct solves."""
     from paper_2204_05988_amd import sgdg
@@ -253,7 +263,7 @@ def _fnorm(P, e):
     return np.sqrt(tot)
 
 
-@pytest.mark.parametrize("case", ["tiny_d2", "c1", "c2_L5", "c5_L5"])
+@pytest.mark.parametrize("case", ["tiny_d1_r2", "tiny_d2", "tiny_d2_r2", "c1", "c2_L5", "c5_L5"])
 def test_solve_strip_parity(dev, case):
     from paper_2204_05988_amd import sgdg
     w, P, ops = _problem(case, CASES[case])
@@ -309,7 +319,12 @@ def test_mixed_precision_solve(dev):
     dist = _fnorm(P, x32.cpu().numpy() - x64.cpu().numpy()) / _fnorm(P, x64.cpu().numpy())
     _say(f"  fp64: {st64.outer_iters} outer {st64.seconds:.3f}s; mixed: {st32.outer_iters} outer "
          f"{st32.refinement_steps} refinements {st32.seconds:.3f}s; oracle residual {res:.2e}, L2 dist {dist:.2e}")
-    assert res <= 1.5e-8
+    # the refinement loop stops on the FP64 residual ||b - A u|| / ||b|| computed on
+    # the device with the FP64 apply, which equals the oracle's operator to ~1e-14,
+    # so the oracle sees the same 1e-8
+    assert res <= 1e-8 * (1 + 1e-6)
+    # both solutions are within 1e-8 residual of the same function (measured 3e-10)
+    assert dist <= 1e-8
 
 
 def test_nan_residual_is_reported(dev):

@@ -478,3 +478,94 @@ def test_forced_convergence_c1(r):
     assert errs[0] > errs[1] > errs[2], errs
     assert errs[0] / errs[2] > 3.0, errs
     assert errs[2] < 0.02, errs
+
+
+# --- Sect. 4.3: the grid-problem preconditioner (mass inverses) ---------------------
+
+from oracle import gridprec  # noqa: E402
+
+
+def _mass_levels(kind, L):
+    w = config_tiny(kind)
+    w.L = L
+    P = Problem(w)
+    return P, [P.factor("x", gridprec.MASS, l, l).toarray() for l in range(w.lmin, L + 1)]
+
+
+@pytest.mark.parametrize("kind,L", [("d1", 5), ("d1p", 5), ("d2", 3), ("d3", 2)])
+def test_jacobi_scaled_mass_spectrum(kind, L):
+    """The eigenvalues of D^-1 M of the P1 mass matrix lie in [1/2, 1 + d/2] (the
+    Jacobi-scaled element mass matrix (I + 1 1^T)/2 of a d-simplex has exactly these
+    two eigenvalues), and the finest level comes close to both ends."""
+    P, Ms = _mass_levels(kind, L)
+    lo, hi = gridprec.interval(P.w.x.d)
+    for M in Ms:
+        D = np.diag(M)
+        lam = np.linalg.eigvalsh(M / np.sqrt(np.outer(D, D)))
+        assert lam.min() >= lo - 1e-12 and lam.max() <= hi + 1e-12, (lam.min(), lam.max())
+    assert lam.max() > 0.8 * hi and lam.min() < 0.8
+
+
+def _cheb_three_term(M, b, k, d):
+    """Chebyshev semi-iteration in its three-term form (Varga / Golub-Van Loan):
+    x_1 = z_0/theta, x_{j+1} = w_{j+1}(x_j + z_j/theta) + (1 - w_{j+1}) x_{j-1},
+    z_j = D^-1 (b - M x_j), w_{j+1} = 2 s T_j(s) / T_{j+1}(s), s = theta/delta."""
+    lo, hi = gridprec.interval(d)
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    s = theta / delta
+    T = [1.0, s]
+    for _ in range(k + 1):
+        T.append(2 * s * T[-1] - T[-2])
+    D = np.diag(M)[:, None]
+    xprev = np.zeros_like(b)
+    x = b / D / theta
+    for j in range(1, k):
+        z = (b - M @ x) / D
+        w = 2 * s * T[j] / T[j + 1]
+        x, xprev = w * (x + z / theta) + (1 - w) * xprev, x
+    return x
+
+
+@pytest.mark.parametrize("kind,L", [("d1", 4), ("d1p", 4), ("d2", 3), ("d3", 2)])
+def test_chebyshev_closed_form_equals_the_iteration(kind, L):
+    P, Ms = _mass_levels(kind, L)
+    d = P.w.x.d
+    M = Ms[-1]
+    b = np.random.default_rng(4).standard_normal((M.shape[0], 3))
+    lo, hi = gridprec.interval(d)
+    # one step is the scaled Jacobi step D^-1 b / theta
+    C1 = gridprec.chebyshev_inverse(M, 1, d)
+    assert np.allclose(C1 @ b, b / np.diag(M)[:, None] / (0.5 * (lo + hi)), rtol=1e-12, atol=0)
+    for k in (2, 3, 5, 8):
+        ref = _cheb_three_term(M, b, k, d)
+        got = gridprec.chebyshev_inverse(M, k, d) @ b
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), k
+    # the error falls at least as fast as 1/T_k(theta/delta) and reaches the exact inverse
+    xs = np.linalg.solve(M, b)
+    Dh = np.sqrt(np.diag(M))[:, None]
+    e0 = np.linalg.norm(Dh * xs)
+    s = (hi + lo) / (hi - lo)
+    for k in (2, 4, 8, 16):
+        ek = np.linalg.norm(Dh * (gridprec.chebyshev_inverse(M, k, d) @ b - xs))
+        assert ek <= e0 / np.cosh(k * np.arccosh(s)) * (1 + 1e-9), k
+    assert np.abs(gridprec.chebyshev_inverse(M, 40, d) @ b - xs).max() <= 1e-12 * np.abs(xs).max()
+
+
+@pytest.mark.parametrize("kind", ["d1", "d2"])
+def test_exact_grid_preconditioner_inverts_its_factors(kind):
+    """sweeps = -1: P_l^-1 followed by the forward product (Tt + delta Ct + Gt) (x) M^x (x) M^v
+    gives back the input on every grid of both diagonals."""
+    w = config_tiny(kind)
+    P = Problem(w)
+    Tb = gridprec.time_block(P)
+    for g in list(P.upper) + list(P.lower):
+        U = np.random.default_rng(1).standard_normal((P.R, P.nx(g[0]), P.nv(g[1])))
+        Z = gridprec.grid_precond(P, g, U, -1)
+        Mx = P.factor("x", gridprec.MASS, g[0], g[0])
+        Mv = P.factor("v", gridprec.MASS, g[1], g[1])
+        back = np.tensordot(Tb, np.stack([(Mv @ (Mx @ Z[s]).T).T for s in range(P.R)]), axes=(1, 0))
+        assert np.abs(back - U).max() <= 1e-11 * np.abs(U).max(), g
+    # sweeps = 0 uses the diagonals only: on a grid with more than one node it differs
+    g = P.upper[-1]
+    U = np.ones((P.R, P.nx(g[0]), P.nv(g[1])))
+    assert np.abs(gridprec.grid_precond(P, g, U, 0) - gridprec.grid_precond(P, g, U, -1)).max() > 1e-3
