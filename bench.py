@@ -3,28 +3,43 @@
 One step = one application of the full strip operator A^(delta) (all blocks
 A_{l,l'} of every component-grid pair: per-grid Kronecker sweeps, cross-grid
 level scans with the embedding matrices, term accumulation) to a batch of
-synthetic input vectors already resident in HBM.  Workload: the 4D phase-space
-problem (d=2, r=1, sparse-grid level 7, 620 892 space-time DOFs per vector).
+synthetic input vectors already resident in HBM.  Workload (default): the 4D
+phase-space problem (d=2, r=1, sparse-grid level 7, 620 892 space-time DOFs per
+vector), 64 vectors (u and y, 636 MB in FP64, exceed the 256 MB MALL).
 
-Prints one JSON line (rank 0).  Also reports, beside the headline number:
-  * strip_solve: the first strip of that problem solved to 1e-8 in FP64 and in
-    mixed precision (FP32 inner, FP64 refinement);
+Prints one JSON line.  Beside the headline number:
+  * timing: bracketed mean, per-step median and 10th/90th percentiles, and a
+    cold run (a 512 MiB buffer written before each application);
+  * roofline (the longest launch group) and roofline_apply (the whole
+    application): algorithmic flops and compulsory bytes (u read, y written)
+    against the FP64 vector and HBM peaks, frac = t_bound / t_measured;
+  * apply_c2_legs: 1, 16 and 64 vectors in FP64, 1 and 64 in FP32;
+  * strip_solve: the first strip of that problem solved to 1e-8 in FP64 and
+    in mixed precision (FP32 inner, FP64 refinement), eagerly and with the
+    grid-problem GMRES cycles replayed from captured graphs, with the Sect. 4.3
+    Chebyshev mass inverses, and with inexact grid solves; strip_solve_small:
+    strip 1 of the 4D problems at level 5 (the sizes the CPU oracle is timed on);
   * learned: the 4D Vlasov-type step (x periodic, frozen random E(x), L=7,
     r=0): (r, P_CT r) pairs recorded from CT-preconditioned solves of strips
     1-8, the per-grid networks trained on them, then strips 9-10 solved to 1e-8
-    with CT, with the learned preconditioner, and learned + mixed precision,
-    and again with inexact CT grid solves (10 GMRES iterations) as CT and as
-    the learned preconditioner's fallback, in FP64 and in mixed precision;
-    its "network" entry is the forward rate of the trained network against
-    the HBM roofline, with its matrix-core utilisation (--network-only: that
-    rate alone, freshly initialised);
+    with CT, with the learned preconditioner, learned + mixed precision, and
+    with inexact CT grid solves as CT and as the learned preconditioner's
+    fallback; its "network" entry is the forward rate of the trained network
+    with its matrix-core utilisation (--network-only: that rate alone);
+  * batched_learned: four such problems (different fields), each with its own
+    networks, solved in one batch with learned + mixed precision against the
+    plain FP64 method one problem at a time;
   * batched: independent 4D problems with levels drawn from {5,6,7}, applied
     and solved in lockstep (FP32 applies inside FP64 refinement) against the
     same problems solved one at a time in plain FP64;
-  * apply_6d: the 6D phase-space problem (d=3, L=6) applied in FP64 and FP32;
+  * apply_6d: the 6D phase-space problem (d=3, L=6) applied to 1 and 8
+    vectors in FP64 and 1 in FP32;
   * apply_2d: the 2D phase-space problem (d=1, L=6) applied to a batch, and
     its 8-strip march with CT-preconditioned FGMRES to 1e-10;
-  * cpu_baseline: the CPU oracle timed on a bounded sample.
+  * vlasov_poisson: Landau damping in 1+1 and 2+2 dimensions with the
+    per-strip fixed point of transport and field;
+  * cpu_baseline: the CPU oracle timed on the host cores (one core and a
+    process pool over all of them) on a bounded sample.
 """
 import argparse
 import json
@@ -48,7 +63,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="operator of the timed apply: the 4D problem (default) or the 6D one")
     ap.add_argument("--level", type=int, default=7)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-solve", action="store_true")
@@ -60,7 +77,10 @@ def parse():
     ap.add_argument("--network-only", action="store_true",
                     help="learned leg reduced to the network's forward rate (freshly initialised weights)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
+    ap.add_argument("--no-vp", action="store_true", help="skip the Vlasov-Poisson leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--cold", type=int, default=10, help="cold-cache repetitions of the headline apply")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other batch sizes and dtypes of the 4D apply")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed loop, copy a 512 MiB buffer once (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -95,8 +115,25 @@ def kernel_work(ops, B, R, elem_bytes):
     nt, nvg, nxg = info["nterms"], info["nvg"], info["nxg"]
     d = ops.w.d
     S = {1: 3, 2: 7, 3: 15}[d]
+    Wd = {1: 5, 2: 19, 3: 65}[d]
     n = len(ops.upper)
-    work = {k: [0.0, 0.0] for k in ("vstage", "ustage", "xstage", "fused")}
+    work = {k: [0.0, 0.0] for k in ("vstage", "ustage", "xstage", "fused", "scan")}
+    # level scans (counted densely, every group at every lower point), per vector:
+    # step t builds the partner sums of lower grid t (v-factor side) and of lower grid
+    # nlow-1-t (x-factor side), R (2W + 4) flops per target point and group (the
+    # restricted W-point stencil plus the two-parent recursion); the restriction
+    # before step t >= 1 maps each group's previous array, R 2S flops per point.
+    low = ops.lower
+    nlow = len(low)
+    pts = [nx * nv for _, _, nx, nv in low]
+    for t in range(n - 1):
+        for ng, lg in ((nvg, t), (nxg, nlow - 1 - t)):
+            work["scan"][0] += B * pts[lg] * ng * R * (2 * Wd + 4)
+            work["scan"][1] += B * pts[lg] * ng * R * elem_bytes      # the partner array written
+            if t >= 1:
+                rl = low[lg - 1][2] * low[lg][3] if lg == t else low[lg][2] * low[lg + 1][3]
+                work["scan"][0] += B * rl * ng * R * 2 * S
+                work["scan"][1] += B * rl * ng * R * elem_bytes
     for gi, (lx, _, nx, nv) in enumerate(ops.upper):
         pts = nx * nv * B
         hp, hq = gi > 0, gi + 1 < n
@@ -142,15 +179,122 @@ def recorded_traffic(kernel, workload_tag):
 
 
 def roofline(fl, by, ms, valu_peak):
+    """Roofline position of a launch (or of a whole application) from its
+    algorithmic flops `fl` and compulsory HBM bytes `by` in `ms` milliseconds:
+    the bound is the larger of the two times at peak (VALU or HBM), and
+    frac = t_bound / t_measured."""
     t_hbm = by / (HBM_PEAK_GBS * 1e9)
     t_alu = fl / (valu_peak * 1e12)
-    if t_alu > t_hbm:
-        ach = fl / (ms * 1e-3) / 1e12
+    t = ms * 1e-3
+    if t_alu >= t_hbm:
+        ach = fl / t / 1e12
         return {"bound": "alu", "achieved": round(ach, 3), "peak": valu_peak, "unit": "TFLOP/s",
-                "frac": round(ach / valu_peak, 4)}
-    ach = by / (ms * 1e-3) / 1e9
+                "frac": round(t_alu / t, 4), "hbm_frac_compulsory": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+    ach = by / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4)}
+            "frac": round(t_hbm / t, 4), "alu_frac": round(fl / t / 1e12 / valu_peak, 4)}
+
+
+SLOTS = {"scan": 0, "fused": 1, "vstage": 3, "ustage": 4, "xstage": 5}
+
+
+def measure_apply(ops, B, dtname, steps, warmup, tune=True, cold=0, dev=None):
+    """Times `steps` applications of the full operator to B vectors already in HBM.
+
+    Returns the bracketed mean (events around all steps), the per-step median and
+    10th/90th percentiles (events around each step), the per-kernel event times
+    of the library (sgdg_profile, on the launching stream) and, with cold > 0,
+    `cold` more steps each preceded by writing a 512 MiB buffer (the MALL holds
+    256 MiB, so u, y and the tables come from HBM again)."""
+    import torch
+    from workloads import random_vector
+    dt = torch.float64 if dtname == "f64" else torch.float32
+    u = torch.tensor(random_vector(ops.ndof, 0, batch=B), device=dev, dtype=dt)
+    y = torch.empty_like(u)
+    stream = torch.cuda.current_stream()
+    tuned = ops.tune(dtname, batch=B, reps=3) if tune else None
+    for _ in range(warmup):
+        ops.apply(u, y, batch=B)
+    torch.cuda.synchronize()
+    ops.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        ops.apply(u, y, batch=B)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    prof = {name: ops.profile_read(slot) for name, slot in SLOTS.items()}
+    prof = {k: v for k, v in prof.items() if v[1] > 0}
+    ops.profile(False)
+    per = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ops.apply(u, y, batch=B)
+        b.record(stream)
+        b.synchronize()
+        per.append(a.elapsed_time(b))
+    out = {"batch": B, "dtype": dtname, "ms_mean": round(ms, 4), "ms_median": round(float(np.median(per)), 4),
+           "ms_p10": round(float(np.percentile(per, 10)), 4), "ms_p90": round(float(np.percentile(per, 90)), 4),
+           "dof_applies_per_s": B * ops.ndof / (ms * 1e-3), "launch_config": tuned, "wall_s": round(wall, 3),
+           "kernel_ms_per_step": {k: round(v[0] / v[1] * (v[1] / steps), 4) for k, v in prof.items()}}
+    if cold:
+        junk = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)
+        cms = []
+        for _ in range(cold):
+            junk.fill_(1.0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ops.apply(u, y, batch=B)
+            b.record(stream)
+            b.synchronize()
+            cms.append(a.elapsed_time(b))
+        out["cold"] = {"ms_median": round(float(np.median(cms)), 4), "ms_p10": round(float(np.percentile(cms, 10)), 4),
+                       "ms_p90": round(float(np.percentile(cms, 90)), 4), "reps": cold,
+                       "dof_applies_per_s": B * ops.ndof / (float(np.median(cms)) * 1e-3),
+                       "note": "each application preceded by writing a 512 MiB buffer"}
+        del junk
+    return out, prof, tuned
+
+
+def roofline_report(ops, B, dtname, prof, ms_step, tuned):
+    """Per-kernel and whole-application roofline positions.
+
+    Flops are the algorithmic counts of kernel_work.  Compulsory HBM bytes are
+    those any implementation must move: u read once and y written once (the
+    v-stage's u read and the last pass's y write); the design's own staged
+    arrays (W between the passes, the partner scan arrays) are reported beside
+    them as `bytes_staged`, not as algorithmic bytes."""
+    R = ops.R
+    elem = 8 if dtname == "f64" else 4
+    valu_peak = FP64_VALU_PEAK_TFLOPS if dtname == "f64" else FP32_VALU_PEAK_TFLOPS
+    work = kernel_work(ops, B, R, elem)
+    io = B * ops.ndof * elem
+    fused = tuned is not None and tuned.get("variant") == "fused"
+    comp = {"vstage": io, "xstage": io, "ustage": 0, "scan": 0, "fused": 2 * io}
+    per = {}
+    for k, (tot, cnt) in prof.items():
+        if k in work and cnt > 0:
+            kms = tot / cnt
+            # one event pair per launch group and application: the level scans are
+            # 2 (grids - 1) - 1 launches of k_scan2, the other passes one launch each
+            per[k] = dict(roofline(work[k][0], comp[k], kms, valu_peak), kernel_ms=round(kms, 4),
+                          launches_in_group=2 * (len(ops.upper) - 1) - 1 if k == "scan" else 1,
+                          flops=work[k][0], bytes_compulsory=comp[k], bytes_staged=work[k][1])
+    kname = {k: "k_" + k for k in per}
+    if "scan" in kname:
+        kname["scan"] = "k_scan2"
+    if tuned is not None and tuned.get("variant") == "split_tiled" and "xstage" in kname:
+        kname["xstage"] = "k_xtile"
+    used = ["scan", "fused"] if fused else ["scan", "vstage", "ustage", "xstage"]
+    fl = sum(work[k][0] for k in used if k in work)
+    whole = dict(roofline(fl, 2 * io, ms_step, valu_peak), ms=round(ms_step, 4), flops=fl,
+                 flops_per_dof=round(fl / (B * ops.ndof), 1), bytes_compulsory=2 * io,
+                 bytes_per_dof=2 * elem)
+    return per, kname, whole
 
 
 def main():
@@ -161,71 +305,48 @@ def main():
         sys.exit(2)
     import torch
     from paper_2204_05988_amd import sgdg
-    from workloads import config_c2, random_vector
+    from workloads import config_c2
 
     dev = torch.device("cuda:0")
-    w = config_c2(L=a.level)
+    if a.workload == "c3":
+        from workloads import config_c3
+        w = config_c3(L=a.level if a.level != 7 else 6)
+        wname = f"6D phase space d=3, r=0, sparse grid L={w.L} (c3), full SD-DG operator"
+    else:
+        w = config_c2(L=a.level)
+        wname = f"4D phase space d=2, r=1, sparse grid L={a.level} (c2), full SD-DG operator"
     ops = sgdg.SparseGridOps(w)
-    R = w.r + 1
     B = a.batch
-    dt = torch.float64 if a.dtype == "f64" else torch.float32
-    u = torch.tensor(random_vector(ops.ndof, 0, batch=B), device=dev, dtype=dt)
-    y = torch.empty_like(u)
-    stream = torch.cuda.current_stream()
-    tuned = None if a.no_tune else ops.tune(a.dtype, batch=B, reps=3)
+    res, prof, tuned = measure_apply(ops, B, a.dtype, a.steps, a.warmup, tune=not a.no_tune, cold=a.cold, dev=dev)
     if tuned is not None:
         _log(f"launch configuration: {tuned}")
-    for _ in range(a.warmup):
-        ops.apply(u, y, batch=B)
-    torch.cuda.synchronize()
-    ops.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(a.steps):
-        ops.apply(u, y, batch=B)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    slots = {"scan": 0, "fused": 1, "vstage": 3, "ustage": 4, "xstage": 5}
-    prof = {name: ops.profile_read(slot) for name, slot in slots.items()}
-    prof = {k: v for k, v in prof.items() if v[1] > 0}
-    ops.profile(False)
-    ms_step = ms / a.steps
-    value = B * ops.ndof / (ms_step * 1e-3)
-    valu_peak = FP64_VALU_PEAK_TFLOPS if a.dtype == "f64" else FP32_VALU_PEAK_TFLOPS
-    work = kernel_work(ops, B, R, 8 if a.dtype == "f64" else 4)
-    per_kernel = {}
-    for k, (tot, cnt) in prof.items():
-        if k in work and cnt > 0:
-            kms = tot / cnt
-            per_kernel[k] = dict(roofline(work[k][0], work[k][1], kms, valu_peak), kernel_ms=round(kms, 4),
-                                 flops=work[k][0], bytes=work[k][1])
-    # the x-stage slot times the tiled kernel when the tuner picked it
-    kname = {k: "k_" + k for k in per_kernel}
-    if tuned is not None and tuned.get("variant") == "split_tiled" and "xstage" in kname:
-        kname["xstage"] = "k_xtile"
+    ms_step = res["ms_mean"]
+    value = res["dof_applies_per_s"]
+    per_kernel, kname, whole = roofline_report(ops, B, a.dtype, prof, ms_step, tuned)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["kernel_ms"])
     roof = dict(per_kernel[dom])
     roof["kernel"] = kname[dom]
-    tag = f"c2_L{a.level}_B{B}_{a.dtype}"
+    tag = f"{a.workload}_L{w.L}_B{B}_{a.dtype}"
     roof["traffic"] = recorded_traffic(kname[dom], tag)
     out = {
         "metric": "DOF-applies/s", "value": value, "unit": "DOF-applies/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": a.dtype, "data": "synthetic",
-        "config": {"workload": f"4D phase space d=2, r=1, sparse grid L={a.level} (c2), full SD-DG operator",
+        "config": {"workload": wname,
                    "dofs_per_vector": ops.ndof, "batch": B, "grids": len(ops.upper)},
-        "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items()},
+        "timing": {k: res[k] for k in ("ms_mean", "ms_median", "ms_p10", "ms_p90") if k in res},
+        "kernel_ms_per_step": res["kernel_ms_per_step"],
         "launch_config": tuned,
         "dominant_kernel": kname[dom],
         "kernel_names": kname,
         "roofline": roof,
+        "roofline_apply": whole,
         "kernels": per_kernel,
-        "wall_s": round(wall, 3),
+        "wall_s": res["wall_s"],
     }
-    _log(f"apply: {value:.3e} DOF-applies/s")
+    if "cold" in res:
+        out["timing"]["cold"] = res["cold"]
+    _log(f"apply: {value:.3e} DOF-applies/s, {ms_step:.4f} ms; whole-apply roofline {whole}")
     if a.calib_copy:
         src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -233,21 +354,46 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         _log("calibration copy: 512 MiB read + 512 MiB written")
+    if not a.no_legs:
+        legs = {}
+        combos = ((1, "f64"), (16, "f64"), (64, "f64"), (1, "f32"), (64, "f32")) if a.workload == "c2" else \
+            ((1, "f64"), (8, "f64"), (1, "f32"))
+        for Bl, dtl in combos:
+            if Bl == B and dtl == a.dtype:
+                continue
+            r, p, t = measure_apply(ops, Bl, dtl, max(5, a.steps // 2), 2, tune=not a.no_tune, cold=5, dev=dev)
+            pk, kn, wh = roofline_report(ops, Bl, dtl, p, r["ms_mean"], t)
+            r["roofline_apply"] = wh
+            r["kernels"] = {kn[k]: {"kernel_ms": v["kernel_ms"], "frac": v["frac"], "bound": v["bound"]}
+                            for k, v in pk.items()}
+            legs[f"{a.workload}_B{Bl}_{dtl}"] = r
+            _log(f"{a.workload} leg B={Bl} {dtl}: {r['dof_applies_per_s']:.3e} DOF-applies/s, {r['ms_median']} ms median")
+        out[f"apply_{a.workload}_legs"] = legs
+    ops.close()
+    gpu_strips = {}
     if not a.no_solve:
+        ops = sgdg.SparseGridOps(w)
         out["strip_solve"] = solve_times(ops, w, dev)
+        ops.close()
         _log(f"strip solves: {out['strip_solve']}")
+        out["strip_solve_small"] = small_strips(dev)
+        gpu_strips = {k: v["seconds"] for k, v in out["strip_solve_small"].items()}
     if a.network_only:
         out["network"] = network_leg(dev)
     elif not a.no_learned:
         out["learned"] = learned_leg(dev, a.train_steps)
+        out["batched_learned"] = batched_learned_leg(dev)
     if a.batched > 0:
         out["batched"] = batched_leg(dev, a.batched)
+    if not a.no_vp:
+        out["vlasov_poisson"] = vlasov_poisson_leg(dev)
     if a.c3_level > 0:
         out["apply_6d"] = apply_6d_leg(dev, a.c3_level)
     if not a.no_2d:
         out["apply_2d"] = apply_2d_leg(dev)
+        gpu_strips.setdefault("c1_march", out["apply_2d"]["march"]["seconds"])
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, value)
+        out["cpu_baseline"] = cpu_baseline(w, value, gpu_strips)
     print(json.dumps(out), flush=True)
 
 
@@ -276,19 +422,65 @@ def solve_times(ops, w, dev):
     b = ops.rhs(u0, 1, nodal(w.f), nodal(w.g))
     res = {}
     # grid problems to 1e-8 (at most 200 GMRES iterations), and inexact (10 iterations each)
-    for name, mixed, cap in (("fp64", False, 200), ("mixed_fp32", True, 200),
-                             ("fp64_inexact_ct", False, 10), ("mixed_fp32_inexact_ct", True, 10)):
+    # (grid preconditioner: mass diagonals, or 4 Chebyshev-Jacobi steps per mass factor;
+    # graph: grid-problem GMRES cycles replayed from captured graphs, captured by a
+    # preceding untimed solve)
+    for name, mixed, cap, sweeps, graph in (("fp64", False, 200, 0, False), ("mixed_fp32", True, 200, 0, False),
+                                            ("fp64_graph", False, 200, 0, True), ("mixed_fp32_graph", True, 200, 0, True),
+                                            ("fp64_mass_cheb4", False, 200, 4, False),
+                                            ("fp64_inexact_ct", False, 10, 0, False),
+                                            ("mixed_fp32_inexact_ct", True, 10, 0, False)):
+        opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=mixed, use_graph=graph,
+                                       pc=sgdg.default_precond_opts(inner_maxit=cap, mass_sweeps=sweeps))
+        if graph:
+            ops.solve_strip(b, torch.zeros_like(b), opts, raise_on_noconv=False)
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=mixed,
-                                       pc=sgdg.default_precond_opts(inner_maxit=cap))
         x, st = ops.solve_strip(b, x, opts, raise_on_noconv=False)
         torch.cuda.synchronize()
         res[name] = {"seconds": round(time.perf_counter() - t0, 4), "outer_iters": st.outer_iters,
                      "inner_iters": st.inner_iters_total, "rel_residual": st.rel_residual,
                      "refinements": st.refinement_steps}
     return res
+
+
+def _strip1_rhs(ops, w, dev):
+    """b_1 on the device: U_0 the sparse-grid interpolant of u0, data f and g sampled
+    at the strip's Gauss points (zero where the workload has none)."""
+    import torch
+    from workloads import gauss_legendre_times, sample_on_grids
+    u0 = _interp_u0(ops, w, dev)
+    tq, _ = gauss_legendre_times(0.0, w.dt, w.r + 2)
+
+    def nodal(fn):
+        if fn is None:
+            return None
+        return torch.tensor(np.stack([np.concatenate([sample_on_grids(w, _grids(ops.upper), fn, t),
+                                                      sample_on_grids(w, _grids(ops.lower), fn, t)]) for t in tq]),
+                            device=dev)
+
+    return ops.rhs(u0, 1, nodal(w.f), nodal(w.g))
+
+
+def small_strips(dev):
+    """Strip 1 of the 4D problems at L = 5 (the sizes the CPU oracle is timed on),
+    FP64 with the combination technique to 1e-8, eager and with the grid-problem
+    GMRES cycles replayed from captured graphs."""
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c2, config_c5
+    out = {}
+    for name, w in (("c2_L5_strip1", config_c2(L=5)), ("c5_L5_strip1", config_c5(L=5))):
+        ops = sgdg.SparseGridOps(w)
+        b = _strip1_rhs(ops, w, dev)
+        _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400))     # first use builds tables
+        _, r = _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400))
+        _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400, use_graph=True))   # captures
+        _, rg = _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400, use_graph=True))
+        out[name] = dict(r, dofs=ops.ndof, graph=rg)
+        _log(f"small strip {name}: {out[name]}")
+        ops.close()
+    return out
 
 
 def _interp_u0(ops, w, dev):
@@ -373,6 +565,116 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
     return out
 
 
+def batched_learned_leg(dev, n=4, L=7, record_strips=8, train_steps=500):
+    """Batched + learned + mixed precision against the plain FP64 method.
+
+    n Vlasov-type problems (seeds 0..n-1: different fields E), each with its own
+    networks trained on pairs recorded from its own CT-preconditioned solves of
+    strips 1..record_strips; strip record_strips + 1 of every problem is then
+    solved to 1e-8 (a) one problem at a time in FP64 with the combination
+    technique, the plain method, and (b) all problems in one batch with the
+    learned preconditioner, FP32 inner solves and FP64 refinement, once with
+    the exact combination technique as the fallback and once with the inexact
+    one (10 GMRES iterations per grid problem)."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_c5
+    probs = []
+    t0 = time.perf_counter()
+    for seed in range(n):
+        w = config_c5(seed=seed, L=L)
+        ops = sgdg.SparseGridOps(w)
+        net = sgdg.LearnedPreconditioner(ops, seed=seed)
+        u = _interp_u0(ops, w, dev)
+        net.record(4096)
+        for j in range(1, record_strips + 1):
+            b = ops.rhs(u, 1)
+            u, _ = _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400))
+        net.record(0)
+        ts = net.train(train_steps, batch=8, lr=1e-3, seed=1)
+        probs.append((w, ops, net, ops.rhs(u, 1), ts))
+    prep = time.perf_counter() - t0
+    out = {"workload": f"{n} Vlasov-type 4D problems (c5 fields, seeds 0..{n - 1}), L={L}, strip {record_strips + 1}",
+           "problems": n, "dofs_total": sum(p[1].ndof for p in probs), "prep_s": round(prep, 2),
+           "train": [{"pairs": p[2].pair_count(), "loss_first": p[4].loss_first, "loss_last": p[4].loss_last,
+                      "seconds": round(p[4].seconds, 2)} for p in probs]}
+    seq, worst = 0.0, 0.0
+    for w, ops, net, b, _ in probs:
+        _, r = _timed_solve(ops, b, sgdg.default_solve_opts(rtol=1e-8, maxit=400))
+        seq += r["seconds"]
+        worst = max(worst, r["rel_residual"])
+    out["plain_fp64_one_at_a_time"] = {"seconds": round(seq, 4), "max_rel_residual": worst}
+    batch = sgdg.SparseGridBatch([p[1] for p in probs])
+    batch.set_networks([p[2] for p in probs])
+    bt = torch.cat([p[3] for p in probs])
+    for name, cap in (("batched_learned_mixed", 200), ("batched_learned_mixed_inexact_fallback", 10)):
+        opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                       pc=sgdg.default_precond_opts(net=probs[0][2], inner_maxit=cap))
+        batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)   # first use builds the batch tables
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, st = batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out[name] = {"seconds": round(el, 4), "outer_iters": st.outer_iters, "refinements": st.refinement_steps,
+                     "fallback": st.fallback_used, "pc_applications": st.pc_applications,
+                     "max_rel_residual": st.rel_residual, "speedup_vs_plain_fp64": round(seq / el, 3)}
+        _log(f"batched learned leg: {name} {out[name]}")
+    opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True)
+    batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st = batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    out["batched_ct_mixed"] = {"seconds": round(el, 4), "outer_iters": st.outer_iters,
+                               "max_rel_residual": st.rel_residual, "speedup_vs_plain_fp64": round(seq / el, 3)}
+    _log(f"batched learned leg: {out}")
+    batch.close()
+    for p in probs:
+        p[2].close()
+        p[1].close()
+    return out
+
+
+def vlasov_poisson_leg(dev, runs=((1, 5, 20), (2, 5, 3))):
+    """Landau damping (Sect. 5.3 setting: alpha = 0.01, k = 1/2, (0, 4 pi)^d x (-6, 6)^d,
+    0.5 time units per strip, r = 1): (d, paper level, strips) per run; the per-strip
+    fixed point of transport and field on the device, with its electric energy."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_landau
+    out = {}
+    for d, pl, nst in runs:
+        w = config_landau(d, pl)
+        ops = sgdg.SparseGridOps(w)
+        f = _interp_u0(ops, w, dev)
+        ops.close()
+        vp = sgdg.VlasovPoisson(w)
+        E, en = vp.field(vp.density(f, 1))
+        prev = 1
+        energies, fps, secs, asm, outer = [en], [], [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(nst):
+            f, _, st = vp.strip(f, prev, E, fp_tol=1e-6, raise_on_noconv=False)
+            prev = w.r + 1
+            E, en = vp.field(vp.density(f, prev, 1.0))
+            energies.append(en)
+            fps.append(st.fp_iters)
+            secs.append(round(st.seconds, 4))
+            asm.append(round(st.assemble_seconds, 4))
+            outer.append(st.outer_iters)
+        total = time.perf_counter() - t0
+        key = f"landau_{d}d{d}v_paper_level{pl}"
+        out[key] = {"dofs": vp.ndof, "x_nodes": vp.n_fine, "strips": nst, "seconds": round(total, 3),
+                    "fixed_point_iters": fps, "fgmres_iters": outer, "strip_seconds": secs,
+                    "assemble_seconds": asm, "electric_energy": energies}
+        _log(f"vlasov-poisson {key}: {nst} strips in {total:.2f}s, fixed point {fps}")
+        vp.close()
+    return out
+
+
 def network_leg(dev, L=7):
     from paper_2204_05988_amd import sgdg
     from workloads import config_c5
@@ -421,10 +723,10 @@ def network_rate(net, ops, dev, reps=20):
 
 
 def apply_6d_leg(dev, L, steps=5):
-    """Operator-apply throughput of the 6D phase-space problem (d=3, r=0), one vector, FP64 and FP32."""
-    import torch
+    """Operator-apply throughput of the 6D phase-space problem (d=3, r=0): one and
+    eight vectors in FP64, one in FP32, each with its whole-apply roofline."""
     from paper_2204_05988_amd import sgdg
-    from workloads import config_c3, random_vector
+    from workloads import config_c3
     w = config_c3(L=L)
     t0 = time.perf_counter()
     ops = sgdg.SparseGridOps(w)
@@ -432,19 +734,15 @@ def apply_6d_leg(dev, L, steps=5):
     _log(f"6d leg: L={L}, {ops.ndof} DOFs, assembled in {setup:.1f}s")
     out = {"workload": f"6D phase space d=3, r=0, sparse grid L={L} (c3), full SD-DG operator", "dofs": ops.ndof,
            "grids": len(ops.upper), "setup_s": round(setup, 2)}
-    u64 = torch.tensor(random_vector(ops.ndof, 0)[0], device=dev)
-    for name, u in (("f64", u64), ("f32", u64.float())):
-        tuned = ops.tune(name, batch=1, reps=2)
-        y = torch.empty_like(u)
-        ops.apply(u, y)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ops.apply(u, y)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / steps
-        out[name] = {"ms": round(el * 1e3, 3), "dof_applies_per_s": ops.ndof / el, "launch_config": tuned}
-        _log(f"6d leg: {name} {out[name]}")
+    for B, dt in ((1, "f64"), (8, "f64"), (1, "f32")):
+        r, p, t = measure_apply(ops, B, dt, steps, 1, tune=True, cold=3, dev=dev)
+        pk, kn, wh = roofline_report(ops, B, dt, p, r["ms_mean"], t)
+        r["roofline_apply"] = wh
+        r["kernels"] = {kn[k]: {"kernel_ms": v["kernel_ms"], "frac": v["frac"], "bound": v["bound"]}
+                        for k, v in pk.items()}
+        out[f"B{B}_{dt}"] = r
+        _log(f"6d leg: B={B} {dt} {r['dof_applies_per_s']:.3e} DOF-applies/s, {r['ms_median']} ms median, "
+             f"roofline {wh['frac']}")
     ops.close()
     return out
 

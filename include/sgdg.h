@@ -249,11 +249,22 @@ sgdg_status sgdg_batch_layout(sgdg_batch b, int64_t* offsets);
  * tiled launch for the whole batch. */
 sgdg_status sgdg_batch_apply(sgdg_batch b, const void* u_dev, void* y_dev, sgdg_dtype t, hipStream_t s);
 /* Solves every problem's strip system in lockstep (FGMRES with the batched
- * combination-technique preconditioner; mixed precision as in
+ * combination-technique preconditioner, or the problems' networks for
+ * pc.kind = 1, see sgdg_batch_set_networks; mixed precision as in
  * sgdg_solve_strip).  st receives the totals and the largest relative
  * residual.  SGDG_E_NOCONV if any problem misses the tolerance. */
 sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
                              sgdg_solve_stats* st, hipStream_t s);
+/* Learned preconditioner for a batch: nets[i] (created with sgdg_net_create
+ * on problem i's handle, see below) stands in for the combination technique
+ * on problem i's slice of every batch vector.  A batch solve with pc.kind = 1
+ * then applies every problem's network (pc.net is not used), with the
+ * combination technique of the whole batch as the fallback, switched when the
+ * largest residual estimate over the problems fails the fallback rule.
+ * n = 0 removes them.  The networks must outlive their use by the batch.
+ * SGDG_E_ARG unless n is 0 or the batch size and every network belongs to the
+ * problem at its position. */
+sgdg_status sgdg_batch_set_networks(sgdg_batch b, const sgdg_net* nets, int n);
 void sgdg_batch_destroy(sgdg_batch b);
 
 /* ------------------------------------------------ learned preconditioner -- */
@@ -320,6 +331,66 @@ sgdg_status sgdg_net_forward(sgdg_net n, const float* x_dev, float* y_dev, hipSt
 sgdg_status sgdg_net_backward(sgdg_net n, const float* x_dev, const float* dy_dev, float* grad_dev, hipStream_t s);
 void sgdg_net_destroy(sgdg_net n);
 
+/* ------------------------------------------------ Vlasov-Poisson coupling -- */
+
+/* The nonlinear Vlasov-Poisson system of Sect. 5.3 for electrons in a
+ * neutralising background:
+ *     d_t f + v . grad_x f - E . grad_v f = 0,
+ *     -Laplace_x phi = 1 - rho,  rho(x) = int f(x, v) dv,  E = -grad_x phi,
+ * solved strip by strip with the fixed point of Sect. 5.3 (eq:E_f, eq:poisson):
+ * the transport with the field of the previous iterate, then the density of
+ * the new iterate at the strip's midpoint (the midpoint rule: the field is
+ * constant over the strip), then the field.  Discretisation of the field: P1
+ * elements on the finest x-lattice, K phi = M (1 - rho) with phi of mean zero,
+ * and E_i the L2 projection of -d_i phi (M E_i = -D_i phi).  The x-domain must
+ * be periodic, d = 1 or 2.  Fields are FP64 device arrays [d][n_fine], n_fine
+ * the nodes of the finest x-lattice (C order). */
+typedef struct sgdg_vp_s* sgdg_vp;
+
+typedef struct {
+  double fp_tol;          /* stop when max|E^(k+1) - E^(k)| + ||f^(k+1) - f^(k)||_L2 (midpoint) < fp_tol */
+  int max_fp;             /* fixed-point iterations per strip */
+  sgdg_solve_opts solve;  /* the transport solve of each iteration (pc.kind must be 0) */
+} sgdg_vp_opts;
+
+typedef struct {
+  int fp_iters;           /* fixed-point iterations taken */
+  int outer_iters;        /* FGMRES iterations over all transport solves */
+  int inner_iters;        /* grid-problem GMRES iterations over all transport solves */
+  double dE, df;          /* the last iteration's field and density changes */
+  double energy;          /* electric energy 1/2 int |E|^2 of the returned field */
+  double rel_residual;    /* relative residual of the last transport solve */
+  double seconds;         /* wall time of the call */
+  double assemble_seconds; /* host assembly of the transport operators (one per iteration) */
+} sgdg_vp_stats;
+
+/* Creates the coupling on the layout g (which must outlive it): dt is the
+ * strip length, delta the streamline-diffusion parameter of the transport.
+ * Host assembly of the finest-level field matrices and upload; SGDG_E_ARG
+ * unless x is periodic and d <= 2. */
+sgdg_status sgdg_vp_create(sgdg_grid g, double dt, double delta, sgdg_vp* out);
+/* n_fine (nodes of the finest x-lattice) and d; either may be NULL. */
+sgdg_status sgdg_vp_info(sgdg_vp p, int64_t* n_fine, int* d);
+/* rho_dev (FP64 n_fine) = int f dv on the finest x-lattice, f_dev a sparse-grid
+ * function (spanning coefficients) with nslices slices: the number of time
+ * slices, evaluated at reference time tau in [-1, 1] of the strip (1 = the
+ * strip's end), or 1 (a one-slice function such as U_0).  Queued on s. */
+sgdg_status sgdg_vp_density(sgdg_vp p, const double* f_dev, int nslices, double tau, double* rho_dev,
+                            hipStream_t s);
+/* E_dev (FP64 [d][n_fine]) = the field of the density rho_dev (conjugate
+ * gradients in one workgroup, relative tolerance 1e-14); *energy (if not NULL,
+ * which synchronises s) = 1/2 int |E|^2. */
+sgdg_status sgdg_vp_field(sgdg_vp p, const double* rho_dev, double* E_dev, double* energy, hipStream_t s);
+/* One strip of the fixed point: f_prev_dev the previous strip's solution
+ * (prev_slices slices) or U_0 (1 slice), E0_dev the field to start from (that
+ * of f_prev's end); returns the strip solution in f_dev (FP64 n_dof) and the
+ * last field in E_dev.  Each iteration assembles the transport operator of
+ * its field on the host.  SGDG_E_NOCONV (results and stats filled) if max_fp
+ * iterations do not reach fp_tol.  Synchronises s. */
+sgdg_status sgdg_vp_strip(sgdg_vp p, const double* f_prev_dev, int prev_slices, const double* E0_dev, double* f_dev,
+                          double* E_dev, const sgdg_vp_opts* o, sgdg_vp_stats* st, hipStream_t s);
+void sgdg_vp_destroy(sgdg_vp p);
+
 /* ------------------------------------------------------------- autotuner -- */
 
 /* Launch configuration of the operator application.  variant 0: split
@@ -336,6 +407,8 @@ typedef struct {
   int block_map;
   double ms;        /* measured time of one full application with this configuration */
   int from_cache;   /* 1 if taken from the tuning cache without measuring */
+  int scan_chunks;  /* blocks sharing the factor groups of a level-scan item (tuned for batches of
+                       at most 4 vectors, else 1); in sgdg_set_launch 0 keeps the current value */
 } sgdg_tune_result;
 
 /* Environment, read when a handle's (or batch's) application state is first
@@ -344,7 +417,8 @@ typedef struct {
  *   SGDG_SPLIT_BC       1, 2 or 4: initial vectors per thread (2; 1 for d = 3)
  *   SGDG_SPLIT_XCD      1: initial block map XCD-contiguous (0)
  *   SGDG_SPLIT_ORDER    1: split items ordered v-block first (0: x-node first)
- *   SGDG_SCAN_CHUNKS    n >= 1: blocks sharing the factor groups of a scan item (1)
+ *   SGDG_SCAN_CHUNKS    n >= 1: blocks sharing the factor groups of a scan item (1);
+ *                       0: chosen per launch from the launch's item count
  *   SGDG_TUNE_CACHE     path of the tuning cache (see sgdg_tune) */
 
 /* Times every candidate configuration of the full operator application for

@@ -33,11 +33,11 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from workloads import grid_levels, nodal_fields
+from workloads import grid_levels, lattice_coords, nodal_fields
 
 from .fe import assemble, weight_nodal
 from .mesh import Lattice, embedding_chain
-from .timedg import time_matrices
+from .timedg import time_matrices, time_quadrature
 
 W1 = (1.0, (), None)
 
@@ -58,16 +58,31 @@ def _cat(w1, w2):
 class Problem:
     """One strip's discrete operator for a workload (FP64, scipy.sparse)."""
 
-    def __init__(self, w):
+    def __init__(self, w, t0=0.0):
         self.w = w
         self.d = w.d
         self.R = w.r + 1
+        self.t0 = t0
         self.fx, self.fv = nodal_fields(w)
         self.upper, self.lower = grid_levels(w)
         self._E = {}
         self._fine = {}
         self._fac = {}
         self.Mt, self.Tt, self.Ct, self.Gt = time_matrices(w.r, w.dt)
+        self.tq = None
+        if w.tfields is not None:
+            # coefficients that depend on time: the fields at the quadrature points of
+            # the strip [t0, t0 + dt], registered as "name@mu"
+            m = w.tquad if w.tquad else w.r + 2
+            self.tq = time_quadrature(w.r, w.dt, m)
+            X = lattice_coords(w.x, w.L)
+            V = lattice_coords(w.v, w.L)
+            for mu, tau in enumerate(self.tq["tau"]):
+                xf, vf = w.tfields(t0 + 0.5 * w.dt * (tau + 1.0))
+                for k, fn in xf.items():
+                    self.fx[f"{k}@{mu}"] = np.ascontiguousarray(fn(X), dtype=np.float64)
+                for k, fn in vf.items():
+                    self.fv[f"{k}@{mu}"] = np.ascontiguousarray(fn(V), dtype=np.float64)
         self.terms = self.build_terms()
         self.sizes = [self.nx(lx) * self.nv(lv) for lx, lv in self.upper]
         self.offsets = np.concatenate([[0], np.cumsum([self.R * s for s in self.sizes])])
@@ -117,10 +132,19 @@ class Problem:
         return self._fac[ck]
 
     # -- the operator as a list of Kronecker terms -----------------------------
-    def spatial_ops(self):
+    def specs_at(self, mu):
+        """beta and sigma of the workload with every field name taken at quadrature point mu."""
+        def ren(names):
+            return tuple(f"{k}@{mu}" for k in names)
+        beta = [None if b is None else (b[0], ren(b[1]), ren(b[2])) for b in self.w.beta]
+        sigma = [(c, ren(P), ren(Q)) for c, P, Q in self.w.sigma]
+        return beta, sigma
+
+    def spatial_ops(self, beta=None, sigma=None):
         d = self.d
         w = self.w
-        beta = w.beta
+        beta = w.beta if beta is None else beta
+        sigma = w.sigma if sigma is None else sigma
         M = [(1.0, _fkey("mass"), _fkey("mass"))]
         T, C, K, Kt, Gm = [], [], [], [], []
         for c in range(2 * d):
@@ -149,7 +173,7 @@ class Problem:
                 else:
                     X, V = _fkey("mass", wa), _fkey("stiff", wb, a=c - d, b=c2 - d)
                 C.append((s1 * s2, X, V))
-        for (sc, P, Q) in w.sigma:
+        for (sc, P, Q) in sigma:
             K.append((sc, _fkey("mass", (1.0, P, None)), _fkey("mass", (1.0, Q, None))))
             # K~_{k,k'} = (sigma phi_k', beta.grad phi_k)
             for c in range(2 * d):
@@ -190,11 +214,27 @@ class Problem:
         """Kronecker terms (time matrix (R,R), x-factor key, v-factor key) of A."""
         w = self.w
         dl = w.delta
-        S = self.spatial_ops()
 
         def tr(ops):
             return [(c, _T(X), _T(V)) for c, X, V in ops]
 
+        if self.tq is not None:
+            # Sect. 4.2, block formula with an m-point time quadrature: per point mu the
+            # spatial factors of the coefficients at tau_mu and the time matrices
+            # w_mu eta_s'(tau_mu) eta_s(tau_mu) (and derivatives); G^t once
+            groups = [(self.Gt, self.spatial_ops()["M"])]
+            for mu in range(len(self.tq["tau"])):
+                S = self.spatial_ops(*self.specs_at(mu))
+                Mm, Tm, Cm = self.tq["M"][mu], self.tq["T"][mu], self.tq["C"][mu]
+                groups += [
+                    (Tm + dl * Cm, S["M"]),
+                    (dl * Tm, tr(S["T"])),
+                    (dl * Tm.T, S["T"] + S["K"]),
+                    (Mm, S["T"] + [(dl * c, X, V) for c, X, V in S["C"]] + S["K"]
+                     + [(dl * c, X, V) for c, X, V in S["Kt"]] + S["Gm"]),
+                ]
+            return self._collect(groups)
+        S = self.spatial_ops()
         groups = [
             (self.Tt + dl * self.Ct + self.Gt, S["M"]),
             (dl * self.Tt, tr(S["T"])),
@@ -202,6 +242,10 @@ class Problem:
             (self.Mt, S["T"] + [(dl * c, X, V) for c, X, V in S["C"]] + S["K"]
              + [(dl * c, X, V) for c, X, V in S["Kt"]] + S["Gm"]),
         ]
+        return self._collect(groups)
+
+    @staticmethod
+    def _collect(groups):
         terms = []
         for Tm, ops in groups:
             if not np.any(Tm):
@@ -217,6 +261,13 @@ class Problem:
     def data_terms(self):
         """b_f(w) = int (f, w + delta (d_t w + d_beta w)) for f in P^r(I_j, V_L)."""
         dl = self.w.delta
+        if self.tq is not None:
+            S0 = self.spatial_ops()
+            groups = [(self.Mt + dl * self.Tt.T, S0["M"])]
+            for mu in range(len(self.tq["tau"])):
+                S = self.spatial_ops(*self.specs_at(mu))
+                groups.append((dl * self.tq["M"][mu], [(c, _T(X), _T(V)) for c, X, V in S["T"]]))
+            return self._collect(groups)
         S = self.spatial_ops()
         ops = [(self.Mt + dl * self.Tt.T, S["M"])] + [(dl * self.Mt, [(c, _T(X), _T(V)) for c, X, V in S["T"]])]
         out = []
@@ -229,6 +280,10 @@ class Problem:
 
     def inflow_data_terms(self):
         """b_g(w) = int over the inflow boundary of |beta.n| g w, for g in P^r(I_j, V_L)."""
+        if self.tq is not None:
+            groups = [(self.tq["M"][mu], self.spatial_ops(*self.specs_at(mu))["Gm"])
+                      for mu in range(len(self.tq["tau"]))]
+            return self._collect(groups)
         S = self.spatial_ops()
         return [(c * self.Mt, X, V) for c, X, V in S["Gm"]]
 

@@ -48,3 +48,19 @@ def left_values(r):
 
 def right_values(r):
     return np.array([eta(s, 1.0) for s in range(r + 1)])
+
+
+def time_quadrature(r, dt, m):
+    """Per-point time matrices of an m-point Gauss-Legendre rule on the strip (Sect. 4.2):
+    M_mu = w_mu eta_s'(tau_mu) eta_s(tau_mu), T_mu = w_mu eta'_s'(tau_mu) eta_s(tau_mu),
+    C_mu = w_mu eta'_s'(tau_mu) eta'_s(tau_mu) (row s test, column s' trial), with the
+    physical weights w_mu (summing to dt) folded in; tau in [-1, 1]."""
+    R = r + 1
+    xg, wg = npleg.leggauss(m)
+    w = wg * dt / 2.0
+    E = np.array([eta(s, xg) for s in range(R)])          # (R, m)
+    Dd = np.array([deta(s, xg, dt) for s in range(R)])
+    M = [w[q] * np.outer(E[:, q], E[:, q]) for q in range(m)]
+    T = [w[q] * np.outer(E[:, q], Dd[:, q]) for q in range(m)]
+    C = [w[q] * np.outer(Dd[:, q], Dd[:, q]) for q in range(m)]
+    return dict(tau=xg, weights=wg, M=M, T=T, C=C)

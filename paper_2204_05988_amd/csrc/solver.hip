@@ -56,6 +56,28 @@ struct BWork {
   DevBuf mU, mX0, mX1, mD0, mD1;  // mass-inverse stages of the grid-problem preconditioner
 };
 
+// Pinned host copies of the per-segment GMRES flags and residual estimates of
+// two consecutive iterations, each with the event that marks its copy done.
+struct FlagRing {
+  int* act[2] = {nullptr, nullptr};
+  double* beta[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int cap = 0;
+  void release() {
+    for (int i = 0; i < 2; ++i) {
+      if (act[i]) (void)hipHostFree(act[i]);
+      if (beta[i]) (void)hipHostFree(beta[i]);
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      act[i] = nullptr;
+      beta[i] = nullptr;
+      ev[i] = nullptr;
+    }
+    cap = 0;
+  }
+  ~FlagRing() { release(); }
+};
+
+
 }  // namespace
 
 struct sgdg_batch_s {
@@ -71,6 +93,8 @@ struct sgdg_batch_s {
   DevBuf rhs_a, rhs_b, rhs_c, rhs_d, rhs_w;
   int64_t inner_iters = 0;
   bool owned_by_ops = false;
+  std::unique_ptr<FlagRing> flags;  // pinned flag copies of the strip FGMRES
+  std::vector<sgdg_net> nets;  // learned preconditioner of each problem (sgdg_batch_set_networks)
   // box-shape choice of the fused kernel per element size (tuned or default)
   int xbox[2] = {0, 0};
   // operator application variant: 0 split (streaming passes), 1 fused box
@@ -78,7 +102,10 @@ struct sgdg_batch_s {
   int variant = 0;
   int split_bc = 0;  // vectors per thread of the split passes (0: default for d)
   int split_xcd = 0;  // 1: XCD-contiguous block order in the split passes
-  int scan_chunks = 1;  // blocks sharing the factor groups of a scan item
+  // blocks sharing the factor groups of a scan item; 0: chosen per launch so
+  // that a step has about kScanBlocks blocks (small steps and single vectors
+  // split their groups; large batched steps keep one block per item)
+  int scan_chunks = 1;
   // graphs of grid-problem GMRES cycles, valid while alloc_epoch() equals
   // graph_epoch (a reallocated work buffer or rebuilt table empties the cache)
   std::map<std::string, hipGraphExec_t> graphs;
@@ -122,7 +149,7 @@ Batch& self_batch(sgdg_ops o) {
       b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
     if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
     b->split_xcd = split_xcd();
-    if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
+    if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(0, atoi(v));
     o->self.reset(b);
   }
   return *o->self;
@@ -521,11 +548,19 @@ static Items& items(Batch& B, int k, int elem) {
   return I;
 }
 
+// target block count of a level-scan launch when the group split is automatic
+constexpr int64_t kScanBlocks = 2048;
+
 template <class T>
 static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   KindData& K = kind(B, k);
   Items& I = items(B, k, int(sizeof(T)));
   BWork<T>& w = work<T>(B);
+  auto buf = [&](DevBuf& d, size_t n) -> T* {
+    d.ensure(sizeof(T) * n);
+    return ptr<T>(d);
+  };
+  auto run = [&](int slot, auto&& launch) { timed(B, slot, s, launch); };
   FusedCall<T> C{};
   C.descs = ptr<ProbDesc>(K.desc);
   C.items = ptr<FusedItem>(I.items);
@@ -540,28 +575,31 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   C.y = y;
   C.sparse_partners = B.variant == 1 ? 0 : 1;
   if (K.any_scan) {
-    w.Pt.ensure(sizeof(T) * size_t(K.pt_bstride) * nb);
-    w.Qt.ensure(sizeof(T) * size_t(K.qt_bstride) * nb);
-    C.Pt = ptr<T>(w.Pt);
-    C.Qt = ptr<T>(w.Qt);
+    C.Pt = buf(w.Pt, size_t(K.pt_bstride) * nb);
+    C.Qt = buf(w.Qt, size_t(K.qt_bstride) * nb);
     C.pt_bstride = K.pt_bstride;
     C.qt_bstride = K.qt_bstride;
-    w.Rv.ensure(sizeof(T) * size_t(K.rv_bstride) * nb);
-    w.Rx.ensure(sizeof(T) * size_t(K.rx_bstride) * nb);
-    C.Rv = ptr<T>(w.Rv);
-    C.Rx = ptr<T>(w.Rx);
+    C.Rv = buf(w.Rv, size_t(K.rv_bstride) * nb);
+    C.Rx = buf(w.Rx, size_t(K.rx_bstride) * nb);
     C.rv_bstride = K.rv_bstride;
     C.rx_bstride = K.rx_bstride;
-    timed(B, 0, s, [&] {
+    run(0, [&] {
       for (size_t t = 0; t < I.step_first.size(); ++t) {
         FusedCall<T> Cs = C;
         Cs.sitems = C.sitems + I.step_first[t];
-        fused_scan_step<T>(Cs, I.step_count[t], B.d, K.R, B.scan_chunks, s);
+        int chunks = B.scan_chunks;
+        if (chunks == 0) {
+          int ng = 1;
+          for (const ProbDesc& D : K.host) ng = std::max(ng, std::max(D.op.nvg, D.op.nxg));
+          const int64_t blocks = int64_t(std::max(1, I.step_count[t])) * nb;
+          chunks = int(std::min<int64_t>(ng, std::max<int64_t>(1, (kScanBlocks + blocks - 1) / blocks)));
+        }
+        fused_scan_step<T>(Cs, I.step_count[t], B.d, K.R, chunks, s);
       }
     });
   }
   if (B.variant == 1) {
-    timed(B, 1, s, [&] { fused_tiles<T>(C, B.d, K.R, s); });
+    run(1, [&] { fused_tiles<T>(C, B.d, K.R, s); });
     return;
   }
   SplitCall<T> S{};
@@ -577,8 +615,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   S.y = y;
   S.Pt = C.Pt;
   S.Qt = C.Qt;
-  w.Z.ensure(sizeof(T) * size_t(K.z_bstride) * nb);
-  S.Z = ptr<T>(w.Z);
+  S.Z = buf(w.Z, size_t(K.z_bstride) * nb);
   S.max_qn = K.max_qn;
   S.tiles = ptr<TileItem>(K.tile_items);
   S.ntiles = B.variant == 2 ? K.n_tile : 0;
@@ -591,7 +628,7 @@ static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
   S.x_assign = K.any_scan ? 0 : 1;
   for (int stage = 0; stage < 3; ++stage) {
     if (stage == 1 && S.x_assign) continue;
-    timed(B, 3 + stage, s, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
+    run(3 + stage, [&] { split_stage<T>(S, B.d, K.R, bc, stage, s); });
   }
 }
 
@@ -1058,9 +1095,24 @@ static std::vector<double> seg_norms(Batch& B, const SegTab& ST, const double* v
 // called after every FGMRES iteration with (iteration, residual estimate, residual at
 // entry); true ends the current cycle (restart from the true residual)
 using Monitor = std::function<bool(int, double, double)>;
+
+static FlagRing& flag_ring(Batch& B, int nseg) {
+  if (!B.flags) B.flags.reset(new FlagRing);
+  FlagRing& f = *B.flags;
+  if (f.cap >= nseg) return f;
+  f.release();
+  for (int i = 0; i < 2; ++i) {
+    SGDG_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&f.act[i]), sizeof(int) * nseg, hipHostMallocDefault));
+    SGDG_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&f.beta[i]), sizeof(double) * nseg, hipHostMallocDefault));
+    SGDG_CHECK_HIP(hipEventCreateWithFlags(&f.ev[i], hipEventDisableTiming));
+  }
+  f.cap = nseg;
+  return f;
+}
 static FgmresResult fgmres(Batch& B, const std::function<void(const double*, double*)>& A,
                            const std::function<void(const double*, double*)>& P, const double* b, double* x,
-                           double tol, int m, int maxit, hipStream_t s, const Monitor* monitor = nullptr) {
+                           double tol, int m, int maxit, hipStream_t s, const Monitor* monitor = nullptr,
+                           const bool* pipelined = nullptr) {
   SegTab& ST = prob_tab(B, B.R);
   const SegTable& S = ST.t;
   const int nseg = S.nseg;
@@ -1088,8 +1140,6 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
     }
   for (int i = 0; i < nseg; ++i)  // b = 0 has the solution 0
     if (bn[i] == 0.0) KernelsT<double>::fill(ST.host[i].len, 0.0, x + ST.host[i].off, s);
-  std::vector<int> act(nseg);
-  std::vector<double> beta(nseg);
   double rel0 = -1;
   for (;;) {
     A(x, w);
@@ -1114,8 +1164,38 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
     gmres_start(nseg, st, S.segs, part, tol, 0, s);  // converged problems start inactive
     KernelsT<double>::seg_scale(S, V, st.inv, V, s);
     const int mm = std::min(m, maxit - res.iters);
-    int j = 0;
+    // The flags and residual estimates of iteration j are copied to pinned host
+    // memory behind its launches.  While the preconditioner runs on the device
+    // alone (*pipelined: the learned map), they are read one iteration late,
+    // after the launches of iteration j + 1 are queued, so the device does not
+    // wait for the host between iterations; an iteration run past a segment's
+    // convergence leaves that segment untouched (inactive segments take no
+    // rotation and count no iteration), so stopping one iteration late changes
+    // no result.  Otherwise (the combination technique, which synchronises
+    // inside) they are read at once, so no preconditioner application is
+    // spent after convergence.
+    FlagRing& fr = flag_ring(B, nseg);
+    enum { GO, CONVERGED, RESTART, BAD };
+    auto evaluate = [&](int e) {
+      const int* a = fr.act[e & 1];
+      const double* be = fr.beta[e & 1];
+      SGDG_CHECK_HIP(hipEventSynchronize(fr.ev[e & 1]));
+      bool any = false, bad = false;
+      double est = 0;
+      for (int i = 0; i < nseg; ++i) {
+        any = any || a[i] == 1;
+        bad = bad || a[i] == -1;
+        if (bn[i] > 0) est = std::max(est, be[i] / bn[i]);
+      }
+      if (verbose) fprintf(stderr, "[sgdg fgmres] it %d  est %.3e\n", res.iters + e + 1, est);
+      const bool restart = monitor && (*monitor)(res.iters + e + 1, est, rel0);
+      if (bad) return int(BAD);
+      if (!any) return int(CONVERGED);
+      return restart ? int(RESTART) : int(GO);
+    };
+    int j = 0, pending = -1, used = -1, ran = 0;
     for (; j < mm; ++j) {
+      ran = j + 1;  // iterations queued (their directions Z_0..Z_j enter the update)
       P(V + int64_t(j) * n, Z + int64_t(j) * n);
       A(Z + int64_t(j) * n, w);
       for (int pass = 0; pass < 2; ++pass) {
@@ -1125,30 +1205,42 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
       }
       gmres_givens(nseg, st, S.segs, part, j, tol * 0.5, s);
       KernelsT<double>::seg_scale(S, w, st.inv, V + int64_t(j + 1) * n, s);
-      SGDG_CHECK_HIP(hipMemcpyAsync(act.data(), st.active, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
-      SGDG_CHECK_HIP(hipMemcpyAsync(beta.data(), st.beta, sizeof(double) * nseg, hipMemcpyDeviceToHost, s));
-      SGDG_CHECK_HIP(hipStreamSynchronize(s));
-      bool any = false, bad = false;
-      double est = 0;
-      for (int i = 0; i < nseg; ++i) {
-        any = any || act[i] == 1;
-        bad = bad || act[i] == -1;
-        if (bn[i] > 0) est = std::max(est, beta[i] / bn[i]);
+      SGDG_CHECK_HIP(hipMemcpyAsync(fr.act[j & 1], st.active, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+      SGDG_CHECK_HIP(hipMemcpyAsync(fr.beta[j & 1], st.beta, sizeof(double) * nseg, hipMemcpyDeviceToHost, s));
+      SGDG_CHECK_HIP(hipEventRecord(fr.ev[j & 1], s));
+      const bool lag = pipelined && *pipelined;
+      int v = GO, e = -1;
+      if (pending >= 0) {
+        e = pending;
+        v = evaluate(e);
       }
-      if (verbose) fprintf(stderr, "[sgdg fgmres] it %d  est %.3e\n", res.iters + j + 1, est);
-      const bool restart = monitor && (*monitor)(res.iters + j + 1, est, rel0);
-      if (bad) {
-        res.nan = true;
-        return res;
+      pending = j;
+      if (v == GO && !lag) {
+        e = j;
+        v = evaluate(e);
+        pending = -1;
       }
-      if (!any || restart) {
-        ++j;
+      if (v != GO) {
+        if (v == BAD) {
+          res.nan = true;
+          return res;
+        }
+        // converged at iteration e: the iterations after it did nothing
+        used = v == CONVERGED ? e + 1 : j + 1;
         break;
       }
     }
-    res.iters += j;
+    if (used < 0) {
+      used = j;
+      if (pending >= 0 && evaluate(pending) == BAD) {  // the cycle's last iteration
+        res.nan = true;
+        return res;
+      }
+    }
+    res.iters += used;
     gmres_lsq(nseg, st, s);
-    KernelsT<double>::seg_axpy(S, Z, n, j, st.y, m, x, 1.0, nullptr, s);
+    // y has kused entries per segment (zeros beyond): every queued direction may enter
+    KernelsT<double>::seg_axpy(S, Z, n, ran, st.y, m, x, 1.0, nullptr, s);
   }
 }
 
@@ -1198,21 +1290,36 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
   // At the switch the cycle ends: the combination technique then starts a
   // fresh Krylov space from the true residual instead of extending the basis
   // the network built.
+  // the learned map runs on the device alone: FGMRES may read its flags late
+  bool device_only_pc = !use_ct;
   const Monitor monitor = [&](int it, double est, double rel0) {
     (void)it;
     if (use_ct) return false;
     if (fb.step(est, rel0)) {
       use_ct = true;
+      device_only_pc = false;
       fell_back = true;
       return true;
     }
     return false;
   };
   auto A64 = [&](const double* in, double* out) { apply<double>(B, K_FULL, in, out, 1, s); };
+  // the learned map: one network per problem, each on its problem's slice
+  auto learned_apply = [&](const double* in, double* out) {
+    if (B.nets.empty()) {
+      net_apply_dev(pc.net, in, out, s);
+      return;
+    }
+    int64_t off = 0;
+    for (size_t i = 0; i < B.P.size(); ++i) {
+      net_apply_dev(B.nets[i], in + off, out + off, s);
+      off += int64_t(B.R) * B.P[i]->grid->up_pts;
+    }
+  };
   auto P64 = [&](const double* in, double* out) {
     ++pc_apps;
     if (!use_ct) {
-      net_apply_dev(pc.net, in, out, s);
+      learned_apply(in, out);
       return;
     }
     ct_apply<double>(B, in, out, pc, graph, s, nan);
@@ -1220,7 +1327,8 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
   };
   sgdg_solve_stats st{};
   if (!so.mixed_precision) {
-    FgmresResult r = fgmres(B, A64, P64, b, u, so.rtol, so.restart, so.maxit, s, learned ? &monitor : nullptr);
+    FgmresResult r =
+        fgmres(B, A64, P64, b, u, so.rtol, so.restart, so.maxit, s, learned ? &monitor : nullptr, &device_only_pc);
     st.outer_iters = r.iters;
     st.rel_residual = r.rel;
     *nan = *nan || r.nan;
@@ -1244,7 +1352,7 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
     auto P32 = [&](const double* in, double* out) {
       ++pc_apps;
       if (!use_ct) {
-        net_apply_dev(pc.net, in, out, s);
+        learned_apply(in, out);
         return;
       }
       convert_f64_to_f32(n, in, a32, s);
@@ -1274,8 +1382,8 @@ static sgdg_solve_stats solve_batch(Batch& B, const double* b, double* u, const 
       if (rel <= so.rtol || total >= so.maxit || steps >= 20) break;
       KernelsT<double>::fill(n, 0.0, e, s);
       fb.begin();  // estimates of this correction solve are relative to its own right-hand side
-      FgmresResult ri =
-          fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s, learned ? &monitor : nullptr);
+      FgmresResult ri = fgmres(B, A32, P32, rr, e, inner_tol, so.restart, so.maxit - total, s,
+                               learned ? &monitor : nullptr, &device_only_pc);
       total += std::max(ri.iters, 1);
       ++steps;
       if (ri.nan) {
@@ -1382,6 +1490,7 @@ static void nodal_to_coef(Batch& B, const double* samples, int nq, const double*
 // ------------------------------------------------------------ autotuner --
 struct TuneCfg {
   int variant, bc, xbox, xcd;
+  int chunks = 1;  // blocks sharing a scan item's factor groups
 };
 
 static std::vector<TuneCfg> tune_candidates(int d) {
@@ -1397,7 +1506,7 @@ static std::vector<TuneCfg> tune_candidates(int d) {
 
 static std::string tune_key(const Batch& B, int elem, int nb) {
   std::ostringstream k;
-  k << "v2_d" << B.d << "_R" << B.R << "_e" << elem << "_b" << nb << "_p" << B.P.size() << "_g";
+  k << "v3_d" << B.d << "_R" << B.R << "_e" << elem << "_b" << nb << "_p" << B.P.size() << "_g";
   for (sgdg_ops o : B.P) {
     for (const auto& gd : o->grid->up) k << gd.lx << "." << gd.lv << ",";
     k << (o->grid->x.periodic ? "P" : "N") << (o->grid->v.periodic ? "P" : "N") << ";";
@@ -1420,7 +1529,7 @@ static bool tune_lookup(const std::string& key, TuneCfg& cfg, double& ms) {
     std::string k;
     TuneCfg c{};
     double t = 0;
-    if (in >> k >> c.variant >> c.bc >> c.xbox >> c.xcd >> t && k == key) {
+    if (in >> k >> c.variant >> c.bc >> c.xbox >> c.xcd >> c.chunks >> t && k == key) {
       cfg = c;
       ms = t;
       found = true;
@@ -1434,10 +1543,12 @@ static void tune_store(const std::string& key, const TuneCfg& c, double ms) {
   const size_t slash = path.find_last_of('/');
   if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);  // one level, best effort
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << c.variant << " " << c.bc << " " << c.xbox << " " << c.xcd << " " << ms << "\n";
+  if (f) f << key << " " << c.variant << " " << c.bc << " " << c.xbox << " " << c.xcd << " " << c.chunks << " " << ms
+           << "\n";
 }
 
 static void set_cfg(Batch& B, const TuneCfg& c) {
+  B.scan_chunks = std::max(0, c.chunks);
   B.variant = c.variant;
   B.split_bc = c.bc;
   B.split_xcd = c.xcd;
@@ -1474,7 +1585,7 @@ static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t
   double best_ms = 0;
   if (!force && tune_lookup(key, best, best_ms)) {
     set_cfg(B, best);
-    r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 1};
+    r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 1, best.chunks};
     return r;
   }
   const int64_t n = kind(B, K_FULL).total * nb;
@@ -1499,12 +1610,33 @@ static sgdg_tune_result tune(Batch& B, int nb, int reps, bool force, hipStream_t
       best = c;
     }
   }
+  if (best_ms >= 1e300) {
+    B.prof = prof;
+    throw Error{SGDG_E_STATE, "no launch configuration could run"};
+  }
+  // few vectors leave the level scans short of blocks: split each item's
+  // factor groups over several blocks (more parallel, the u gathers repeated)
+  if (nb <= 4) {
+    int ng = 1;
+    for (const ProbDesc& D : kind(B, K_FULL).host) ng = std::max(ng, std::max(D.op.nvg, D.op.nxg));
+    const TuneCfg base = best;
+    for (int ch : {2, 4, 8}) {
+      if (ch > ng) break;
+      TuneCfg c = base;
+      c.chunks = ch;
+      set_cfg(B, c);
+      const double ms = time_apply<T>(B, ptr<T>(u), ptr<T>(y), nb, std::max(1, reps), s);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
   B.prof = prof;
-  if (best_ms >= 1e300) throw Error{SGDG_E_STATE, "no launch configuration could run"};
   set_cfg(B, best);
   SGDG_CHECK_HIP(hipStreamSynchronize(s));
   tune_store(key, best, best_ms);
-  r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 0};
+  r = {best.variant, best.bc, best.xbox, best.xcd, best_ms, 0, best.chunks};
   return r;
 }
 
@@ -1624,9 +1756,14 @@ static void check_solve_opts(const sgdg_solve_opts* so, const Batch& B) {
   require(so->rtol > 0 && so->restart >= 1 && so->restart <= 64 && so->maxit >= 1, "invalid solver options");
   require(so->pc.kind == 0 || so->pc.kind == 1, "unknown preconditioner kind");
   check_mass(so->pc, B.d);
-  if (so->pc.kind == 1)
-    require(so->pc.net != nullptr && B.P.size() == 1 && net_problem(so->pc.net) == B.P[0],
-            "the learned preconditioner needs the network of this problem");
+  if (so->pc.kind == 1) {
+    if (B.owned_by_ops)
+      require(so->pc.net != nullptr && net_problem(so->pc.net) == B.P[0],
+              "the learned preconditioner needs the network of this problem");
+    else
+      require(B.nets.size() == B.P.size(),
+              "the learned preconditioner of a batch needs one network per problem (sgdg_batch_set_networks)");
+  }
 }
 
 extern "C" sgdg_status sgdg_solve_strip(sgdg_ops o, const double* b_dev, double* u_dev, const sgdg_solve_opts* so,
@@ -1661,7 +1798,7 @@ extern "C" sgdg_status sgdg_batch_create(const sgdg_ops* ops, int n, sgdg_batch*
     b->variant = std::string(v) == "fused" ? 1 : (std::string(v) == "split_tiled" ? 2 : 0);
   if (const char* v = getenv("SGDG_SPLIT_BC")) b->split_bc = atoi(v);
   b->split_xcd = split_xcd();
-  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(1, atoi(v));
+  if (const char* v = getenv("SGDG_SCAN_CHUNKS")) b->scan_chunks = std::max(0, atoi(v));
   *out = b;
   API_END
 }
@@ -1696,6 +1833,17 @@ extern "C" sgdg_status sgdg_batch_solve(sgdg_batch b, const double* b_dev, doubl
   if (st) *st = stats;
   if (nan) throw Error{SGDG_E_NAN, "non-finite residual norm"};
   if (stats.rel_residual > so->rtol) throw Error{SGDG_E_NOCONV, "iteration limit reached before the tolerance"};
+  API_END
+}
+
+extern "C" sgdg_status sgdg_batch_set_networks(sgdg_batch b, const sgdg_net* nets, int n) {
+  API_BEGIN
+  require(b != nullptr, "null batch");
+  require(n == 0 || (nets != nullptr && n == int(b->P.size())), "need one network per problem of the batch (or n = 0)");
+  for (int i = 0; i < n; ++i)
+    require(nets[i] != nullptr && net_problem(nets[i]) == b->P[size_t(i)],
+            "network " + std::to_string(i) + " does not belong to problem " + std::to_string(i) + " of the batch");
+  b->nets.assign(nets, nets + n);
   API_END
 }
 
@@ -1830,7 +1978,9 @@ extern "C" sgdg_status sgdg_set_launch(sgdg_ops o, const sgdg_tune_result* cfg) 
   else
     require(cfg->xbox >= 1 && cfg->xbox <= 256, "xbox must be 1..256");
   require(cfg->block_map == 0 || cfg->block_map == 1, "block_map must be 0 or 1");
+  require(cfg->scan_chunks >= 0 && cfg->scan_chunks <= 64, "scan_chunks must be 0..64");
   set_cfg(B, TuneCfg{cfg->variant, cfg->variant != 1 ? cfg->vectors_per_thread : 0,
-                     cfg->variant == 1 ? cfg->xbox : B.xbox[0], cfg->variant != 1 ? cfg->block_map : 0});
+                     cfg->variant == 1 ? cfg->xbox : B.xbox[0], cfg->variant != 1 ? cfg->block_map : 0,
+                     cfg->scan_chunks > 0 ? cfg->scan_chunks : B.scan_chunks});
   API_END
 }

@@ -28,6 +28,8 @@ EXPORTS = [
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
     "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune", "sgdg_set_launch",
     "sgdg_graph_cache_size", "sgdg_debug_fallback", "sgdg_debug_grid_precond",
+    "sgdg_batch_set_networks", "sgdg_vp_create", "sgdg_vp_info", "sgdg_vp_density", "sgdg_vp_field",
+    "sgdg_vp_strip", "sgdg_vp_destroy",
 ]
 
 
@@ -71,14 +73,24 @@ class SolveStats(C.Structure):
 VARIANTS = ("split", "fused", "split_tiled")
 
 
+class VpOpts(C.Structure):
+    _fields_ = [("fp_tol", C.c_double), ("max_fp", C.c_int), ("solve", SolveOpts)]
+
+
+class VpStats(C.Structure):
+    _fields_ = [("fp_iters", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int), ("dE", C.c_double),
+                ("df", C.c_double), ("energy", C.c_double), ("rel_residual", C.c_double), ("seconds", C.c_double),
+                ("assemble_seconds", C.c_double)]
+
+
 class TuneResult(C.Structure):
     _fields_ = [("variant", C.c_int), ("vectors_per_thread", C.c_int), ("xbox", C.c_int), ("block_map", C.c_int),
-                ("ms", C.c_double), ("from_cache", C.c_int)]
+                ("ms", C.c_double), ("from_cache", C.c_int), ("scan_chunks", C.c_int)]
 
     def as_dict(self):
         return {"variant": VARIANTS[self.variant], "vectors_per_thread": self.vectors_per_thread,
                 "xbox": self.xbox, "block_map": "xcd" if self.block_map else "round_robin", "ms": self.ms,
-                "from_cache": bool(self.from_cache)}
+                "from_cache": bool(self.from_cache), "scan_chunks": self.scan_chunks}
 
 
 class TrainOpts(C.Structure):
@@ -124,6 +136,14 @@ def lib():
     L.sgdg_batch_layout.argtypes = [vp, i64p]
     L.sgdg_batch_apply.argtypes = [vp, vp, vp, C.c_int, vp]
     L.sgdg_batch_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+    L.sgdg_batch_set_networks.argtypes = [vp, C.POINTER(vp), C.c_int]
+    L.sgdg_vp_create.argtypes = [vp, C.c_double, C.c_double, C.POINTER(vp)]
+    L.sgdg_vp_info.argtypes = [vp, i64p, ip]
+    L.sgdg_vp_density.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp]
+    L.sgdg_vp_field.argtypes = [vp, vp, vp, dp, vp]
+    L.sgdg_vp_strip.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(VpOpts), C.POINTER(VpStats), vp]
+    L.sgdg_vp_destroy.argtypes = [vp]
+    L.sgdg_vp_destroy.restype = None
     L.sgdg_batch_destroy.argtypes = [vp]
     L.sgdg_batch_destroy.restype = None
     fp = C.POINTER(C.c_float)
@@ -148,7 +168,7 @@ def lib():
     L.sgdg_debug_grid_precond.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp]
     for name in EXPORTS:
         if name not in ("sgdg_last_error", "sgdg_grid_destroy", "sgdg_ops_destroy", "sgdg_batch_destroy",
-                        "sgdg_net_destroy"):
+                        "sgdg_net_destroy", "sgdg_vp_destroy"):
             getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -358,8 +378,8 @@ class SparseGridOps:
                                _stream(stream)))
         return r.as_dict()
 
-    def set_launch(self, variant="split", vectors_per_thread=2, xbox=8, block_map=0):
-        r = TuneResult(VARIANTS.index(variant), vectors_per_thread, xbox, block_map, 0.0, 0)
+    def set_launch(self, variant="split", vectors_per_thread=2, xbox=8, block_map=0, scan_chunks=0):
+        r = TuneResult(VARIANTS.index(variant), vectors_per_thread, xbox, block_map, 0.0, 0, scan_chunks)
         _check(lib().sgdg_set_launch(self.ops, C.byref(r)))
 
     def grid_precond(self, x, y, sweeps=0, stream=None):
@@ -429,6 +449,14 @@ class SparseGridBatch:
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return u, st
+
+    def set_networks(self, nets):
+        """One LearnedPreconditioner per problem (same order), used by solves with
+        a learned preconditioner (default_precond_opts(net=...) with any of them);
+        an empty list removes them."""
+        arr = (C.c_void_p * max(1, len(nets)))(*[n.h.value for n in nets])
+        _check(lib().sgdg_batch_set_networks(self.h, arr, len(nets)))
+        self._nets = list(nets)  # keeps the networks alive
 
     def close(self):
         if getattr(self, "h", None):
@@ -511,6 +539,80 @@ class LearnedPreconditioner:
         if getattr(self, "h", None):
             lib().sgdg_net_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VlasovPoisson:
+    """The Vlasov-Poisson fixed point on a workload's sparse-grid layout (x
+    periodic, d <= 2): density, field and strips, all on the device."""
+
+    def __init__(self, w):
+        L = lib()
+        self.w = w
+        self.R = w.r + 1
+        self._dx, self._dv = _domain(w.x), _domain(w.v)
+        g = C.c_void_p()
+        _check(L.sgdg_build_sparse_grid(C.byref(self._dx), C.byref(self._dv), w.lmin, w.L, w.r, C.byref(g)))
+        self.grid = g
+        h = C.c_void_p()
+        _check(L.sgdg_vp_create(g, w.dt, w.delta, C.byref(h)))
+        self.h = h
+        n, d = C.c_int64(), C.c_int()
+        _check(L.sgdg_vp_info(h, C.byref(n), C.byref(d)))
+        self.n_fine, self.d = n.value, d.value
+        k = C.c_int()
+        _check(L.sgdg_grid_info(g, 0, C.byref(k), None, None, None, None, None, None))
+        nx, nv = (C.c_int64 * k.value)(), (C.c_int64 * k.value)()
+        _check(L.sgdg_grid_info(g, 0, None, None, None, None, nx, nv, None))
+        self.npts = int(sum(a * b for a, b in zip(nx, nv)))
+        self.ndof = self.R * self.npts
+
+    def density(self, f, nslices, tau=0.0, rho=None, stream=None):
+        import torch
+        if rho is None:
+            rho = torch.empty(self.n_fine, dtype=torch.float64, device=f.device)
+        pf = _dev(f, "f", nslices * self.npts)
+        pr = _dev(rho, "rho", self.n_fine)
+        _check(lib().sgdg_vp_density(self.h, pf, nslices, tau, pr, _stream(stream)))
+        return rho
+
+    def field(self, rho, E=None, stream=None):
+        """(E [d][n_fine], electric energy)."""
+        import torch
+        if E is None:
+            E = torch.empty(self.d * self.n_fine, dtype=torch.float64, device=rho.device)
+        en = C.c_double()
+        _check(lib().sgdg_vp_field(self.h, _dev(rho, "rho", self.n_fine), _dev(E, "E", self.d * self.n_fine),
+                                   C.byref(en), _stream(stream)))
+        return E, en.value
+
+    def strip(self, f_prev, prev_slices, E0, fp_tol=1e-9, max_fp=30, solve=None, stream=None,
+              raise_on_noconv=True):
+        """(f, E, stats) of one strip of the fixed point."""
+        import torch
+        f = torch.empty(self.ndof, dtype=torch.float64, device=f_prev.device)
+        E = torch.empty(self.d * self.n_fine, dtype=torch.float64, device=f_prev.device)
+        o = VpOpts(fp_tol, max_fp, solve or default_solve_opts(rtol=1e-10))
+        st = VpStats()
+        code = lib().sgdg_vp_strip(self.h, _dev(f_prev, "f_prev", prev_slices * self.npts), prev_slices,
+                                   _dev(E0, "E0", self.d * self.n_fine), _dev(f, "f", self.ndof),
+                                   _dev(E, "E", self.d * self.n_fine), C.byref(o), C.byref(st), _stream(stream))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        return f, E, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sgdg_vp_destroy(self.h)
+            self.h = None
+        if getattr(self, "grid", None):
+            lib().sgdg_grid_destroy(self.grid)
+            self.grid = None
 
     def __del__(self):
         try:

@@ -255,3 +255,51 @@ def test_net_parity_at_benchmark_size(dev):
         assert e <= 1e-2
         assert eg <= 1e-2
     net.close()
+
+
+def test_batched_learned_mixed_solve(dev):
+    """Two 4D Vlasov-type problems (different seeds, so different fields E) in one
+    batch, each with its own network (trained briefly on pairs recorded from its
+    own CT solves): the batched learned + mixed-precision solve reaches 1e-8 under
+    each problem's oracle operator, with and without the CT fallback taking over;
+    a batch solve with a learned preconditioner but no networks is refused."""
+    from paper_2204_05988_amd import sgdg
+    probs = []
+    for seed in (0, 1):
+        w = config_c5(seed=seed, L=4)
+        P = Problem(w)
+        ops = sgdg.SparseGridOps(w)
+        net = sgdg.LearnedPreconditioner(ops, seed=10 + seed)
+        net.record(64)
+        u = torch.tensor(ostrip.initial_coefficients(P), device=dev)
+        for j in range(1, 4):
+            b = ops.rhs(u, 1)
+            u, _ = ops.solve_strip(b, torch.zeros_like(b), sgdg.default_solve_opts(rtol=1e-8))
+        net.record(0)
+        ts = net.train(steps=150, batch=8, lr=1e-3, seed=2)
+        _say(f"problem seed {seed}: {net.pair_count()} pairs, loss {ts.loss_first:.3e} -> {ts.loss_last:.3e}")
+        probs.append((w, P, ops, net, ops.rhs(u, 1)))
+    batch = sgdg.SparseGridBatch([p[2] for p in probs])
+    off = batch.offsets
+    bt = torch.cat([p[4] for p in probs])
+    bn = bt.cpu().numpy()
+    opts = sgdg.default_solve_opts(rtol=1e-8, maxit=300, mixed=True,
+                                   pc=sgdg.default_precond_opts(net=probs[0][3]))
+    with pytest.raises(sgdg.SgdgError):
+        batch.solve(bt, torch.zeros_like(bt), opts)
+    batch.set_networks([p[3] for p in probs])
+    for drop, label in ((10.0, "default fallback rule"), (1e30, "fallback at the first check")):
+        opts.pc.fallback_drop = drop
+        x, st = batch.solve(bt, torch.zeros_like(bt), opts)
+        xs = x.cpu().numpy()
+        _say(f"  batched learned+mixed ({label}): {st.outer_iters} iterations, {st.refinement_steps} refinements, "
+             f"fallback {st.fallback_used}, {st.pc_applications} applications, {st.seconds:.3f}s")
+        for k, (w, P, ops, net, b) in enumerate(probs):
+            res = np.linalg.norm(bn[off[k]:off[k + 1]] - P.apply(xs[off[k]:off[k + 1]])) / \
+                np.linalg.norm(bn[off[k]:off[k + 1]])
+            _say(f"    problem {k}: oracle residual {res:.2e}")
+            assert res <= 1e-8 * (1 + 1e-6)
+    assert st.fallback_used == 1
+    batch.close()
+    for p in probs:
+        p[3].close()

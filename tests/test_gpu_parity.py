@@ -338,3 +338,28 @@ def test_nan_residual_is_reported(dev):
     with pytest.raises(sgdg.SgdgError) as ei:
         ops.precondition(rt, zt)
     assert ei.value.code == -6
+
+
+@pytest.mark.parametrize("case", ["tiny_d3", "c1", "c2_L5", "c5_L5"])
+def test_scan_group_split_is_exact(dev, case):
+    """Level scans whose factor groups are split over 2, 4 or 7 blocks per item (the
+    tuned setting for single vectors) give the unsplit result bit for bit."""
+    w, P, ops = _problem(case, CASES[case])
+    u = torch.tensor(random_vector(P.ndof, 77)[0], device=dev)
+    base = "split" if w.d == 3 else "split_tiled"
+    bc = 1 if w.d == 3 else 2
+    ops.set_launch(base, bc, 8, 0, 1)
+    y1 = torch.empty_like(u)
+    ops.apply(u, y1)
+    torch.cuda.synchronize()
+    assert _rel(y1.cpu().numpy(), P.apply(u.cpu().numpy())) <= 1e-10
+    try:
+        for ch in (2, 4, 7):
+            ops.set_launch(base, bc, 8, 0, ch)
+            y = torch.empty_like(u)
+            ops.apply(u, y)
+            torch.cuda.synchronize()
+            _say(f"scan groups over {ch} blocks: {case}")
+            assert torch.equal(y, y1)
+    finally:
+        ops.set_launch("split", bc, 8, 0, 1)

@@ -25,7 +25,7 @@ __all__ = [
     "Domain", "Workload", "lattice_shape", "lattice_coords", "nodal_fields",
     "grid_levels", "gauss_legendre_times", "random_vector", "sample_on_grids",
     "config_c1", "config_c2", "config_c3", "config_c4_member", "config_c4",
-    "config_c5", "config_table1", "config_tiny", "h_min",
+    "config_c5", "config_table1", "config_tiny", "config_landau", "h_min",
 ]
 
 
@@ -60,6 +60,10 @@ class Workload:
     exact: Optional[Callable] = None    # exact solution u(t, X, V) if known
     seed: int = 0
     noise: float = 0.0                  # amplitude of N(0,1) noise on u0 coefficients
+    # coefficients that depend on time: t -> (xfields, vfields) at time t, the same
+    # names as xfields / vfields (which then give the fields' layout only)
+    tfields: Optional[Callable] = None
+    tquad: int = 0                      # time quadrature points per strip (0: r + 2)
 
     @property
     def d(self):
@@ -297,6 +301,33 @@ def config_table1(Lp: int, r: int = 1) -> Workload:
         delta=2.0 ** (-(Lp + 1)), nstrips=nst,
         beta=[(1.0, (), ()), (1.0, (), ())], sigma=[], xfields={}, vfields={},
         u0=lambda X, V: exact(0.0, X, V), f=None, g=None, exact=exact)
+
+
+def config_landau(d: int = 1, paper_level: int = 5, r: int = 1, dt: float = 0.5, alpha: float = 1e-2,
+                  k: float = 0.5, E=None, vmax: float = 6.0) -> Workload:
+    """Landau damping (Sect. 5.3): periodic (0, 4 pi)^d x (-vmax, vmax)^d, four cells per
+    axis on the coarsest level (lmin = 2, so the paper's level L is L + 1 here),
+    f0 = exp(-|v|^2/2) / (2 pi)^(d/2) * (1 + alpha sum_i cos(k x_i)), beta = (v, -E(x))
+    with E the nodal field on the finest x-lattice, [d][n] (zero when None)."""
+    lmin = 2
+    L = lmin + paper_level - 1
+    x = Domain(d, (0.0,) * d, (4 * np.pi,) * d, periodic=True)
+    v = Domain(d, (-vmax,) * d, (vmax,) * d)
+    nfine = (2 ** L) ** d
+    Ef = np.zeros((d, nfine)) if E is None else np.asarray(E, float).reshape(d, nfine)
+    beta = [(1.0, (), (f"v{i}",)) for i in range(d)] + [(-1.0, (f"E{i}",), ()) for i in range(d)]
+    h = min(4 * np.pi, 2 * vmax) / 2 ** L
+
+    def f0(X, V):
+        return (np.exp(-0.5 * np.sum(V * V, axis=-1)) / (2 * np.pi) ** (d / 2)
+                * (1 + alpha * np.sum(np.cos(k * X), axis=-1)))
+
+    return Workload(
+        name=f"landau_d{d}_L{paper_level}", x=x, v=v, lmin=lmin, L=L, r=r, dt=dt, delta=0.5 * h,
+        nstrips=int(round(50 / dt)), beta=beta, sigma=[],
+        xfields={f"E{i}": (lambda P, i=i: Ef[i].copy()) for i in range(d)},
+        vfields={f"v{i}": _coord(i) for i in range(d)},
+        u0=f0, f=None, g=None, exact=None)
 
 
 def config_tiny(kind: str) -> Workload:
