@@ -189,6 +189,31 @@ typedef struct {
 sgdg_status sgdg_precondition(sgdg_ops o, const void* r_dev, void* z_dev, sgdg_dtype t, int batch,
                               const sgdg_precond_opts* po, hipStream_t s);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ * y_dev = Op u_dev exactly as sgdg_apply_operator (same arguments, same
+ * kernels and launch configuration, same results), but every work array of
+ * the call (the cross-grid scan arrays and the staged v-stage values) is
+ * carved from one fixed library-owned device array of
+ * SGDG_NOALLOC_SCRATCH_BYTES per device, taken at the first call on a device
+ * and held until the process ends.  The call allocates nothing and times
+ * nothing.
+ * Requirements and errors: the current device must be the handle's device
+ * (SGDG_E_ARG otherwise); the handle's launch tables for this kind and dtype
+ * must exist -- the first sgdg_apply_operator call with that kind and dtype
+ * builds them, and tuning or sgdg_set_launch rebuilds them -- else
+ * SGDG_E_STATE; a call needing more scratch than the array holds (about
+ * (n_xgroups + 4 n_groups 2^-d) n_dof elements per vector, e.g. 0.13 GB for
+ * one FP64 vector of the 4D problem at level 7) fails with SGDG_E_ARG and a
+ * message giving the bytes it needs.
+ * Sharing: every call on one device uses the same array, and it keeps the
+ * last call's contents (nothing in it needs to start at zero).  Calls that
+ * overlap on one device -- two streams, two threads, two handles -- race on
+ * it and give wrong results: order them on one stream. */
+#define SGDG_NOALLOC_SCRATCH_BYTES (256u << 20)
+sgdg_status sgdg_apply_operator_noalloc(sgdg_ops o, int kind, const void* u_dev, void* y_dev, sgdg_dtype t,
+                                        int batch, hipStream_t s);
+
 /* --------------------------------------------------------- strip solves -- */
 
 /* Right-hand side b_j of (eq:weak_form_j) into b_dev (FP64, n_dof):

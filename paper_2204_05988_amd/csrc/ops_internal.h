@@ -43,6 +43,10 @@ static inline void require(bool ok, const std::string& msg) {
   if (!ok) throw Error{SGDG_E_ARG, msg};
 }
 
+static inline void require_state(bool ok, const std::string& msg) {
+  if (!ok) throw Error{SGDG_E_STATE, msg};
+}
+
 template <class T>
 static inline T* ptr(const DevBuf& b) {
   return static_cast<T*>(b.p);

@@ -5,6 +5,7 @@
 #include <sys/stat.h>
 
 #include <chrono>
+#include <mutex>
 #include <fstream>
 #include <limits>
 #include <sstream>
@@ -551,16 +552,55 @@ static Items& items(Batch& B, int k, int elem) {
 // target block count of a level-scan launch when the group split is automatic
 constexpr int64_t kScanBlocks = 2048;
 
+// Caller-provided scratch for the allocation-free application: the work
+// arrays of one call are carved from it in turn (256-byte aligned pieces).
+struct Carve {
+  unsigned char* base = nullptr;
+  size_t bytes = 0, used = 0;
+  template <class T>
+  T* take(size_t n) {
+    const size_t b = (sizeof(T) * n + 255) & ~size_t(255);
+    if (used + b > bytes) throw Error{SGDG_E_ARG, "scratch too small"};
+    T* p = reinterpret_cast<T*>(base + used);
+    used += b;
+    return p;
+  }
+};
+
+// Scratch bytes one application of kind k needs for nb vectors of T (the
+// launch tables must exist).
 template <class T>
-static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s) {
+static size_t apply_scratch_bytes(Batch& B, int k, int nb) {
+  const KindData& K = B.kinds[k];
+  auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t need = 0;
+  if (K.any_scan)
+    need += r(sizeof(T) * size_t(K.pt_bstride) * nb) + r(sizeof(T) * size_t(K.qt_bstride) * nb) +
+            r(sizeof(T) * size_t(K.rv_bstride) * nb) + r(sizeof(T) * size_t(K.rx_bstride) * nb);
+  if (B.variant != 1) need += r(sizeof(T) * size_t(K.z_bstride) * nb);
+  return need;
+}
+
+// ws == nullptr: work arrays from the handle's workspaces (grown on demand);
+// otherwise every work array comes from *ws, the tables must already exist and
+// nothing is allocated or timed.
+template <class T>
+static void apply(Batch& B, int k, const T* u, T* y, int nb, hipStream_t s, Carve* ws = nullptr) {
+  if (ws) require_state(!B.kinds[k].host.empty() && B.kinds[k].it[sizeof(T) == 8 ? 0 : 1].built,
+                        "launch tables of this operator kind and dtype are not built yet: apply it once with "
+                        "sgdg_apply_operator first");
   KindData& K = kind(B, k);
   Items& I = items(B, k, int(sizeof(T)));
   BWork<T>& w = work<T>(B);
   auto buf = [&](DevBuf& d, size_t n) -> T* {
+    if (ws) return ws->take<T>(n);
     d.ensure(sizeof(T) * n);
     return ptr<T>(d);
   };
-  auto run = [&](int slot, auto&& launch) { timed(B, slot, s, launch); };
+  auto run = [&](int slot, auto&& launch) {
+    if (ws) launch();
+    else timed(B, slot, s, launch);
+  };
   FusedCall<T> C{};
   C.descs = ptr<ProbDesc>(K.desc);
   C.items = ptr<FusedItem>(I.items);
@@ -1653,6 +1693,59 @@ extern "C" sgdg_status sgdg_apply_operator(sgdg_ops o, int kind_, const void* u_
   Batch& B = self_batch(o);
   if (t == SGDG_F64) apply<double>(B, map[kind_], static_cast<const double*>(u_dev), static_cast<double*>(y_dev), batch, s);
   else apply<float>(B, map[kind_], static_cast<const float*>(u_dev), static_cast<float*>(y_dev), batch, s);
+  API_END
+}
+
+// ------------------------------------------------ allocation-free apply ---
+// Device scratch of sgdg_apply_operator_noalloc.  Host code never uses this
+// name as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SGDG_NOALLOC_SCRATCH_BYTES];
+
+static unsigned char* scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> ptrs;
+  int dev = -1;
+  SGDG_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  SGDG_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  require(p != nullptr, "no device address for the scratch array");
+  ptrs[dev] = static_cast<unsigned char*>(p);
+  return static_cast<unsigned char*>(p);
+}
+
+extern "C" sgdg_status sgdg_apply_operator_noalloc(sgdg_ops o, int kind_, const void* u_dev, void* y_dev,
+                                                   sgdg_dtype t, int batch, hipStream_t s) {
+  API_BEGIN
+  require(o != nullptr, "null ops");
+  require(kind_ >= SGDG_OP_FULL && kind_ <= SGDG_OP_DATA_G, "unknown operator kind");
+  require(u_dev && y_dev && u_dev != y_dev, "u and y must be distinct non-null device buffers");
+  require(batch >= 1, "batch must be >= 1");
+  require(t == SGDG_F64 || t == SGDG_F32, "dtype must be F64 or F32");
+  int dev = -1;
+  SGDG_CHECK_HIP(hipGetDevice(&dev));
+  require(dev == o->device, "the current device is not the device of the ops handle");
+  static const int map[5] = {K_FULL, K_DIAG, K_MASS, K_DATAF, K_DATAG};
+  require_state(o->self != nullptr, "the ops handle has no launch tables yet: apply it once with sgdg_apply_operator first");
+  Batch& B = *o->self;
+  const int k = map[kind_];
+  const int e = t == SGDG_F64 ? 0 : 1;
+  require_state(!B.kinds[k].host.empty() && B.kinds[k].it[e].built,
+                "launch tables of this operator kind and dtype are not built yet: apply it once with "
+                "sgdg_apply_operator first");
+  const size_t need = t == SGDG_F64 ? apply_scratch_bytes<double>(B, k, batch) : apply_scratch_bytes<float>(B, k, batch);
+  if (need > SGDG_NOALLOC_SCRATCH_BYTES) {
+    std::ostringstream m;
+    m << "the application needs " << need << " bytes of scratch; the allocation-free entry point holds "
+      << size_t(SGDG_NOALLOC_SCRATCH_BYTES) << " (use a smaller batch or sgdg_apply_operator)";
+    throw Error{SGDG_E_ARG, m.str()};
+  }
+  Carve c{scratch_ptr(), size_t(SGDG_NOALLOC_SCRATCH_BYTES), 0};
+  if (t == SGDG_F64) apply<double>(B, k, static_cast<const double*>(u_dev), static_cast<double*>(y_dev), batch, s, &c);
+  else apply<float>(B, k, static_cast<const float*>(u_dev), static_cast<float*>(y_dev), batch, s, &c);
   API_END
 }
 

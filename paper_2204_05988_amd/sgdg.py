@@ -27,7 +27,7 @@ EXPORTS = [
     "sgdg_net_create", "sgdg_net_shape", "sgdg_net_get_params", "sgdg_net_set_params", "sgdg_net_add_pairs",
     "sgdg_net_record", "sgdg_net_pair_count", "sgdg_net_train", "sgdg_net_apply", "sgdg_net_forward",
     "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune", "sgdg_set_launch",
-    "sgdg_graph_cache_size", "sgdg_debug_fallback", "sgdg_debug_grid_precond",
+    "sgdg_graph_cache_size", "sgdg_debug_fallback", "sgdg_debug_grid_precond", "sgdg_apply_operator_noalloc",
     "sgdg_batch_set_networks", "sgdg_vp_create", "sgdg_vp_info", "sgdg_vp_density", "sgdg_vp_field",
     "sgdg_vp_strip", "sgdg_vp_destroy",
 ]
@@ -122,6 +122,7 @@ def lib():
     L.sgdg_ops_destroy.argtypes = [vp]
     L.sgdg_ops_destroy.restype = None
     L.sgdg_apply_operator.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
+    L.sgdg_apply_operator_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
     L.sgdg_combine.argtypes = [vp, vp, vp, C.c_int, vp]
     L.sgdg_precondition.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.POINTER(PrecondOpts), vp]
     L.sgdg_rhs.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp]
@@ -321,6 +322,17 @@ class SparseGridOps:
         py = _dev(y, "y", batch * n, (str(u.dtype).replace("torch.", ""),))
         dt = F64 if u.dtype == torch.float64 else F32
         _check(lib().sgdg_apply_operator(self.ops, kind, pu, py, dt, batch, _stream(stream)))
+        return y
+
+    def apply_noalloc(self, u, y, kind=OP_FULL, batch=1, stream=None):
+        """The same operator through sgdg_apply_operator_noalloc (scratch from the
+        library's fixed device array; the tables must exist: apply() once first)."""
+        import torch
+        n = self.ndof // self.R if kind == OP_MASS else self.ndof
+        pu = _dev(u, "u", batch * n, ("float64", "float32"))
+        py = _dev(y, "y", batch * n, (str(u.dtype).replace("torch.", ""),))
+        dt = F64 if u.dtype == torch.float64 else F32
+        _check(lib().sgdg_apply_operator_noalloc(self.ops, kind, pu, py, dt, batch, _stream(stream)))
         return y
 
     def combine(self, nodal, coef, nslices, stream=None):
