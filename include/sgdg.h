@@ -129,6 +129,25 @@ typedef struct sgdg_ops_s* sgdg_ops;
  * needs beta's component to be one separable term (it is by construction).
  * The grid must outlive the ops handle. */
 sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out);
+/* Coefficients that depend on time (Sect. 4.2, the block formula with an
+ * m-point time quadrature): beta and sigma given at the points tau[mu] of the
+ * strip's reference interval [-1, 1] (t = t_{j-1} + dt (tau + 1) / 2), as
+ * at[mu] (same structure at every point), with weights weight[mu] summing to
+ * 2.  Each point contributes the spatial factors of its coefficients times the
+ * time matrices w_mu eta_s'(tau_mu) eta_s(tau_mu) and their derivative forms;
+ * the operator is the strip's (build one per strip).  dt and delta are taken
+ * from at[0] and must agree at every point. */
+typedef struct {
+  int m;                    /* quadrature points, 1..8 */
+  const double* tau;        /* [m] points in [-1, 1] */
+  const double* weight;     /* [m] weights on [-1, 1] */
+  const sgdg_problem* at;   /* [m] coefficients at each point */
+} sgdg_problem_t;
+
+/* As sgdg_assemble_1d_factors for time-dependent coefficients.  SGDG_E_ARG on
+ * m outside 1..8, points outside [-1, 1], weights not summing to 2, or
+ * dt / delta differing between points. */
+sgdg_status sgdg_assemble_factors_t(sgdg_grid g, const sgdg_problem_t* p, sgdg_ops* out);
 void sgdg_ops_destroy(sgdg_ops o);
 
 /* -------------------------------------------------------------- operators -- */

@@ -482,9 +482,7 @@ static void invert_small(int R, const double* A, double* inv) {
   std::memcpy(inv, b, sizeof(double) * R * R);
 }
 
-extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out) {
-  API_BEGIN
-  require(g && p && out, "null argument");
+static void check_problem(const sgdg_grid g, const sgdg_problem* p) {
   require(p->dt > 0 && p->delta >= 0, "dt must be > 0 and delta >= 0");
   const int d = g->x.d;
   for (int c = 0; c < 2 * d; ++c)
@@ -498,6 +496,12 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   for (int t = 0; t < p->n_sigma; ++t)
     require(p->sigma[t].n_xf >= 0 && p->sigma[t].n_vf >= 0 && p->sigma[t].n_xf <= 2 && p->sigma[t].n_vf <= 2,
             "each sigma term may carry at most two field factors per domain");
+}
+
+// Factor tables, term lists and uploads of one strip operator; `terms` fills
+// the four term lists (registering the factors it uses).
+template <class F>
+static sgdg_ops assemble_ops(sgdg_grid g, double dt, double delta, F&& terms) {
   std::unique_ptr<sgdg_ops_s> o(new sgdg_ops_s);
   o->grid = g;
   SGDG_CHECK_HIP(hipGetDevice(&o->device));
@@ -509,7 +513,7 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
     build_domain_tables(D);
   }
   TermList tl[4];
-  build_terms(o->X, o->V, *p, g->r, tl);
+  terms(o->X, o->V, tl);
   // the plain mass factor drives the inner preconditioner
   FactorKey mk;
   mk.kind = kMass;
@@ -541,10 +545,37 @@ extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem*
   // inner preconditioner time block (Tt + delta Ct + Gt)^-1
   const int R = g->R;
   double Mt[9], Tt[9], Ct[9], Gt[9], P[9];
-  time_matrices(g->r, p->dt, Mt, Tt, Ct, Gt);
-  for (int i = 0; i < R * R; ++i) P[i] = Tt[i] + p->delta * Ct[i] + Gt[i];
+  time_matrices(g->r, dt, Mt, Tt, Ct, Gt);
+  for (int i = 0; i < R * R; ++i) P[i] = Tt[i] + delta * Ct[i] + Gt[i];
   invert_small(R, P, o->pinv);
-  *out = o.release();
+  return o.release();
+}
+
+extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out) {
+  API_BEGIN
+  require(g && p && out, "null argument");
+  check_problem(g, p);
+  *out = assemble_ops(g, p->dt, p->delta,
+                      [&](DomainData& X, DomainData& V, TermList* tl) { build_terms(X, V, *p, g->r, tl); });
+  API_END
+}
+
+extern "C" sgdg_status sgdg_assemble_factors_t(sgdg_grid g, const sgdg_problem_t* p, sgdg_ops* out) {
+  API_BEGIN
+  require(g && p && out && p->tau && p->weight && p->at, "null argument");
+  require(p->m >= 1 && p->m <= 8, "m must be 1..8");
+  double wsum = 0;
+  for (int mu = 0; mu < p->m; ++mu) {
+    require(p->tau[mu] >= -1.0 && p->tau[mu] <= 1.0, "quadrature points must lie in [-1, 1]");
+    check_problem(g, &p->at[mu]);
+    require(p->at[mu].dt == p->at[0].dt && p->at[mu].delta == p->at[0].delta,
+            "dt and delta must agree at every quadrature point");
+    wsum += p->weight[mu];
+  }
+  require(std::fabs(wsum - 2.0) <= 1e-12, "quadrature weights must sum to 2 (the reference interval [-1, 1])");
+  *out = assemble_ops(g, p->at[0].dt, p->at[0].delta, [&](DomainData& X, DomainData& V, TermList* tl) {
+    build_terms_t(X, V, p->at, p->tau, p->weight, p->m, g->r, tl);
+  });
   API_END
 }
 

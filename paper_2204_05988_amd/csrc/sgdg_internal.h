@@ -135,6 +135,11 @@ struct ProblemIn {
 };
 // Builds the operator term lists: 0 FULL, 1 MASS, 2 DATA_F, 3 DATA_G. Registers factors.
 void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, TermList out[4]);
+// The same for coefficients given at m time-quadrature points tau (reference
+// interval [-1, 1], weights wref summing to 2): at[mu] holds beta and sigma at
+// tau[mu]; dt and delta from at[0].
+void build_terms_t(DomainData& X, DomainData& V, const sgdg_problem* at, const double* tau, const double* wref, int m,
+                   int r, TermList out[4]);
 void time_matrices(int r, double dt, double Mt[], double Tt[], double Ct[], double Gt[]);
 
 // ------------------------------------------------------ device descriptors --

@@ -100,15 +100,19 @@ bool weight_zero(const DomainData& D, const Weight& w) {
 
 }  // namespace
 
-void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, TermList out[4]) {
-  const int d = X.dom.d;
-  const int R = r + 1;
-  const int64_t nx = X.L(X.lmax).n, nv = V.L(V.lmax).n;
-  const double dl = p.delta;
+namespace {
 
+// The spatial operators of one coefficient set as Kronecker lists.
+struct Spatial {
   std::vector<KTerm> M, T, C, K, Kt, Gm;
+};
+
+Spatial spatial_terms(DomainData& X, DomainData& V, const sgdg_problem& p) {
+  const int d = X.dom.d;
+  const int64_t nx = X.L(X.lmax).n, nv = V.L(V.lmax).n;
+  Spatial S;
   const Weight one;
-  M.push_back({1.0, key(kMass, one), key(kMass, one)});
+  S.M.push_back({1.0, key(kMass, one), key(kMass, one)});
 
   std::vector<Weight> A(2 * d), B(2 * d);
   std::vector<double> sc(2 * d, 0.0);
@@ -122,8 +126,8 @@ void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, Ter
   }
   for (int c = 0; c < 2 * d; ++c) {
     if (!has[c]) continue;
-    if (c < d) T.push_back({sc[c], key(kDeriv, A[c], c), key(kMass, B[c])});
-    else T.push_back({sc[c], key(kMass, A[c]), key(kDeriv, B[c], c - d)});
+    if (c < d) S.T.push_back({sc[c], key(kDeriv, A[c], c), key(kMass, B[c])});
+    else S.T.push_back({sc[c], key(kMass, A[c]), key(kDeriv, B[c], c - d)});
   }
   for (int c = 0; c < 2 * d; ++c)
     for (int c2 = 0; c2 < 2 * d; ++c2) {
@@ -144,18 +148,18 @@ void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, Ter
         fx = key(kMass, wa);
         fv = key(kStiff, wb, c - d, c2 - d);
       }
-      C.push_back({sc[c] * sc[c2], fx, fv});
+      S.C.push_back({sc[c] * sc[c2], fx, fv});
     }
   for (int t = 0; t < p.n_sigma; ++t) {
     const sgdg_separable* s = &p.sigma[t];
     const Weight P = plain(X, s, true, nx), Q = plain(V, s, false, nv);
-    K.push_back({s->scale, key(kMass, P), key(kMass, Q)});
+    S.K.push_back({s->scale, key(kMass, P), key(kMass, Q)});
     for (int c = 0; c < 2 * d; ++c) {
       if (!has[c]) continue;
       const Weight wa = concat(P, A[c]), wb = concat(Q, B[c]);
       // (sigma phi', beta_c d_c phi)
-      if (c < d) Kt.push_back({s->scale * sc[c], tr(key(kDeriv, wa, c)), key(kMass, wb)});
-      else Kt.push_back({s->scale * sc[c], key(kMass, wa), tr(key(kDeriv, wb, c - d))});
+      if (c < d) S.Kt.push_back({s->scale * sc[c], tr(key(kDeriv, wa, c)), key(kMass, wb)});
+      else S.Kt.push_back({s->scale * sc[c], key(kMass, wa), tr(key(kDeriv, wb, c - d))});
     }
   }
   for (int side_dom = 0; side_dom < 2; ++side_dom) {  // 0: faces of Omega_x, 1: faces of Omega_v
@@ -173,75 +177,157 @@ void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, Ter
           wb.scale = 1.0;
           wb.kink = pass == 0 ? 2 : 1;
           if (weight_zero(X, wa) || weight_zero(V, wb)) continue;
-          if (side_dom == 0) Gm.push_back({1.0, key(kFace, wa, -1, -1, axis, side), key(kMass, wb)});
-          else Gm.push_back({1.0, key(kMass, wa), key(kFace, wb, -1, -1, axis, side)});
+          if (side_dom == 0) S.Gm.push_back({1.0, key(kFace, wa, -1, -1, axis, side), key(kMass, wb)});
+          else S.Gm.push_back({1.0, key(kMass, wa), key(kFace, wb, -1, -1, axis, side)});
         }
       }
     }
   }
+  return S;
+}
 
+// Appends scale * tm (x) ops to L (terms with the same factor pair merge).
+void add_terms(DomainData& X, DomainData& V, TermList& L, const double* tm, double scale,
+               const std::vector<KTerm>& ops, bool transpose) {
+  bool nz = false;
+  for (int i = 0; i < L.Rout * L.Rin; ++i) nz = nz || tm[i] != 0.0;
+  if (!nz || scale == 0.0) return;
+  for (const KTerm& k : ops) {
+    Term t;
+    const FactorKey fx = transpose ? tr(k.X) : k.X;
+    const FactorKey fv = transpose ? tr(k.V) : k.V;
+    t.xf = X.factor_id(fx);
+    t.vf = V.factor_id(fv);
+    for (int i = 0; i < L.Rout * L.Rin; ++i) t.tm[i] = scale * k.c * tm[i];
+    bool merged = false;
+    for (Term& e : L.terms)
+      if (e.xf == t.xf && e.vf == t.vf) {
+        for (int i = 0; i < L.Rout * L.Rin; ++i) e.tm[i] += t.tm[i];
+        merged = true;
+        break;
+      }
+    if (!merged) L.terms.push_back(t);
+  }
+}
+
+double legendre_val(int s, double z, double* deriv) {
+  // P_s(z) and P_s'(z) by the three-term recurrence
+  double p0 = 1, p1 = z, d0 = 0, d1 = 1;
+  if (s == 0) {
+    *deriv = 0;
+    return 1;
+  }
+  for (int k = 1; k < s; ++k) {
+    const double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+    const double d2 = ((2 * k + 1) * (p1 + z * d1) - k * d0) / (k + 1);
+    p0 = p1;
+    p1 = p2;
+    d0 = d1;
+    d1 = d2;
+  }
+  *deriv = d1;
+  return p1;
+}
+
+void init_lists(TermList out[4], int R) {
+  out[0].Rin = out[0].Rout = R;
+  out[1].Rin = out[1].Rout = 1;
+  out[2].Rin = out[2].Rout = R;
+  out[3].Rin = out[3].Rout = R;
+  for (int k = 0; k < 4; ++k) out[k].terms.clear();
+}
+
+}  // namespace
+
+void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, TermList out[4]) {
+  const int R = r + 1;
+  const double dl = p.delta;
+  const Spatial S = spatial_terms(X, V, p);
   double Mt[9], Tt[9], Ct[9], Gt[9], TtT[9];
   time_matrices(r, p.dt, Mt, Tt, Ct, Gt);
   for (int s = 0; s < R; ++s)
     for (int q = 0; q < R; ++q) TtT[s * R + q] = Tt[q * R + s];
-
-  auto add = [&](TermList& L, const double* tm, double scale, const std::vector<KTerm>& ops, bool transpose) {
-    bool nz = false;
-    for (int i = 0; i < L.Rout * L.Rin; ++i) nz = nz || tm[i] != 0.0;
-    if (!nz || scale == 0.0) return;
-    for (const KTerm& k : ops) {
-      Term t;
-      const FactorKey fx = transpose ? tr(k.X) : k.X;
-      const FactorKey fv = transpose ? tr(k.V) : k.V;
-      t.xf = X.factor_id(fx);
-      t.vf = V.factor_id(fv);
-      for (int i = 0; i < L.Rout * L.Rin; ++i) t.tm[i] = scale * k.c * tm[i];
-      // merge with an existing (xf, vf) pair
-      bool merged = false;
-      for (Term& e : L.terms)
-        if (e.xf == t.xf && e.vf == t.vf) {
-          for (int i = 0; i < L.Rout * L.Rin; ++i) e.tm[i] += t.tm[i];
-          merged = true;
-          break;
-        }
-      if (!merged) L.terms.push_back(t);
-    }
-  };
-
+  init_lists(out, R);
   // FULL
   TermList& F = out[0];
-  F.Rin = F.Rout = R;
-  F.terms.clear();
   double P0[9];
   for (int i = 0; i < R * R; ++i) P0[i] = Tt[i] + dl * Ct[i] + Gt[i];
-  add(F, P0, 1.0, M, false);
-  add(F, Tt, dl, T, true);
-  add(F, TtT, dl, T, false);
-  add(F, TtT, dl, K, false);
-  add(F, Mt, 1.0, T, false);
-  add(F, Mt, dl, C, false);
-  add(F, Mt, 1.0, K, false);
-  add(F, Mt, dl, Kt, false);
-  add(F, Mt, 1.0, Gm, false);
+  add_terms(X, V, F, P0, 1.0, S.M, false);
+  add_terms(X, V, F, Tt, dl, S.T, true);
+  add_terms(X, V, F, TtT, dl, S.T, false);
+  add_terms(X, V, F, TtT, dl, S.K, false);
+  add_terms(X, V, F, Mt, 1.0, S.T, false);
+  add_terms(X, V, F, Mt, dl, S.C, false);
+  add_terms(X, V, F, Mt, 1.0, S.K, false);
+  add_terms(X, V, F, Mt, dl, S.Kt, false);
+  add_terms(X, V, F, Mt, 1.0, S.Gm, false);
   // MASS
-  TermList& Ms = out[1];
-  Ms.Rin = Ms.Rout = 1;
-  Ms.terms.clear();
   const double one1[1] = {1.0};
-  add(Ms, one1, 1.0, M, false);
+  add_terms(X, V, out[1], one1, 1.0, S.M, false);
   // DATA_F
-  TermList& Df = out[2];
-  Df.Rin = Df.Rout = R;
-  Df.terms.clear();
   double P1[9];
   for (int i = 0; i < R * R; ++i) P1[i] = Mt[i] + dl * TtT[i];
-  add(Df, P1, 1.0, M, false);
-  add(Df, Mt, dl, T, true);
+  add_terms(X, V, out[2], P1, 1.0, S.M, false);
+  add_terms(X, V, out[2], Mt, dl, S.T, true);
   // DATA_G
-  TermList& Dg = out[3];
-  Dg.Rin = Dg.Rout = R;
-  Dg.terms.clear();
-  add(Dg, Mt, 1.0, Gm, false);
+  add_terms(X, V, out[3], Mt, 1.0, S.Gm, false);
+}
+
+// Coefficients that depend on time (Sect. 4.2, the block formula with an
+// m-point time quadrature): per point mu the spatial factors of the
+// coefficients at tau_mu and the time matrices w_mu eta_s'(tau_mu) eta_s(tau_mu)
+// (M_mu), w_mu eta'_s'(tau_mu) eta_s(tau_mu) (T_mu), w_mu eta'_s' eta'_s (C_mu):
+//   A = G^t (x) M + sum_mu [ (T_mu + delta C_mu) (x) M + delta T_mu (x) T_mu^T
+//       + delta T_mu^T (x) (T_mu + K_mu) + M_mu (x) (T_mu + delta C_mu + K_mu + delta K~_mu - G_mu) ],
+// and the data functionals (M^t + delta T^t^T) (x) M + sum_mu delta M_mu (x) T_mu^T
+// and sum_mu M_mu (x) (-G_mu).
+void build_terms_t(DomainData& X, DomainData& V, const sgdg_problem* at, const double* tau, const double* wref, int m,
+                   int r, TermList out[4]) {
+  const int R = r + 1;
+  const double dt = at[0].dt, dl = at[0].delta;
+  double Mt[9], Tt[9], Ct[9], Gt[9], TtT[9];
+  time_matrices(r, dt, Mt, Tt, Ct, Gt);
+  for (int s = 0; s < R; ++s)
+    for (int q = 0; q < R; ++q) TtT[s * R + q] = Tt[q * R + s];
+  init_lists(out, R);
+  const Spatial S0 = spatial_terms(X, V, at[0]);
+  add_terms(X, V, out[0], Gt, 1.0, S0.M, false);
+  const double one1[1] = {1.0};
+  add_terms(X, V, out[1], one1, 1.0, S0.M, false);
+  double P1[9];
+  for (int i = 0; i < R * R; ++i) P1[i] = Mt[i] + dl * TtT[i];
+  add_terms(X, V, out[2], P1, 1.0, S0.M, false);
+  for (int mu = 0; mu < m; ++mu) {
+    const Spatial S = spatial_terms(X, V, at[mu]);
+    double e[kMaxR], de[kMaxR];
+    for (int s = 0; s < R; ++s) {
+      double dp;
+      e[s] = legendre_val(s, tau[mu], &dp);
+      de[s] = dp * 2.0 / dt;
+    }
+    const double w = wref[mu] * dt / 2.0;
+    double Mm[9], Tm[9], Cm[9], TmT[9], P0[9];
+    for (int s = 0; s < R; ++s)
+      for (int q = 0; q < R; ++q) {
+        Mm[s * R + q] = w * e[q] * e[s];
+        Tm[s * R + q] = w * de[q] * e[s];
+        Cm[s * R + q] = w * de[q] * de[s];
+        TmT[s * R + q] = w * de[s] * e[q];
+      }
+    for (int i = 0; i < R * R; ++i) P0[i] = Tm[i] + dl * Cm[i];
+    TermList& F = out[0];
+    add_terms(X, V, F, P0, 1.0, S.M, false);
+    add_terms(X, V, F, Tm, dl, S.T, true);
+    add_terms(X, V, F, TmT, dl, S.T, false);
+    add_terms(X, V, F, TmT, dl, S.K, false);
+    add_terms(X, V, F, Mm, 1.0, S.T, false);
+    add_terms(X, V, F, Mm, dl, S.C, false);
+    add_terms(X, V, F, Mm, 1.0, S.K, false);
+    add_terms(X, V, F, Mm, dl, S.Kt, false);
+    add_terms(X, V, F, Mm, 1.0, S.Gm, false);
+    add_terms(X, V, out[2], Mm, dl, S.T, true);
+    add_terms(X, V, out[3], Mm, 1.0, S.Gm, false);
+  }
 }
 
 }  // namespace sgdg

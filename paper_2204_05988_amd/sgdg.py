@@ -29,7 +29,7 @@ EXPORTS = [
     "sgdg_net_backward", "sgdg_net_destroy", "sgdg_tune", "sgdg_batch_tune", "sgdg_set_launch",
     "sgdg_graph_cache_size", "sgdg_debug_fallback", "sgdg_debug_grid_precond", "sgdg_apply_operator_noalloc",
     "sgdg_batch_set_networks", "sgdg_vp_create", "sgdg_vp_info", "sgdg_vp_density", "sgdg_vp_field",
-    "sgdg_vp_strip", "sgdg_vp_destroy",
+    "sgdg_vp_strip", "sgdg_vp_destroy", "sgdg_assemble_factors_t",
 ]
 
 
@@ -51,6 +51,11 @@ class Separable(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("beta", C.POINTER(Separable) * 6), ("n_sigma", C.c_int), ("sigma", C.POINTER(Separable)),
                 ("dt", C.c_double), ("delta", C.c_double)]
+
+
+class ProblemT(C.Structure):
+    _fields_ = [("m", C.c_int), ("tau", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double)),
+                ("at", C.POINTER(Problem))]
 
 
 class PrecondOpts(C.Structure):
@@ -119,6 +124,7 @@ def lib():
     L.sgdg_grid_destroy.argtypes = [vp]
     L.sgdg_grid_destroy.restype = None
     L.sgdg_assemble_1d_factors.argtypes = [vp, C.POINTER(Problem), C.POINTER(vp)]
+    L.sgdg_assemble_factors_t.argtypes = [vp, C.POINTER(ProblemT), C.POINTER(vp)]
     L.sgdg_ops_destroy.argtypes = [vp]
     L.sgdg_ops_destroy.restype = None
     L.sgdg_apply_operator.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.c_int, vp]
@@ -270,8 +276,10 @@ def default_solve_opts(rtol=1e-8, restart=50, maxit=400, mixed=False, inner_oute
 class SparseGridOps:
     """One strip operator of a workload on the current HIP device."""
 
-    def __init__(self, w, fields=None):
-        from workloads import nodal_fields
+    def __init__(self, w, fields=None, t0=0.0):
+        """w.tfields set: coefficients that depend on time, sampled at the w.tquad
+        (default r + 2) Gauss-Legendre points of the strip [t0, t0 + dt]."""
+        from workloads import lattice_coords, nodal_fields
         L = lib()
         self.w = w
         self.R = w.r + 1
@@ -280,9 +288,24 @@ class SparseGridOps:
         g = C.c_void_p()
         _check(L.sgdg_build_sparse_grid(C.byref(self._dx), C.byref(self._dv), w.lmin, w.L, w.r, C.byref(g)))
         self.grid = g
-        self.prob = _ProblemHolder(w, fx, fv)
         o = C.c_void_p()
-        _check(L.sgdg_assemble_1d_factors(g, C.byref(self.prob.p), C.byref(o)))
+        if w.tfields is None:
+            self.prob = _ProblemHolder(w, fx, fv)
+            _check(L.sgdg_assemble_1d_factors(g, C.byref(self.prob.p), C.byref(o)))
+        else:
+            m = w.tquad if w.tquad else w.r + 2
+            tau, wts = np.polynomial.legendre.leggauss(m)
+            X, V = lattice_coords(w.x, w.L), lattice_coords(w.v, w.L)
+            self.prob = []
+            for t in t0 + 0.5 * w.dt * (tau + 1.0):
+                xf, vf = w.tfields(t)
+                self.prob.append(_ProblemHolder(w, {k: fn(X) for k, fn in xf.items()},
+                                                {k: fn(V) for k, fn in vf.items()}))
+            at = (Problem * m)(*[h.p for h in self.prob])
+            self._t = (np.ascontiguousarray(tau), np.ascontiguousarray(wts), at)
+            pt = ProblemT(m, self._t[0].ctypes.data_as(C.POINTER(C.c_double)),
+                          self._t[1].ctypes.data_as(C.POINTER(C.c_double)), C.cast(at, C.POINTER(Problem)))
+            _check(L.sgdg_assemble_factors_t(g, C.byref(pt), C.byref(o)))
         self.ops = o
         self.upper = self.info(0)
         self.lower = self.info(1)

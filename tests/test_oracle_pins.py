@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from workloads import (Domain, Workload, config_c1, config_table1, config_tiny, grid_levels,
-                       lattice_coords)
+from workloads import (Domain, Workload, config_c1, config_table1, config_tiny, config_timedep_exact,
+                       grid_levels, lattice_coords, with_time_fields)
 from oracle.brute import Brute
 from oracle.ct import CTPreconditioner
 from oracle.fe import assemble
@@ -569,3 +569,51 @@ def test_exact_grid_preconditioner_inverts_its_factors(kind):
     g = P.upper[-1]
     U = np.ones((P.R, P.nx(g[0]), P.nv(g[1])))
     assert np.abs(gridprec.grid_precond(P, g, U, 0) - gridprec.grid_precond(P, g, U, -1)).max() > 1e-3
+
+
+# --- Sect. 4.2: coefficients that depend on time (m-point time quadrature) -------------
+
+@pytest.mark.parametrize("kind", ["d1", "d2"])
+def test_time_quadrature_of_constant_fields_is_the_constant_operator(kind):
+    """Coefficients that do not change in time: the quadrature form (per-point factors and
+    time matrices) equals the closed-form time blocks, for the operator and both data
+    functionals (a wrong weight, point or transposed time matrix breaks it)."""
+    w = config_tiny(kind)
+    P = Problem(w)
+    wt = with_time_fields(config_tiny(kind), lambda t, w=w: (dict(w.xfields), dict(w.vfields)))
+    Pt = Problem(wt, t0=0.3)
+    u = np.random.default_rng(6).standard_normal(P.ndof)
+    for a, b in ((P.apply(u), Pt.apply(u)), (P.apply(u, P.data_terms()), Pt.apply(u, Pt.data_terms())),
+                 (P.apply(u, P.inflow_data_terms()), Pt.apply(u, Pt.inflow_data_terms()))):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("d,r,L", [(1, 1, 4), (2, 1, 2)])
+def test_time_dependent_discrete_exact_solution(d, r, L):
+    w = config_timedep_exact(d, r, L)
+    u_prev, R_prev = None, 1
+    for j in (1, 2):
+        P = Problem(w, t0=(j - 1) * w.dt)
+        if u_prev is None:
+            u_prev = strip.initial_coefficients(P)
+        b = strip.rhs(P, j, u_prev, R_prev)
+        U, st = fgmres(P.apply, b, CTPreconditioner(P), tol=1e-13, restart=50, maxit=200)
+        assert st["rel"] <= 1e-12
+        ref = _legendre_slices(P, w.exact, (j - 1) * w.dt, w.dt, P.R)
+        blocks = P.split(U)
+        err2 = ref2 = 0.0
+        for s in range(P.R):
+            us = np.concatenate([bb[s].ravel() for bb in blocks])
+            e = us - ref[s]
+            err2 += abs(e @ P.apply_mass(e))
+            ref2 += abs(ref[s] @ P.apply_mass(ref[s]))
+        assert np.sqrt(err2 / ref2) < 1e-10, (j, np.sqrt(err2 / ref2))
+        u_prev, R_prev = U, P.R
+    # frozen at the strip's start instead, the coefficients miss the exact solution
+    w2 = config_timedep_exact(d, r, L)
+    w2.tfields = None
+    xf, vf = w.tfields(w.dt)
+    w2.xfields = xf
+    P2 = Problem(w2)
+    b = strip.rhs(Problem(w, t0=w.dt), 2, u_prev, P2.R)
+    assert np.linalg.norm(P2.apply(U) - b) > 1e-4 * np.linalg.norm(b)

@@ -25,7 +25,8 @@ __all__ = [
     "Domain", "Workload", "lattice_shape", "lattice_coords", "nodal_fields",
     "grid_levels", "gauss_legendre_times", "random_vector", "sample_on_grids",
     "config_c1", "config_c2", "config_c3", "config_c4_member", "config_c4",
-    "config_c5", "config_table1", "config_tiny", "config_landau", "h_min",
+    "config_c5", "config_table1", "config_tiny", "config_landau", "config_timedep_exact",
+    "with_time_fields", "h_min",
 ]
 
 
@@ -209,9 +210,11 @@ def config_c3(seed: int = 0, L: int = 6) -> Workload:
         sigma=[], xfields={}, vfields={f"v{i}": _coord(i) for i in range(3)}, seed=seed)
 
 
-def config_c4_member(i: int, seed: int = 0, L: Optional[int] = None) -> Workload:
+def config_c4_member(i: int, seed: int = 0, L: Optional[int] = None, tvary: float = 0.0) -> Workload:
     """One of the 64 batched 4D problems: beta=(v, a_i), sigma_i, Fourier forcing.
-    L overrides the drawn level (smaller members for parity tests)."""
+    L overrides the drawn level (smaller members for parity tests).  tvary > 0 makes
+    the coefficients depend on time: a_i + tvary b_i t and sigma_i (1 + tvary sin(2 pi t)),
+    b_i ~ U[-1, 1]^2 (drawn after everything else, so the other draws are unchanged)."""
     rng = np.random.default_rng([seed, i])
     L_drawn = int(rng.integers(5, 8))
     L = L_drawn if L is None else int(L)
@@ -235,12 +238,27 @@ def config_c4_member(i: int, seed: int = 0, L: Optional[int] = None) -> Workload
             out = out + amp * np.cos(2 * np.pi * (X @ k[:2]) + np.pi * (V @ k[2:]) + th)
         return out
 
+    if tvary <= 0.0:
+        return Workload(
+            name=f"c4_member{i}_L{L}", x=x, v=v, lmin=0, L=L, r=1, dt=1.0 / 64,
+            delta=0.5 * h_min(x, v, L), nstrips=4,
+            beta=[(1.0, (), ("v0",)), (1.0, (), ("v1",)), (float(a[0]), (), ()), (float(a[1]), (), ())],
+            sigma=[(sig, (), ())], xfields={}, vfields={"v0": _coord(0), "v1": _coord(1)},
+            u0=None, f=forcing, g=None, seed=seed)
+    b = rng.uniform(-1.0, 1.0, size=2)
+
+    def consts(t):
+        vals = {"a0": a[0] + tvary * b[0] * t, "a1": a[1] + tvary * b[1] * t,
+                "s": sig * (1.0 + tvary * np.sin(2 * np.pi * t))}
+        return {k: (lambda P, c=c: np.full(len(P), c)) for k, c in vals.items()}
+
+    vf = {"v0": _coord(0), "v1": _coord(1)}
     return Workload(
-        name=f"c4_member{i}_L{L}", x=x, v=v, lmin=0, L=L, r=1, dt=1.0 / 64,
+        name=f"c4_member{i}_L{L}_t", x=x, v=v, lmin=0, L=L, r=1, dt=1.0 / 64,
         delta=0.5 * h_min(x, v, L), nstrips=4,
-        beta=[(1.0, (), ("v0",)), (1.0, (), ("v1",)), (float(a[0]), (), ()), (float(a[1]), (), ())],
-        sigma=[(sig, (), ())], xfields={}, vfields={"v0": _coord(0), "v1": _coord(1)},
-        u0=None, f=forcing, g=None, seed=seed)
+        beta=[(1.0, (), ("v0",)), (1.0, (), ("v1",)), (1.0, ("a0",), ()), (1.0, ("a1",), ())],
+        sigma=[(1.0, ("s",), ())], xfields=consts(0.0), vfields=vf,
+        u0=None, f=forcing, g=None, seed=seed, tfields=lambda t: (consts(t), dict(vf)))
 
 
 def config_c4(seed: int = 0, n: int = 64):
@@ -328,6 +346,67 @@ def config_landau(d: int = 1, paper_level: int = 5, r: int = 1, dt: float = 0.5,
         xfields={f"E{i}": (lambda P, i=i: Ef[i].copy()) for i in range(d)},
         vfields={f"v{i}": _coord(i) for i in range(d)},
         u0=f0, f=None, g=None, exact=None)
+
+
+def with_time_fields(w: Workload, tfields, tquad: int = 0) -> Workload:
+    """The workload with coefficients given as functions of time (tfields: t -> fields)."""
+    w.tfields = tfields
+    w.tquad = tquad
+    return w
+
+
+def config_timedep_exact(d: int, r: int, L: int) -> Workload:
+    """u = p(x, v) + q t affine in space with beta_v moving in time: beta = (v, c0 + c1 x + c2 t)
+    (d = 1) or (v, a + b t) (d = 2); f = d_t u + beta.grad u + sigma u and g = u lie in the
+    discrete space, so every strip reproduces u (consistency and uniqueness, as for
+    constant coefficients), provided the time quadrature integrates the degree-4
+    integrands exactly (r + 2 Gauss points)."""
+    sig = 0.3
+    qt = 0.7 if r >= 1 else 0.0
+    if d == 1:
+        x = Domain(1, (0.0,), (1.0,))
+        v = Domain(1, (-1.0,), (1.0,))
+        c0, c1, c2 = 0.5, 0.8, 0.9
+
+        def u(t, X, V):
+            return 1.0 + 0.6 * X[..., 0] - 0.9 * V[..., 0] + qt * t
+
+        def f(t, X, V):
+            return qt + 0.6 * V[..., 0] + (c0 + c1 * X[..., 0] + c2 * t) * (-0.9) + sig * u(t, X, V)
+
+        def tf(t):
+            return {"c": lambda P, t=t: c0 + c1 * P[:, 0] + c2 * t}, {"v0": lambda P: P[:, 0].copy()}
+
+        w = Workload(name="exact_t_d1", x=x, v=v, lmin=1, L=L, r=r, dt=0.05, delta=0.04, nstrips=2,
+                     beta=[(1.0, (), ("v0",)), (1.0, ("c",), ())], sigma=[(sig, (), ())],
+                     xfields={"c": lambda P: c0 + c1 * P[:, 0]}, vfields={"v0": lambda P: P[:, 0].copy()},
+                     u0=lambda X, V: u(0.0, X, V), f=f, g=u, exact=u)
+        return with_time_fields(w, tf)
+    x = Domain(2, (0.0, 0.0), (1.0, 1.0))
+    v = Domain(2, (-1.0, -1.0), (1.0, 1.0))
+    a = np.array([0.5, -0.3])
+    bt = np.array([0.6, 0.4])
+    bx = np.array([0.4, -0.7])
+    cv = np.array([0.2, 0.5])
+
+    def u(t, X, V):
+        return 1.0 + X @ bx + V @ cv + qt * t
+
+    def f(t, X, V):
+        return qt + V @ bx + float(cv @ (a + bt * t)) + sig * u(t, X, V)
+
+    def tf(t):
+        return ({"a0": lambda P, t=t: np.full(len(P), a[0] + bt[0] * t),
+                 "a1": lambda P, t=t: np.full(len(P), a[1] + bt[1] * t)},
+                {"v0": lambda P: P[:, 0].copy(), "v1": lambda P: P[:, 1].copy()})
+
+    w = Workload(name="exact_t_d2", x=x, v=v, lmin=0, L=L, r=r, dt=0.05, delta=0.05, nstrips=2,
+                 beta=[(1.0, (), ("v0",)), (1.0, (), ("v1",)), (1.0, ("a0",), ()), (1.0, ("a1",), ())],
+                 sigma=[(sig, (), ())],
+                 xfields={"a0": lambda P: np.full(len(P), a[0]), "a1": lambda P: np.full(len(P), a[1])},
+                 vfields={"v0": lambda P: P[:, 0].copy(), "v1": lambda P: P[:, 1].copy()},
+                 u0=lambda X, V: u(0.0, X, V), f=f, g=u, exact=u)
+    return with_time_fields(w, tf)
 
 
 def config_tiny(kind: str) -> Workload:
