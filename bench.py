@@ -544,10 +544,20 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
                                               pc=sgdg.default_precond_opts(net=net, inner_maxit=10))
     learned_inexact_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
                                                     pc=sgdg.default_precond_opts(net=net, inner_maxit=10))
+    # the grid problems preconditioned by the x-transport inverse (periodic x, FFT) instead of
+    # the mass diagonals: exact CT at a fraction of the inner iterations
+    ct_transport = sgdg.default_solve_opts(rtol=1e-8, maxit=400, pc=sgdg.default_precond_opts(mass_sweeps=-2))
+    ct_transport_mixed = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                                 pc=sgdg.default_precond_opts(mass_sweeps=-2))
+    learned_transport = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                                pc=sgdg.default_precond_opts(net=net, mass_sweeps=-2))
     for j in range(record_strips + 1, record_strips + test_strips + 1):
         b = ops.rhs(u, prev)
         row = {"strip": j}
         x, row["ct_fp64"] = _timed_solve(ops, b, ct)
+        _, row["ct_transport_fp64"] = _timed_solve(ops, b, ct_transport)
+        _, row["ct_transport_mixed"] = _timed_solve(ops, b, ct_transport_mixed)
+        _, row["learned_transport_fallback_mixed"] = _timed_solve(ops, b, learned_transport)
         _, row["learned_fp64"] = _timed_solve(ops, b, learned)
         _, row["learned_mixed"] = _timed_solve(ops, b, learned_mixed)
         _, row["ct_inexact_fp64"] = _timed_solve(ops, b, ct_inexact)
@@ -556,7 +566,9 @@ def learned_leg(dev, train_steps, L=7, record_strips=8, test_strips=2):
         t0 = row["ct_fp64"]["seconds"]
         row["gain_vs_ct_fp64"] = {k: round(t0 / row[k]["seconds"], 3)
                                   for k in ("learned_fp64", "learned_mixed", "ct_inexact_fp64",
-                                            "learned_inexact_fallback_fp64", "learned_inexact_fallback_mixed")}
+                                            "learned_inexact_fallback_fp64", "learned_inexact_fallback_mixed",
+                                            "ct_transport_fp64", "ct_transport_mixed",
+                                            "learned_transport_fallback_mixed")}
         out["strips"].append(row)
         _log(f"learned leg: {row}")
         u = x
@@ -620,15 +632,17 @@ def batched_learned_leg(dev, n=4, L=7, record_strips=8, train_steps=500):
                      "fallback": st.fallback_used, "pc_applications": st.pc_applications,
                      "max_rel_residual": st.rel_residual, "speedup_vs_plain_fp64": round(seq / el, 3)}
         _log(f"batched learned leg: {name} {out[name]}")
-    opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True)
-    batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _, st = batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    out["batched_ct_mixed"] = {"seconds": round(el, 4), "outer_iters": st.outer_iters,
-                               "max_rel_residual": st.rel_residual, "speedup_vs_plain_fp64": round(seq / el, 3)}
+    for name, sweeps in (("batched_ct_mixed", 0), ("batched_ct_transport_mixed", -2)):
+        opts = sgdg.default_solve_opts(rtol=1e-8, maxit=400, mixed=True,
+                                       pc=sgdg.default_precond_opts(mass_sweeps=sweeps))
+        batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = batch.solve(bt, torch.zeros_like(bt), opts, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out[name] = {"seconds": round(el, 4), "outer_iters": st.outer_iters, "inner_iters": st.inner_iters_total,
+                     "max_rel_residual": st.rel_residual, "speedup_vs_plain_fp64": round(seq / el, 3)}
     _log(f"batched learned leg: {out}")
     batch.close()
     for p in probs:
@@ -656,8 +670,9 @@ def vlasov_poisson_leg(dev, runs=((1, 5, 20), (2, 5, 3))):
         energies, fps, secs, asm, outer = [en], [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        vopts = sgdg.default_solve_opts(rtol=1e-10, pc=sgdg.default_precond_opts(mass_sweeps=-2))
         for j in range(nst):
-            f, _, st = vp.strip(f, prev, E, fp_tol=1e-6, raise_on_noconv=False)
+            f, _, st = vp.strip(f, prev, E, fp_tol=1e-6, solve=vopts, raise_on_noconv=False)
             prev = w.r + 1
             E, en = vp.field(vp.density(f, prev, 1.0))
             energies.append(en)

@@ -189,7 +189,12 @@ typedef struct {
   int mass_sweeps;      /* mass inverses of the grid-problem preconditioner (Sect. 4.3): 0 = diagonals of
                            M^x and M^v; k = 1..64: k Chebyshev-Jacobi steps per mass factor (a fixed
                            polynomial in D^-1 M, eigenvalues in [1/2, 1 + d/2]); -1 (d = 1 only): exact
-                           tridiagonal solves per grid line */
+                           tridiagonal solves per grid line.  -2 (periodic x only, at most 1024 nodes per
+                           x-axis): instead the x-transport preconditioner, an extension beyond Sect. 4.3:
+                           the terms of A_{l,l} with translation-invariant x-factors (mass, derivatives,
+                           stiffness without x-field weights) and mass v-factors, the v-factors lumped to
+                           their row sums, inverted exactly mode by mode after a discrete Fourier
+                           transform over x (for every v-node an R x R system per mode) */
   sgdg_net net;         /* kind 1: the trained network of this problem */
   int fallback_iters;   /* kind 1: if over any fallback_iters consecutive FGMRES iterations (default 10) ... */
   double fallback_drop; /* ... the residual estimate drops by less than this factor (default 10), the

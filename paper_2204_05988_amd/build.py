@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libsgdg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "assembly.cpp", "terms.cpp", "debug.cpp", "kernels.hip", "fused.hip", "problem.hip", "solver.hip", "net.hip", "split.hip", "vlasov.hip"]
+SOURCES = ["mesh.cpp", "assembly.cpp", "terms.cpp", "debug.cpp", "kernels.hip", "fused.hip", "problem.hip", "solver.hip", "net.hip", "split.hip", "vlasov.hip", "fourier.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SGDG_ARCH", "gfx950")

@@ -11,6 +11,9 @@
 #include <sstream>
 #include <type_traits>
 
+#include <complex>
+
+#include "fourier.h"
 #include "ops_internal.h"
 #include "split.h"
 
@@ -27,6 +30,10 @@ struct SegTab {
   DevBuf segs, blk;
   std::vector<SegInfo> host;
   SegTable t;
+  // x-transport preconditioner of the segments (periodic x), built on first use
+  DevBuf fsegs, flines, fpinv;
+  FourierTab ftab;
+  bool fourier = false;
 };
 
 struct Items {
@@ -96,6 +103,7 @@ struct sgdg_batch_s {
   bool owned_by_ops = false;
   std::unique_ptr<FlagRing> flags;  // pinned flag copies of the strip FGMRES
   std::vector<sgdg_net> nets;  // learned preconditioner of each problem (sgdg_batch_set_networks)
+  DevBuf fourier_c;            // complex scratch of the x-transport preconditioner
   // box-shape choice of the fused kernel per element size (tuned or default)
   int xbox[2] = {0, 0};
   // operator application variant: 0 split (streaming passes), 1 fused box
@@ -987,6 +995,147 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
   return it;
 }
 
+// ------------------------------------- x-transport preconditioner tables ---
+// For every grid-problem segment: the terms of the strip operator whose
+// x-factor is translation invariant (no x-field weight, not a face) and whose
+// v-factor is a mass matrix, the v-factor lumped to its row sums.  On a
+// periodic x-lattice these form, for every v-node q, a circulant operator in
+// x; its action on the Fourier mode theta is the R x R matrix
+//   sum_terms Tm_k * xhat_k(theta) * lambda_k(q),
+//   xhat_k(theta) = sum_slots c_e exp(i theta . o_e)  (the stencil of any row),
+//   lambda_k(q) = sum_e V_k[q, e],
+// which the tables hold inverted, one per (mode, v-node).
+static FourierTab& fourier_tab(Batch& B, SegTab& ST) {
+  if (ST.fourier) return ST.ftab;
+  using cd = std::complex<double>;
+  std::vector<FourierSeg> fs;
+  std::vector<int2> lines;
+  std::vector<double> pinv;
+  const int d = B.d;
+  for (size_t gi = 0; gi < ST.host.size(); ++gi) {
+    const SegInfo& S = ST.host[gi];
+    sgdg_ops o = B.P[size_t(S.prob)];
+    const DomainData& X = o->X;
+    const DomainData& V = o->V;
+    require(X.dom.periodic, "the x-transport preconditioner needs a periodic x-domain");
+    const int n1 = X.dom.axis_nodes(S.lx);
+    require(n1 <= 1024, "the x-transport preconditioner takes at most 1024 nodes per x-axis");
+    const int R = S.R;
+    FourierSeg F{};
+    F.off = S.off;
+    F.poff = int64_t(pinv.size() / 2);
+    F.nx = S.nx;
+    F.nv = S.nv;
+    F.R = R;
+    F.n1 = n1;
+    F.d = d;
+    fs.push_back(F);
+    const int Sx = X.st.S, Sv = V.st.S;
+    const int lxi = S.lx - X.lmin, lvi = S.lv - V.lmin;
+    const LevelTables& VL = V.L(S.lv);
+    struct Sel {
+      const Term* t;
+      std::vector<cd> sym;
+      std::vector<double> lam;
+    };
+    std::vector<Sel> sel;
+    for (const Term& t : o->ops[0].host.terms) {
+      const FactorKey& kx = X.factors[size_t(t.xf)];
+      const FactorKey& kv = V.factors[size_t(t.vf)];
+      if (kx.kind == kFace || !kx.w.fields.empty() || kx.w.kink != 0 || kv.kind != kMass) continue;
+      const std::vector<double>& xv = X.values[size_t(t.xf)][size_t(lxi)];
+      // translation invariance: every row repeats row 0
+      for (int64_t r = 0; r < S.nx; ++r)
+        for (int e = 0; e < Sx; ++e)
+          require(std::fabs(xv[size_t(r * Sx + e)] - xv[size_t(e)]) <= 1e-12 * (1.0 + std::fabs(xv[size_t(e)])),
+                  "an x-factor of the x-transport part is not translation invariant");
+      Sel z;
+      z.t = &t;
+      z.sym.resize(size_t(S.nx));
+      for (int64_t m = 0; m < S.nx; ++m) {
+        int64_t rem = m;
+        double th[3] = {0, 0, 0};
+        for (int a = d - 1; a >= 0; --a) {
+          th[a] = 2.0 * M_PI * double(rem % n1) / double(n1);
+          rem /= n1;
+        }
+        cd acc = 0;
+        for (int e = 0; e < Sx; ++e) {
+          double ph = 0;
+          for (int a = 0; a < d; ++a) ph += th[a] * X.st.off[e][a];
+          acc += xv[size_t(e)] * cd(std::cos(ph), std::sin(ph));
+        }
+        z.sym[size_t(m)] = acc;
+      }
+      const std::vector<double>& vv = V.values[size_t(t.vf)][size_t(lvi)];
+      z.lam.assign(size_t(S.nv), 0.0);
+      for (int64_t q = 0; q < S.nv; ++q)
+        for (int e = 0; e < Sv; ++e)
+          if (VL.valid[size_t(q * Sv + e)]) z.lam[size_t(q)] += vv[size_t(q * Sv + e)];
+      sel.push_back(std::move(z));
+    }
+    require(!sel.empty(), "no translation-invariant terms for the x-transport preconditioner");
+    std::vector<cd> P(size_t(R * R)), Inv(size_t(R * R));
+    for (int64_t m = 0; m < S.nx; ++m)
+      for (int64_t q = 0; q < S.nv; ++q) {
+        std::fill(P.begin(), P.end(), cd(0));
+        for (const Sel& z : sel) {
+          const cd f = z.sym[size_t(m)] * z.lam[size_t(q)];
+          for (int i = 0; i < R * R; ++i) P[size_t(i)] += z.t->tm[i] * f;
+        }
+        // Gauss-Jordan with partial pivoting
+        std::vector<cd> A = P;
+        for (int i = 0; i < R * R; ++i) Inv[size_t(i)] = (i / R == i % R) ? cd(1) : cd(0);
+        for (int c = 0; c < R; ++c) {
+          int pr = c;
+          for (int r = c + 1; r < R; ++r)
+            if (std::abs(A[size_t(r * R + c)]) > std::abs(A[size_t(pr * R + c)])) pr = r;
+          require(std::abs(A[size_t(pr * R + c)]) > 1e-300, "singular mode of the x-transport preconditioner");
+          if (pr != c)
+            for (int k = 0; k < R; ++k) {
+              std::swap(A[size_t(c * R + k)], A[size_t(pr * R + k)]);
+              std::swap(Inv[size_t(c * R + k)], Inv[size_t(pr * R + k)]);
+            }
+          const cd piv = A[size_t(c * R + c)];
+          for (int k = 0; k < R; ++k) {
+            A[size_t(c * R + k)] /= piv;
+            Inv[size_t(c * R + k)] /= piv;
+          }
+          for (int r = 0; r < R; ++r) {
+            if (r == c) continue;
+            const cd f = A[size_t(r * R + c)];
+            for (int k = 0; k < R; ++k) {
+              A[size_t(r * R + k)] -= f * A[size_t(c * R + k)];
+              Inv[size_t(r * R + k)] -= f * Inv[size_t(c * R + k)];
+            }
+          }
+        }
+        for (int i = 0; i < R * R; ++i) {
+          pinv.push_back(Inv[size_t(i)].real());
+          pinv.push_back(Inv[size_t(i)].imag());
+        }
+      }
+    int64_t other = 1;
+    for (int a = 0; a < d - 1; ++a) other *= n1;
+    const int64_t nl = int64_t(R) * S.nv * other;
+    for (int64_t l = 0; l < nl; ++l) lines.push_back(int2{int(gi), int(l)});
+  }
+  upload(ST.fsegs, fs);
+  upload(ST.flines, lines);
+  upload(ST.fpinv, pinv);
+  ST.ftab.d = d;
+  ST.ftab.nlines = int(lines.size());
+  ST.ftab.segs = ptr<FourierSeg>(ST.fsegs);
+  ST.ftab.lines = ptr<int2>(ST.flines);
+  ST.ftab.pinv = ptr<double>(ST.fpinv);
+  ST.fourier = true;
+  return ST.ftab;
+}
+
+static int64_t seg_total(const SegTab& ST) {
+  return ST.host.empty() ? 0 : ST.host.back().off + ST.host.back().len;
+}
+
 // ------------------------------------------- grid-problem preconditioner ---
 // Chebyshev semi-iteration coefficients for M z = b with the Jacobi splitting:
 // the eigenvalues of D^-1 M of the P1 mass matrix on Kuhn simplices lie in
@@ -1016,7 +1165,7 @@ static void mass_cheb_coefs(int d, int k, double* cd, double* cr) {
 }
 
 static void check_mass(const sgdg_precond_opts& po, int d) {
-  require(po.mass_sweeps >= -1 && po.mass_sweeps <= 64, "mass_sweeps must be -1..64");
+  require(po.mass_sweeps >= -2 && po.mass_sweeps <= 64, "mass_sweeps must be -2..64");
   require(po.mass_sweeps != -1 || d == 1, "mass_sweeps = -1 (exact tridiagonal mass solves) needs d = 1");
 }
 
@@ -1033,6 +1182,12 @@ static void mass_precond(Batch& B, const SegTab& ST, int sweeps, const T* in, T*
   BWork<T>& w = work<T>(B);
   if (sweeps == 0) {
     KernelsT<T>::minv(S, in, out, q);
+    return;
+  }
+  if (sweeps == -2) {
+    const int64_t total = seg_total(ST);
+    B.fourier_c.ensure(sizeof(double) * 2 * size_t(total));
+    fourier_precond_n<T>(fourier_tab(B, const_cast<SegTab&>(ST)), S, total, in, out, ptr<double>(B.fourier_c), q);
     return;
   }
   if (sweeps < 0) {
@@ -1088,6 +1243,10 @@ static void ct_apply(Batch& B, const T* r, T* z, const sgdg_precond_opts& po, bo
   T* b = ptr<T>(w.ctb);
   KernelsT<T>::ct_gather(ST.t, r, b, s);
   items(B, K_CT, int(sizeof(T)));  // tables exist before any capture
+  if (po.mass_sweeps == -2) {
+    fourier_tab(B, ST);
+    B.fourier_c.ensure(sizeof(double) * 2 * size_t(nct));
+  }
   const int sweeps = po.mass_sweeps;
   auto A = [&](const T* in, T* out, hipStream_t q) { apply<T>(B, K_CT, in, out, 1, q); };
   auto M = [&](const T* in, T* out, hipStream_t q) { mass_precond<T>(B, ST, sweeps, in, out, q); };

@@ -199,3 +199,72 @@ def _fnorm(P, e):
         v = np.concatenate([blk[s].ravel() for blk in blocks])
         tot += abs(v @ P.apply_mass(v))
     return np.sqrt(tot)
+
+
+def _periodic_transport_case(kind, r):
+    w = config_tiny("d1p") if kind == "d1" else config_c5(L=4)
+    w.r = r
+    return w
+
+
+TP_CASES = [("tiny_d1p", lambda: config_tiny("d1p")), ("tiny_d1p_r1", lambda: _periodic_transport_case("d1", 1)),
+            ("c5_L4", lambda: config_c5(L=4)), ("c5_L4_r1", lambda: _periodic_transport_case("d2", 1))]
+
+
+@pytest.mark.parametrize("case", TP_CASES, ids=[c[0] for c in TP_CASES])
+def test_x_transport_preconditioner_matches_oracle(dev, case):
+    """mass_sweeps = -2 (periodic x): the FFT-based mode inverses equal the oracle's
+    direct solve of the x-transport operator on every grid problem."""
+    from paper_2204_05988_amd import sgdg
+    name, fn = case
+    w = fn()
+    P = Problem(w)
+    ops = sgdg.SparseGridOps(w)
+    n = P.R * (ops.npts_up + ops.npts_low)
+    x = random_vector(n, 29)[0]
+    _say(f"x-transport preconditioner {name}: n={n}")
+    ref = gridprec.transport_precond_all(P, x)
+    xt = torch.tensor(x, device=dev)
+    y = torch.empty_like(xt)
+    ops.grid_precond(xt, y, -2)
+    y32 = torch.empty(n, dtype=torch.float32, device=dev)
+    ops.grid_precond(xt.float(), y32, -2)
+    torch.cuda.synchronize()
+    e64, e32 = _rel(y.cpu().numpy(), ref), _rel(y32.double().cpu().numpy(), ref)
+    _say(f"  fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= 1e-10
+    assert e32 <= 2e-5
+    ops.close()
+
+
+def test_x_transport_preconditioner_in_ct_and_solves(dev):
+    """The CT with tightly solved grid problems does not depend on their preconditioner
+    (equals the oracle's CT); in c5 strip solves the x-transport preconditioner cuts
+    the grid-problem iterations far below the mass forms'."""
+    from paper_2204_05988_amd import sgdg
+    w = config_c5(L=4)
+    P = Problem(w)
+    ops = sgdg.SparseGridOps(w)
+    r = random_vector(P.ndof, 31)[0]
+    z_ref = CTPreconditioner(P)(r)
+    rt = torch.tensor(r, device=dev)
+    zt = torch.empty_like(rt)
+    ops.precondition(rt, zt, sgdg.default_precond_opts(inner_rtol=1e-13, inner_maxit=2000, mass_sweeps=-2))
+    torch.cuda.synchronize()
+    e = _rel(zt.cpu().numpy(), z_ref)
+    _say(f"CT with the x-transport preconditioner vs oracle CT: {e:.2e}")
+    assert e <= 1e-9
+    u0 = ostrip.initial_coefficients(P)
+    b_ref = ostrip.rhs(P, 1, u0, 1)
+    b = torch.tensor(b_ref, device=dev)
+    inner = {}
+    for sweeps in (0, -2):
+        x, st = ops.solve_strip(b, torch.zeros_like(b),
+                                sgdg.default_solve_opts(rtol=1e-8, pc=sgdg.default_precond_opts(mass_sweeps=sweeps)))
+        res = np.linalg.norm(b_ref - P.apply(x.cpu().numpy())) / np.linalg.norm(b_ref)
+        inner[sweeps] = st.inner_iters_total / max(1, st.pc_applications)
+        _say(f"  c5 L4 strip, mass_sweeps {sweeps}: {st.outer_iters} outer, {inner[sweeps]:.1f} inner per CT, "
+             f"{st.seconds:.3f}s, oracle residual {res:.2e}")
+        assert res <= 1e-8 * (1 + 1e-6)
+    assert inner[-2] < 0.5 * inner[0]
+    ops.close()

@@ -617,3 +617,67 @@ def test_time_dependent_discrete_exact_solution(d, r, L):
     P2 = Problem(w2)
     b = strip.rhs(Problem(w, t0=w.dt), 2, u_prev, P2.R)
     assert np.linalg.norm(P2.apply(U) - b) > 1e-4 * np.linalg.norm(b)
+
+
+def _periodic_x_transport(kind, r):
+    """A periodic-x workload whose only coefficients move along x: beta = (v, 0), sigma = 0,
+    so every v-factor of A_{l,l} is a (weighted) mass matrix."""
+    if kind == "d1":
+        w = config_tiny("d1p")
+        w.beta = [(1.0, (), ("v0",)), None]
+        w.sigma = []
+    else:
+        w = config_tiny("d2")
+        w.x = Domain(2, (0.0, 0.0), (1.0, 1.0), periodic=True)
+        w.beta = [(1.0, (), ("v0",)), (1.0, (), ("v1",)), None, None]
+        w.sigma = []
+    w.r = r
+    return w
+
+
+@pytest.mark.parametrize("kind,r", [("d1", 0), ("d1", 1), ("d2", 1)])
+def test_x_transport_operator_is_exact_on_v_constant_functions(kind, r):
+    """Lumping a v-mass matrix keeps its action on the constants, so on functions that are
+    constant in v the x-transport operator equals the grid problem's A_{l,l} (every term
+    of which it keeps when beta has no v-component and sigma = 0); on other functions it
+    differs (the lumping is real)."""
+    from oracle import gridprec
+    w = _periodic_x_transport(kind, r)
+    P = Problem(w)
+    rng = np.random.default_rng(12)
+    for g in list(P.upper) + list(P.lower):
+        T = gridprec.transport_operator(P, g)
+        A = P.diag_block(g)
+        gx = rng.standard_normal((P.R, P.nx(g[0]), 1))
+        u = np.broadcast_to(gx, (P.R, P.nx(g[0]), P.nv(g[1]))).ravel()
+        assert np.abs(T @ u - A @ u).max() <= 1e-12 * np.abs(A @ u).max(), g
+    g = P.upper[0]
+    u = rng.standard_normal(P.R * P.nx(g[0]) * P.nv(g[1]))
+    T, A = gridprec.transport_operator(P, g), P.diag_block(g)
+    assert np.abs(T @ u - A @ u).max() > 1e-6 * np.abs(A @ u).max()
+
+
+def test_x_transport_operator_acts_on_fourier_modes_by_its_symbol():
+    """On a periodic x-lattice the operator maps exp(i theta.x) (x) e_q to
+    P(theta, q) exp(i theta.x) (x) e_q with an R x R matrix P(theta, q): a circulant
+    block per v-node (checked on every mode of a small grid)."""
+    from oracle import gridprec
+    w = _periodic_x_transport("d2", 1)
+    P = Problem(w)
+    g = (2, 0)
+    T = gridprec.transport_operator(P, g).toarray()
+    n1 = 2 ** g[0]
+    nx, nv, R = P.nx(g[0]), P.nv(g[1]), P.R
+    X = np.indices((n1, n1)).reshape(2, -1).T
+    for m0 in range(n1):
+        for m1 in range(n1):
+            th = 2 * np.pi * np.array([m0, m1]) / n1
+            mode = np.exp(1j * (X @ th))
+            for q in range(nv):
+                for s in range(R):
+                    u = np.zeros((R, nx, nv), complex)
+                    u[s, :, q] = mode
+                    y = (T @ u.ravel()).reshape(R, nx, nv)
+                    assert np.abs(np.delete(y, q, axis=2)).max() < 1e-12
+                    coef = y[:, :, q] / mode[None, :]
+                    assert np.abs(coef - coef[:, :1]).max() < 1e-12
