@@ -871,10 +871,13 @@ static GmresState gstate(GBufs& b, int nseg, int m) {
 
 // Right-preconditioned restarted GMRES on the independent grid problems
 // A_{l,l} dU_l = r_l (one segment each), preconditioner M fixed and linear.
-// A cycle of m iterations needs no host synchronisation.  Eagerly, the host
-// polls the convergence flags every 8 iterations; with use_graph the whole
-// cycle is captured once (per buffer set) and replayed, and converged
-// segments idle through the remaining iterations.
+// A cycle of m iterations needs no host synchronisation.  The host polls the
+// convergence flags every kPoll iterations; with use_graph each chunk of kPoll
+// iterations is captured once (per buffer set and chunk) and replayed, with
+// the same polls between chunks, so graph and eager solves run the same
+// iterations; converged segments idle until the next poll.
+constexpr int kPoll = 8;
+
 template <class T>
 static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(const T*, T*, hipStream_t)>& A,
                          const std::function<void(const T*, T*, hipStream_t)>& M, const T* b, T* x, T* V, T* w, T* tmp, int m,
@@ -931,53 +934,65 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
         B.clear_graphs();
         B.graph_epoch = alloc_epoch();
       }
-      std::ostringstream key;
-      key << sizeof(T) << '/' << m << '/' << total << '/' << (const void*)V << '/' << (const void*)w << '/'
-          << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b
-          << '/' << B.variant << '/' << B.split_bc << '/' << B.split_xcd;
-      auto g = B.graphs.find(key.str());
-      if (g == B.graphs.end()) {
-        // One eager application of M and A first: workspaces and item tables
-        // are created on first use, and allocation and table uploads cannot be
-        // captured.  Its result is overwritten by the cycle.
-        M(V, tmp, s);
-        A(tmp, w, s);
-        SGDG_CHECK_HIP(hipStreamSynchronize(s));
-        if (B.graph_epoch != alloc_epoch()) {  // the warm-up allocated: older graphs may be stale
-          B.clear_graphs();
-          B.graph_epoch = alloc_epoch();
-        }
-        // capture on a private stream (the caller's may be the null stream, which cannot be captured)
-        if (!B.cap_stream) SGDG_CHECK_HIP(hipStreamCreate(&B.cap_stream));
-        const bool prof = B.prof;
-        B.prof = false;
-        hipGraph_t graph = nullptr;
-        SGDG_CHECK_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
-        try {
-          for (int jj = 0; jj < m; ++jj) step(jj, B.cap_stream);
-        } catch (...) {
-          (void)hipStreamEndCapture(B.cap_stream, &graph);
-          if (graph) (void)hipGraphDestroy(graph);
+      // the cycle in chunks of kPoll iterations, one graph per chunk, with the
+      // same convergence polls between chunks as the eager loop below
+      std::ostringstream base;
+      base << sizeof(T) << '/' << m << '/' << total << '/' << (const void*)V << '/' << (const void*)w << '/'
+           << (const void*)tmp << '/' << (const void*)part << '/' << (const void*)st.H << '/' << (const void*)b
+           << '/' << B.variant << '/' << B.split_bc << '/' << B.split_xcd << '/' << B.scan_chunks;
+      bool warmed = false;
+      while (j < mm) {
+        const int j1 = std::min(mm, j + kPoll);
+        std::ostringstream key;
+        key << base.str() << '/' << j << '-' << j1;
+        auto g = B.graphs.find(key.str());
+        if (g == B.graphs.end()) {
+          if (!warmed) {
+            // One eager application of M and A first: workspaces and item tables
+            // are created on first use, and allocation and table uploads cannot be
+            // captured.  Its result is overwritten by the cycle.
+            M(V + int64_t(j) * total, tmp, s);
+            A(tmp, w, s);
+            SGDG_CHECK_HIP(hipStreamSynchronize(s));
+            if (B.graph_epoch != alloc_epoch()) {  // the warm-up allocated: older graphs may be stale
+              B.clear_graphs();
+              B.graph_epoch = alloc_epoch();
+            }
+            warmed = true;
+          }
+          // capture on a private stream (the caller's may be the null stream, which cannot be captured)
+          if (!B.cap_stream) SGDG_CHECK_HIP(hipStreamCreate(&B.cap_stream));
+          const bool prof = B.prof;
+          B.prof = false;
+          hipGraph_t graph = nullptr;
+          SGDG_CHECK_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
+          try {
+            for (int jj = j; jj < j1; ++jj) step(jj, B.cap_stream);
+          } catch (...) {
+            (void)hipStreamEndCapture(B.cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            B.prof = prof;
+            throw;
+          }
           B.prof = prof;
-          throw;
+          SGDG_CHECK_HIP(hipStreamEndCapture(B.cap_stream, &graph));
+          hipGraphExec_t exec = nullptr;
+          const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          SGDG_CHECK_HIP(e);
+          g = B.graphs.emplace(key.str(), exec).first;
+          // instantiation allocates no DevBuf: the epoch still matches the capture
+          require(B.graph_epoch == alloc_epoch(), "work buffers changed during graph capture");
         }
-        B.prof = prof;
-        SGDG_CHECK_HIP(hipStreamEndCapture(B.cap_stream, &graph));
-        hipGraphExec_t exec = nullptr;
-        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        SGDG_CHECK_HIP(e);
-        g = B.graphs.emplace(key.str(), exec).first;
-        // instantiation allocates no DevBuf: the epoch still matches the capture
-        require(B.graph_epoch == alloc_epoch(), "work buffers changed during graph capture");
+        timed(B, 2, s, [&] { SGDG_CHECK_HIP(hipGraphLaunch(g->second, s)); });
+        j = j1;
+        if (j < mm && !any_active()) break;
       }
-      timed(B, 2, s, [&] { SGDG_CHECK_HIP(hipGraphLaunch(g->second, s)); });
-      j = m;
     } else {
       timed(B, 2, s, [&] {
         for (; j < mm; ++j) {
           step(j, s);
-          if ((j + 1) % 8 == 0 && j + 1 < mm && !any_active()) {
+          if ((j + 1) % kPoll == 0 && j + 1 < mm && !any_active()) {
             ++j;
             break;
           }
