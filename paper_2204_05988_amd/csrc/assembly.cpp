@@ -414,6 +414,21 @@ void assemble_factor(DomainData& D, int fid) {
   FactorKey key = D.factors[fid];
   const int nlev = D.lmax - D.lmin + 1;
   std::vector<std::vector<double>> vals(nlev);
+  if (!key.parts.empty()) {
+    // a combination: the same linear combination of its parts on every level
+    // (the Galerkin restriction and the transposition are linear)
+    for (int l = 0; l < nlev; ++l) {
+      const size_t n = D.values[size_t(key.parts[0].second)][size_t(l)].size();
+      vals[size_t(l)].assign(n, 0.0);
+      for (const auto& p : key.parts) {
+        const auto& src = D.values[size_t(p.second)][size_t(l)];
+        if (src.size() != n) throw std::logic_error("combination of factors assembled before its parts");
+        for (size_t i = 0; i < n; ++i) vals[size_t(l)][i] += p.first * src[i];
+      }
+    }
+    D.values[fid] = std::move(vals);
+    return;
+  }
   FactorKey base = key;
   base.trans = false;
   assemble_finest(D, base, vals[nlev - 1]);
@@ -426,6 +441,24 @@ void assemble_factor(DomainData& D, int fid) {
     }
   }
   D.values[fid] = std::move(vals);
+}
+
+void assemble_all(DomainData& D) {
+  D.values.assign(D.factors.size(), {});
+  D.rvalues.assign(D.factors.size(), {});
+  D.pvalues.assign(D.factors.size(), {});
+  build_wide_tables(D);
+  build_prolong_tables(D);
+  for (int phase = 0; phase < 2; ++phase) {
+    // assembled factors first, then the combinations of them
+#pragma omp parallel for schedule(dynamic)
+    for (int f = 0; f < int(D.factors.size()); ++f) {
+      if (D.factors[size_t(f)].parts.empty() != (phase == 0)) continue;
+      assemble_factor(D, f);
+      restrict_factor(D, f);
+      prolong_factor(D, f);
+    }
+  }
 }
 
 }  // namespace sgdg

@@ -152,7 +152,15 @@ bool FactorKey::operator<(const FactorKey& o) const {
   if (trans != o.trans) return trans < o.trans;
   if (w < o.w) return true;
   if (o.w < w) return false;
-  return false;
+  return parts < o.parts;
+}
+
+bool factor_plain(const DomainData& D, int fid) {
+  const FactorKey& k = D.factors[size_t(fid)];
+  if (k.parts.empty()) return k.w.fields.empty() && k.w.kink == 0;
+  for (const auto& p : k.parts)
+    if (!factor_plain(D, p.second)) return false;
+  return true;
 }
 
 int DomainData::field_id(const double* src, int64_t n) {

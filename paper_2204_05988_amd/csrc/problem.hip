@@ -519,20 +519,8 @@ static sgdg_ops assemble_ops(sgdg_grid g, double dt, double delta, F&& terms) {
   mk.kind = kMass;
   o->dx.d.mass_fac = o->X.factor_id(mk);
   o->dv.d.mass_fac = o->V.factor_id(mk);
-  for (int side = 0; side < 2; ++side) {
-    DomainData& D = side == 0 ? o->X : o->V;
-    D.values.assign(D.factors.size(), {});
-    D.rvalues.assign(D.factors.size(), {});
-    D.pvalues.assign(D.factors.size(), {});
-    build_wide_tables(D);
-    build_prolong_tables(D);
-#pragma omp parallel for schedule(dynamic)
-    for (int f = 0; f < int(D.factors.size()); ++f) {
-      assemble_factor(D, f);
-      restrict_factor(D, f);
-      prolong_factor(D, f);
-    }
-  }
+  assemble_all(o->X);
+  assemble_all(o->V);
   const int mfx = o->dx.d.mass_fac, mfv = o->dv.d.mass_fac;
   upload_domain(o->X, o->dx);
   upload_domain(o->V, o->dv);

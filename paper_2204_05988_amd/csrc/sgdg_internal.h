@@ -78,14 +78,21 @@ struct Weight {
 
 enum FactorKind { kMass = 0, kDeriv = 1, kStiff = 2, kFace = 3 };
 
+struct DomainData;
+
 struct FactorKey {
   int kind = kMass;
   int a = -1, b = -1;        // derivative directions
   int axis = -1, side = -1;  // face
   Weight w;
   bool trans = false;
+  // a linear combination sum_i c_i F_i of registered factors of one kind
+  // (ids ascending, none itself a combination); empty for an assembled factor
+  std::vector<std::pair<double, int>> parts;
   bool operator<(const FactorKey& o) const;
 };
+// true if the factor (every part of a combination) has a constant weight and no kink
+bool factor_plain(const DomainData& D, int fid);
 
 struct DomainData {
   Dom dom;
@@ -125,6 +132,8 @@ struct TermList {
 // Host-side construction (mesh.cpp, assembly.cpp, terms.cpp).
 void build_domain_tables(DomainData& D);
 void assemble_factor(DomainData& D, int fid);  // all levels of one factor
+// every factor of D: values, restricted and prolongated stencils (combinations after their parts)
+void assemble_all(DomainData& D);
 void build_wide_tables(DomainData& D);          // woff and wide_idx
 void restrict_factor(DomainData& D, int fid);   // rvalues of one factor
 void build_prolong_tables(DomainData& D);       // pro_idx

@@ -1057,7 +1057,7 @@ static FourierTab& fourier_tab(Batch& B, SegTab& ST) {
     for (const Term& t : o->ops[0].host.terms) {
       const FactorKey& kx = X.factors[size_t(t.xf)];
       const FactorKey& kv = V.factors[size_t(t.vf)];
-      if (kx.kind == kFace || !kx.w.fields.empty() || kx.w.kink != 0 || kv.kind != kMass) continue;
+      if (kx.kind == kFace || !factor_plain(X, t.xf) || kv.kind != kMass) continue;
       const std::vector<double>& xv = X.values[size_t(t.xf)][size_t(lxi)];
       // translation invariance: every row repeats row 0
       for (int64_t r = 0; r < S.nx; ++r)

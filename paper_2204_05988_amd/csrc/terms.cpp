@@ -20,6 +20,7 @@
 // and  inflow |beta.n| g w -> Mt (x) (-G).
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <stdexcept>
 
 #include "sgdg_internal.h"
@@ -229,6 +230,77 @@ double legendre_val(int s, double z, double* deriv) {
   return p1;
 }
 
+// tm_j = a tm_i (to rounding), a returned
+bool proportional(const double* ti, const double* tj, int n, double* a) {
+  int p = 0;
+  double mi = 0.0, mj = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (std::fabs(ti[k]) > mi) {
+      mi = std::fabs(ti[k]);
+      p = k;
+    }
+    mj = std::max(mj, std::fabs(tj[k]));
+  }
+  if (mi == 0.0 || mj == 0.0) return false;
+  const double r = tj[p] / ti[p];
+  for (int k = 0; k < n; ++k)
+    if (std::fabs(tj[k] - r * ti[k]) > 1e-14 * mj) return false;
+  *a = r;
+  return true;
+}
+
+// The factor c_i F_i + c_j F_j (F_i, F_j of one kind), registered as a combination.
+int combine(DomainData& D, int fi, double ci, int fj, double cj) {
+  std::map<int, double> acc;
+  auto add = [&](int f, double c) {
+    const FactorKey& k = D.factors[size_t(f)];
+    if (k.parts.empty()) {
+      acc[f] += c;
+      return;
+    }
+    for (const auto& p : k.parts) acc[p.second] += c * p.first;
+  };
+  add(fi, ci);
+  add(fj, cj);
+  FactorKey key;
+  key.kind = D.factors[size_t(fi)].kind;
+  for (const auto& e : acc)
+    if (e.second != 0.0) key.parts.push_back({e.second, e.first});
+  if (key.parts.size() == 1 && key.parts[0].first == 1.0) return key.parts[0].second;
+  return D.factor_id(key);
+}
+
+// Terms that share one factor and whose time blocks are proportional,
+// tm (x) X (x) V_i + a tm (x) X (x) V_j = tm (x) X (x) (V_i + a V_j) (and the
+// same with the roles of x and v swapped), become one term with a combined
+// factor of the same kind: the passes then run fewer stencils, staged arrays
+// and partner scans.  Repeated until no pair is left.
+void merge_terms(DomainData& X, DomainData& V, TermList& L) {
+  const int n = L.Rout * L.Rin;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (size_t i = 0; i < L.terms.size() && !changed; ++i)
+      for (size_t j = i + 1; j < L.terms.size() && !changed; ++j) {
+        Term& a = L.terms[i];
+        const Term& b = L.terms[j];
+        double r;
+        if (a.xf == b.xf && a.vf == b.vf) {  // a pair made equal by an earlier merge
+          for (int k = 0; k < n; ++k) a.tm[k] += b.tm[k];
+        } else if (!proportional(a.tm, b.tm, n, &r)) {
+          continue;
+        } else if (a.xf == b.xf && V.factors[size_t(a.vf)].kind == V.factors[size_t(b.vf)].kind) {
+          a.vf = combine(V, a.vf, 1.0, b.vf, r);
+        } else if (a.vf == b.vf && X.factors[size_t(a.xf)].kind == X.factors[size_t(b.xf)].kind) {
+          a.xf = combine(X, a.xf, 1.0, b.xf, r);
+        } else {
+          continue;
+        }
+        L.terms.erase(L.terms.begin() + std::ptrdiff_t(j));
+        changed = true;
+      }
+  }
+}
+
 void init_lists(TermList out[4], int R) {
   out[0].Rin = out[0].Rout = R;
   out[1].Rin = out[1].Rout = 1;
@@ -271,6 +343,7 @@ void build_terms(DomainData& X, DomainData& V, const sgdg_problem& p, int r, Ter
   add_terms(X, V, out[2], Mt, dl, S.T, true);
   // DATA_G
   add_terms(X, V, out[3], Mt, 1.0, S.Gm, false);
+  for (int k = 0; k < 4; ++k) merge_terms(X, V, out[k]);
 }
 
 // Coefficients that depend on time (Sect. 4.2, the block formula with an
@@ -328,6 +401,7 @@ void build_terms_t(DomainData& X, DomainData& V, const sgdg_problem* at, const d
     add_terms(X, V, out[2], Mm, dl, S.T, true);
     add_terms(X, V, out[3], Mm, 1.0, S.Gm, false);
   }
+  for (int k = 0; k < 4; ++k) merge_terms(X, V, out[k]);
 }
 
 }  // namespace sgdg
