@@ -38,6 +38,9 @@ Prints one JSON line.  Beside the headline number:
     its 8-strip march with CT-preconditioned FGMRES to 1e-10;
   * vlasov_poisson: Landau damping in 1+1 and 2+2 dimensions with the
     per-strip fixed point of transport and field;
+  * table1: the periodic advection test of Sect. 5.1 (r = 1) for d = 1, 2, 3:
+    every strip of one period solved on the device, the error in the SD norm
+    and its observed order beside the paper's Table 1;
   * cpu_baseline: the CPU oracle timed on the host cores (one core and a
     process pool over all of them) on a bounded sample.
 """
@@ -78,6 +81,8 @@ def parse():
                     help="learned leg reduced to the network's forward rate (freshly initialised weights)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-vp", action="store_true", help="skip the Vlasov-Poisson leg")
+    ap.add_argument("--table1", default="6,6,3",
+                    help="highest paper levels of the Table-1 leg for d = 1,2,3 (0 skips a dimension; 0 alone skips the leg)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--cold", type=int, default=10, help="cold-cache repetitions of the headline apply")
     ap.add_argument("--no-legs", action="store_true", help="skip the other batch sizes and dtypes of the 4D apply")
@@ -158,7 +163,8 @@ def kernel_work(ops, B, R, elem_bytes):
 
 def recorded_traffic(kernel, workload_tag):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary of this workload, or None if there is none or the kernel source changed since."""
+    summary of this workload, or None if there is none or the kernel source or the term
+    builder changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"apply_{workload_tag}_hbm_traffic.txt")
     if not os.path.exists(path):
@@ -167,10 +173,12 @@ def recorded_traffic(kernel, workload_tag):
            "k_scan2": "fused.hip", "k_fused": "fused.hip"}.get(kernel)
     if src is None:
         return None
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2204_05988_amd", "csrc", src), "rb").read()).hexdigest()[:16]
     text = open(path).read()
-    if f"{src} sha256/16 {sha}" not in text:
-        return None
+    # the counters hold for the kernel's source and for the term lists that set its work
+    for f in (src, "terms.cpp"):
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2204_05988_amd", "csrc", f), "rb").read()).hexdigest()[:16]
+        if f"{f} sha256/16 {sha}" not in text:
+            return None
     for line in text.splitlines():
         f = line.split()
         if f and f[0] == kernel:
@@ -389,6 +397,9 @@ def main():
         out["vlasov_poisson"] = vlasov_poisson_leg(dev)
     if a.c3_level > 0:
         out["apply_6d"] = apply_6d_leg(dev, a.c3_level)
+    t1 = tuple((d + 1, int(m)) for d, m in enumerate(a.table1.split(",")) if m and int(m) > 0)
+    if t1:
+        out["table1"] = table1_leg(dev, t1)
     if not a.no_2d:
         out["apply_2d"] = apply_2d_leg(dev)
         gpu_strips.setdefault("c1_march", out["apply_2d"]["march"]["seconds"])
@@ -878,6 +889,180 @@ def batched_leg(dev, n):
     batch.close()
     for o in ops_list:
         o.close()
+    return out
+
+
+# --- Sect. 5.1 (Table 1): the periodic advection test and its error in the SD norm -------------
+#
+# For beta = 1 in all 2d directions, sigma = 0 and periodic domains the strip
+# operator satisfies, for every strip solution U (time slices U_s),
+#   U^T A U = 1/2 ||U(t_j^-)||^2 + 1/2 ||U(t_{j-1}^+)||^2 + delta int_{I_j} ||d_t U + beta.grad U||^2
+# (the mass-time-derivative and advection parts integrate to the trace terms,
+# the advection part of a periodic constant-coefficient field vanishes, G^t
+# adds the left trace).  The exact solution u solves d_t u + beta.grad u = 0
+# and is continuous in time, so with e = U - u the norm (eq:norm_SD) is
+#   |||e|||^2 = sum_j [U_j^T A U_j - (||U_j(t_j^-)||^2 + ||U_j(t_{j-1}^+)||^2) / 2]
+#               + sum_{j<N} ||U_{j+1}(t_j^+) - U_j(t_j^-)||^2 + ||U_1(0^+) - u(0)||^2 + ||U_N(T^-) - u(T)||^2,
+# every term an operator application or a mass product, the two end terms
+# through ||w - u||^2 = ||w||^2 - 2 (u, w) + ||u||^2 with ||u||^2 = 1/2 and
+# (u, phi_i (x) phi_j) = Im(exp(-4 pi i d t) a_lx a_lv exp(2 pi i sum x_i) exp(2 pi i sum v_j)),
+# a_l the Fourier coefficient of the hat at the origin of the level-l lattice.
+
+def _collapsed_rule(k, n):
+    """Barycentric coordinates (Q, k+1) and weights (Q,) of a Gauss rule on the
+    reference k-simplex (weights sum to 1/k!): a tensor Gauss-Legendre rule on
+    the unit cube pushed through the collapsed (Duffy) coordinates."""
+    g, gw = np.polynomial.legendre.leggauss(n)
+    g, gw = 0.5 * (g + 1.0), 0.5 * gw
+    mesh = np.stack(np.meshgrid(*([g] * k), indexing="ij"), -1).reshape(-1, k)
+    wts = np.prod(np.stack(np.meshgrid(*([gw] * k), indexing="ij"), -1).reshape(-1, k), axis=1)
+    y = np.empty_like(mesh)
+    rest = np.ones(len(mesh))
+    for j in range(k):
+        y[:, j] = mesh[:, j] * rest
+        rest = rest * (1.0 - mesh[:, j])
+    jac = np.ones(len(mesh))
+    for j in range(k - 1):
+        jac *= (1.0 - mesh[:, j]) ** (k - 1 - j)
+    bary = np.concatenate([1.0 - y.sum(axis=1, keepdims=True), y], axis=1)
+    return bary, wts * jac
+
+
+def hat_fourier(d, level, n=12):
+    """int exp(2 pi i sum_a y_a) phi_0(y) dy, phi_0 the P1 hat at the origin of the
+    level-`level` Kuhn lattice of the unit cube (spacing 2^-level).  Its support is
+    the (d+1) d! simplices that have the origin as a vertex: for every ordering of
+    the axes and every position k of the origin on the monotone path through a
+    cell, the path shifted so that its k-th vertex is the origin."""
+    import itertools
+    h = 2.0 ** -level
+    bary, wq = _collapsed_rule(d, n)
+    tot = 0j
+    for perm in itertools.permutations(range(d)):
+        path = [np.zeros(d)]
+        for a in perm:
+            nxt = path[-1].copy()
+            nxt[a] += 1.0
+            path.append(nxt)
+        path = np.array(path)
+        for k in range(d + 1):
+            pts = bary @ ((path - path[k]) * h)
+            tot += h ** d * np.sum(wq * bary[:, k] * np.exp(2j * np.pi * pts.sum(axis=1)))
+    return tot
+
+
+def _exact_dot(w, grids, vec, t):
+    """(u(t), W) for the Table-1 solution u and the one-slice spanning vector vec
+    (host array) over the upper grids (lx, lv, nx, nv)."""
+    from workloads import lattice_coords
+    d = w.d
+    out, off = 0.0, 0
+    ph = np.exp(-4j * np.pi * d * t)
+    for lx, lv, nx, nv in grids:
+        ex = hat_fourier(d, lx) * np.exp(2j * np.pi * lattice_coords(w.x, lx).sum(axis=1))
+        ev = hat_fourier(d, lv) * np.exp(2j * np.pi * lattice_coords(w.v, lv).sum(axis=1))
+        blk = vec[off:off + nx * nv].reshape(nx, nv)
+        out += float(np.imag(ph * (ex @ blk @ ev)))
+        off += nx * nv
+    return out
+
+
+def sd_error_table1(w, grids, sols, apply_full, apply_mass, dot, cat, to_host):
+    """SD-norm error of the strip solutions sols (each R slices on the upper grids
+    (lx, lv, nx, nv)) of the Table-1 problem w, from operator applications only:
+    apply_full(u) = A u, apply_mass(v) = M v (one slice); dot, cat and to_host act
+    on the vectors' array type (numpy or device tensors)."""
+    R = w.r + 1
+
+    def traces(u):
+        rt, lt, off = [], [], 0
+        for _, _, nx, nv in grids:
+            n = nx * nv
+            blk = u[off:off + R * n].reshape(R, n)
+            rt.append(blk.sum(0))
+            lt.append(sum(((-1) ** s) * blk[s] for s in range(R)))
+            off += R * n
+        return cat(rt), cat(lt)
+
+    sq = lambda v: dot(v, apply_mass(v))
+    strip = jump = 0.0
+    prev_right = None
+    for j, u in enumerate(sols):
+        right, left = traces(u)
+        strip += dot(u, apply_full(u)) - 0.5 * (sq(right) + sq(left))
+        if j == 0:
+            first = left
+        else:
+            jump += sq(left - prev_right)
+        prev_right = right
+    T = len(sols) * w.dt
+    end = 0.0
+    for v, t in ((first, 0.0), (prev_right, T)):
+        end += sq(v) - 2.0 * _exact_dot(w, grids, to_host(v), t) + 0.5
+    return float(np.sqrt(strip + jump + end)), dict(strip=strip, jump=jump, end=end)
+
+
+def table1_run(w, dev, tol=1e-10, mass_sweeps=0):
+    """All 2^(Lp+1) strips of the Table-1 problem w on the device (FGMRES with the
+    combination technique to tol), then the SD-norm error; returns (error, stats)."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    ops = sgdg.SparseGridOps(w)
+    t0 = time.perf_counter()
+    u_prev, prev = _interp_u0(ops, w, dev), 1
+    opts = sgdg.default_solve_opts(rtol=tol, maxit=400, pc=sgdg.default_precond_opts(mass_sweeps=mass_sweeps))
+    sols, outer = [], 0
+    for _ in range(w.nstrips):
+        b = ops.rhs(u_prev, prev)
+        u = torch.zeros_like(b)
+        _, st = ops.solve_strip(b, u, opts)
+        outer += st.outer_iters
+        sols.append(u)
+        u_prev, prev = u, ops.R
+    torch.cuda.synchronize()
+    march_s = time.perf_counter() - t0
+
+    def full(u):
+        y = torch.empty_like(u)
+        ops.apply(u, y)
+        return y
+
+    def mass(v):
+        y = torch.empty_like(v)
+        ops.apply(v, y, kind=sgdg.OP_MASS)
+        return y
+
+    err, parts = sd_error_table1(w, ops.upper, sols, full, mass, lambda a, b: float(torch.dot(a, b)),
+                                 torch.cat, lambda v: v.cpu().numpy())
+    dim = ops.npts_up - ops.npts_low
+    ops.close()
+    return err, dict(dim=dim, strips=w.nstrips, outer_iters=outer, march_s=round(march_s, 3), parts=parts)
+
+
+# Table 1 of the paper (Sect. 5.1), r = 1: SD-norm error after one period per paper level.
+TABLE1_R1 = {1: {1: 8.68e-01, 2: 5.25e-01, 3: 2.03e-01, 4: 7.20e-02, 5: 2.55e-02, 6: 8.99e-03},
+             2: {1: 8.14e-01, 2: 5.98e-01, 3: 2.64e-01, 4: 9.58e-02, 5: 3.39e-02, 6: 1.19e-02},
+             3: {1: 7.36e-01, 2: 6.17e-01, 3: 3.13e-01, 4: 1.17e-01}}
+
+
+def table1_leg(dev, levels=((1, 6), (2, 6), (3, 3))):
+    """The r = 1 columns of Table 1 on the device: errors, observed orders and the
+    paper's values beside them (P1 on Kuhn simplices here, the paper's d >= 2 runs
+    use cubes)."""
+    from workloads import config_table1
+    out = {}
+    for d, lmax in levels:
+        rows, prev = [], None
+        for Lp in range(1, lmax + 1):
+            err, st = table1_run(config_table1(Lp, d=d), dev)
+            row = dict(L=Lp, error=err, paper=TABLE1_R1[d].get(Lp), **st)
+            if prev is not None:
+                row["order"] = float(np.log2(prev / err))
+            prev = err
+            rows.append(row)
+            _log(f"table 1 d={d} L={Lp}: dof {st['dim']} error {err:.3e} (paper {row['paper']}) "
+                 f"order {row.get('order')} march {st['march_s']} s")
+        out[f"d{d}"] = rows
     return out
 
 

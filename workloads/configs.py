@@ -301,23 +301,24 @@ def config_c5(seed: int = 0, L: int = 7) -> Workload:
         vfields={"v0": _coord(0), "v1": _coord(1)}, u0=u0, seed=seed)
 
 
-def config_table1(Lp: int, r: int = 1) -> Workload:
-    """Sect. 5.1, d=1: periodic advection with beta=(1,1) on [0,1]^2, one period T=1/2.
+def config_table1(Lp: int, r: int = 1, d: int = 1) -> Workload:
+    """Sect. 5.1: periodic advection with beta = 1 in all 2d directions on [0,1]^(2d),
+    u0 = sin(2 pi sum_i (x_i + v_i)), one period T = 1/(2d).
 
-    Paper level Lp (4 cells at paper level 1) maps to lmin=2, L=Lp+1; delta is the
-    finest edge length; 2**(Lp+1) time steps.
+    Paper level Lp (4 cells per axis at paper level 1) maps to lmin=2, L=Lp+1; delta is
+    the finest edge length; 2**(Lp+1) time steps.
     """
-    x = Domain(1, (0.0,), (1.0,), periodic=True)
-    v = Domain(1, (0.0,), (1.0,), periodic=True)
+    x = Domain(d, (0.0,) * d, (1.0,) * d, periodic=True)
+    v = Domain(d, (0.0,) * d, (1.0,) * d, periodic=True)
     nst = 2 ** (Lp + 1)
 
     def exact(t, X, V):
-        return np.sin(2 * np.pi * (X[..., 0] + V[..., 0] - 2 * t))
+        return np.sin(2 * np.pi * (X.sum(axis=-1) + V.sum(axis=-1) - 2 * d * t))
 
     return Workload(
-        name=f"table1_d1_Lp{Lp}", x=x, v=v, lmin=2, L=Lp + 1, r=r, dt=0.5 / nst,
+        name=f"table1_d{d}_Lp{Lp}", x=x, v=v, lmin=2, L=Lp + 1, r=r, dt=1.0 / (2 * d) / nst,
         delta=2.0 ** (-(Lp + 1)), nstrips=nst,
-        beta=[(1.0, (), ()), (1.0, (), ())], sigma=[], xfields={}, vfields={},
+        beta=[(1.0, (), ())] * (2 * d), sigma=[], xfields={}, vfields={},
         u0=lambda X, V: exact(0.0, X, V), f=None, g=None, exact=exact)
 
 
