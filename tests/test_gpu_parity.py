@@ -161,6 +161,28 @@ def test_apply_batch_equals_single(dev):
         assert torch.equal(yb, y[b])
 
 
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d1p", "tiny_d1_r2", "tiny_d2", "tiny_d2_r2", "c1", "c2_L5",
+                                  "c5_L5"])
+@pytest.mark.parametrize("B", [4, 5, 8])
+def test_apply_batches_equal_single_vectors(dev, case, B):
+    """Batches of several vectors (B = 5: an odd count, a last group of vectors
+    per thread with one live vector): every vector equals its single-vector
+    apply bit for bit and the oracle to 1e-10 (FP64) or 2e-5 (FP32)."""
+    w, P, ops = _problem(case, CASES[case])
+    u = random_vector(P.ndof, 13, batch=B)
+    _say(f"batch {B} against single vectors: {case}")
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 2e-5)):
+        ut = torch.tensor(u, device=dev, dtype=dt)
+        yt = torch.empty_like(ut)
+        ops.apply(ut, yt, batch=B)
+        for b in range(B):
+            yb = torch.empty_like(ut[b])
+            ops.apply(ut[b].contiguous(), yb)
+            torch.cuda.synchronize()
+            assert torch.equal(yb, yt[b]), (dt, b)
+            assert _rel(yt[b].double().cpu().numpy(), P.apply(u[b])) <= tol, (dt, b)
+
+
 def test_apply_c2_full_size(dev):
     """BASELINE workload c2 at its full size (L=7, 620 892 space-time DOFs)."""
     w, P, ops = _problem("c2", config_c2)
