@@ -275,6 +275,24 @@ def test_ct_preconditioner_parity(dev, case):
     assert _rel(zt.cpu().numpy(), z_ref) <= 1e-9
 
 
+@pytest.mark.parametrize("case", ["tiny_d1", "tiny_d2", "tiny_d2_r2", "c1"])
+def test_ct_preconditioner_fp32_parity(dev, case):
+    """The FP32 CT (grid problems solved in FP32 to their floor 1e-5) against the
+    oracle's CT with direct solves: its error is the FP32 solve tolerance carried
+    through the combination, stated here (measured about 1e-5)."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem(case, CASES[case])
+    r = random_vector(P.ndof, 9)[0]
+    z_ref = CTPreconditioner(P)(r)
+    rt = torch.tensor(r, device=dev, dtype=torch.float32)
+    zt = torch.empty_like(rt)
+    ops.precondition(rt, zt, sgdg.default_precond_opts(inner_rtol=1e-5, inner_maxit=2000))
+    torch.cuda.synchronize()
+    err = _rel(zt.double().cpu().numpy(), z_ref)
+    _say(f"FP32 CT parity {case}: rel err {err:.2e}")
+    assert err <= 1e-4
+
+
 def _fnorm(P, e):
     R = P.R
     tot = 0.0

@@ -7,9 +7,10 @@ oracle's quadrature on the CPU).
 * d = 1: the errors are within 12% of the paper's and the observed orders
   within 0.05 of its orders for L >= 3 (the bar the oracle meets: the paper
   compares with an order-(r+1) interpolant of u, this evaluation with u itself);
-* d = 2: the observed order reaches the rate h^(r+1/2) = h^1.5 of Thm. 3 and
-  the paper's 1.50 at L = 5 (P1 on Kuhn simplices here, cubes in the paper, so
-  the error values differ by a factor that settles near 1.65);
+* d = 2: the observed order reaches the rate h^(r+1/2) = h^1.5 of the
+  convergence theorem (thm:convergence) and the paper's 1.50 at L = 5 (P1 on
+  Kuhn simplices here, cubes in the paper, so the error values differ by a
+  factor that settles near 1.65);
 * d = 3: the error falls with the level (pre-asymptotic at these levels, as in
   the paper).
 """

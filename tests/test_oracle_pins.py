@@ -456,8 +456,8 @@ def test_discrete_exact_solution_needs_every_data_term():
 def test_forced_convergence_c1(r):
     """c1 with a reaction sigma = 0.5 and the forcing f = sigma u that keeps
     sin(2 pi (x - v t)) exp(-4 v^2) exact: the error at the final time falls
-    with every level (Thm 3: order r + 1/2 in the SD norm, less in L2 near the
-    time-step floor)."""
+    with every level (the convergence theorem, thm:convergence: order r + 1/2
+    in the SD norm; less in L2 near the time-step floor)."""
     errs = []
     for L in (4, 5, 6):
         w = config_c1()
