@@ -324,6 +324,31 @@ def test_solve_strip_parity(dev, case):
     assert dist <= 1e-8
 
 
+@pytest.mark.parametrize("case", ["c2_L5", "c5_L5"])
+def test_capped_inner_solves_still_converge(dev, case):
+    """Grid problems cut off after 5 GMRES iterations make the CT an inexact,
+    changing preconditioner; the flexible outer iteration still reaches the
+    tolerance and the oracle's solution."""
+    from paper_2204_05988_amd import sgdg
+    w, P, ops = _problem(case, CASES[case])
+    u0 = ostrip.initial_coefficients(P)
+    b_ref = ostrip.rhs(P, 1, u0, 1)
+    x_ref, _ = __import__("oracle.krylov", fromlist=["fgmres"]).fgmres(
+        P.apply, b_ref, CTPreconditioner(P), tol=1e-11, restart=50, maxit=300)
+    b = torch.tensor(b_ref, device=dev)
+    x = torch.zeros_like(b)
+    opts = sgdg.default_solve_opts(rtol=1e-10, maxit=400, pc=sgdg.default_precond_opts(inner_maxit=5))
+    x, st = ops.solve_strip(b, x, opts)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(b_ref - P.apply(xg)) / np.linalg.norm(b_ref)
+    dist = _fnorm(P, xg - x_ref) / _fnorm(P, x_ref)
+    _say(f"capped inner solves {case}: outer {st.outer_iters}, inner {st.inner_iters_total}, residual {res:.2e}, "
+         f"L2 distance {dist:.2e}")
+    assert st.inner_iters_total <= 5 * st.pc_applications
+    assert res <= 2e-10
+    assert dist <= 1e-8
+
+
 def test_march_c1_matches_oracle(dev):
     """Eight strips of c1 entirely on the device (rhs, solve, trace update)."""
     from paper_2204_05988_amd import sgdg
