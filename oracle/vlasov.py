@@ -25,11 +25,17 @@ Discrete readings (the paper names the method only):
   * the change of f is measured in L2 (cross-grid mass), the paper's H1 norm
     being a stopping heuristic.
 
+The linear theory at the end (the dielectric function of Maxwellian beams and
+its roots) is an independent check of the runs' rates, not part of the scheme.
+
 Parity: pinned by the tests -- a density of a single-grid product function
 integrates exactly; the discrete field of rho = 1 + a cos(k x) converges to
 -(a/k) sin(k x) at second order; the 1+1-dimensional Landau damping decays at
 the linear-theory rate gamma ~ 0.153 with mass conserved to the solver
-tolerance.
+tolerance; the dielectric root of a Maxwellian at k = 1/2 damps at the
+paper's 0.153, the two-stream rate tends to the closed form of cold beams as
+the thermal speed goes to zero, and the symmetric two-stream dielectric is real
+on the imaginary axis.
 """
 from __future__ import annotations
 
@@ -39,7 +45,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from workloads import config_landau
+from workloads import config_landau, config_twostream
 
 from .ct import CTPreconditioner
 from .fe import assemble
@@ -169,3 +175,78 @@ def decay_rate(rec, t_max=None):
     pk = [i for i in range(1, len(e) - 1) if e[i] >= e[i - 1] and e[i] >= e[i + 1]]
     slope = np.polyfit(t[pk], np.log(e[pk]), 1)[0]
     return -0.5 * slope, t[pk], e[pk]
+
+
+# --- linear theory: an independent check of the runs (not part of the scheme) -------------
+
+def dielectric(omega, k, beams):
+    """Longitudinal dielectric function of a plasma of Maxwellian beams, each given
+    as (weight, drift u, thermal speed s), in the units of the runs (plasma
+    frequency 1):
+
+        eps(omega, k) = 1 + sum_b weight_b (1 + zeta_b Z(zeta_b)) / (k s_b)^2,
+        zeta_b = (omega / k - u_b) / (sqrt(2) s_b),
+
+    with the plasma dispersion function Z(zeta) = i sqrt(pi) w(zeta), w the
+    Faddeeva function (scipy.special.wofz), which continues the Landau contour
+    below the real axis.  Roots in omega are the linear modes exp(i(kx - omega t))."""
+    from scipy.special import wofz
+    omega = complex(omega)
+    out = 1.0 + 0.0j
+    for wt, u, sd in beams:
+        z = (omega / k - u) / (math.sqrt(2.0) * sd)
+        out += wt * (1.0 + z * 1j * math.sqrt(math.pi) * wofz(z)) / (k * sd) ** 2
+    return out
+
+
+def dispersion_root(k, beams, guess, tol=1e-13, maxit=100):
+    """A root of eps(., k) = 0 near guess by the secant method."""
+    w0, w1 = complex(guess), complex(guess) * (1 + 1e-4) + 1e-6
+    f0, f1 = dielectric(w0, k, beams), dielectric(w1, k, beams)
+    for _ in range(maxit):
+        w2 = w1 - f1 * (w1 - w0) / (f1 - f0)
+        if abs(w2 - w1) < tol * max(1.0, abs(w2)):
+            return w2
+        w0, f0, w1, f1 = w1, f1, w2, dielectric(w2, k, beams)
+    raise RuntimeError("dispersion root did not converge")
+
+
+def landau_mode(k=0.5):
+    """Frequency and damping of the least-damped mode of a unit Maxwellian."""
+    return dispersion_root(k, [(1.0, 0.0, 1.0)], 1.0 + 1.5 * k * k - 0.1j)
+
+
+def twostream_growth_rate(k=0.2, v0=2.4, vth=1.0):
+    """Growth rate gamma of the symmetric two-stream mode (omega = i gamma) of two
+    beams of half the density at +-v0 with thermal speed vth (the field amplitude
+    grows as exp(gamma t)); 0 if the mode is stable."""
+    from scipy.optimize import brentq
+    beams = [(0.5, v0, vth), (0.5, -v0, vth)]
+    f = lambda g: dielectric(1j * g, k, beams).real
+    hi = k * v0 + 1.0
+    if f(1e-9) * f(hi) > 0:
+        return 0.0
+    return brentq(f, 1e-9, hi, xtol=1e-14)
+
+
+def cold_twostream_growth_rate(k=0.2, v0=2.4):
+    """The cold-beam limit: 1 = (1/2) [1 / (omega - k v0)^2 + 1 / (omega + k v0)^2]
+    gives omega^2 = ((2a^2 + 1) - sqrt(8a^2 + 1)) / 2 with a = k v0."""
+    a = k * v0
+    w2 = ((2 * a * a + 1) - math.sqrt(8 * a * a + 1)) / 2
+    return math.sqrt(-w2) if w2 < 0 else 0.0
+
+
+def growth_rate(rec, t0, t1):
+    """Growth rate of the field amplitude from the electric energy records
+    (energy ~ exp(2 gamma t)): least-squares slope of log(energy) on [t0, t1] / 2."""
+    t = np.array([r["t"] for r in rec])
+    e = np.array([r["energy"] for r in rec])
+    keep = (t >= t0) & (t <= t1)
+    return 0.5 * float(np.polyfit(t[keep], np.log(e[keep]), 1)[0])
+
+
+def twostream_workload(d=1, paper_level=5, r=1, dt=0.5, **kw):
+    """The two-stream workload (its data live with the other workloads)."""
+    return config_twostream(d, paper_level, r, dt, **kw)
+

@@ -126,3 +126,36 @@ def test_landau_damping_on_the_device(dev):
     assert abs(gamma - 0.153) < 0.1 * 0.153
     assert abs(m1 / m0 - 1) < 1e-6
     vp.close()
+
+
+def test_twostream_instability_grows_at_the_linear_rate(dev):
+    """The 1+1-dimensional two-stream instability of Sect. 5.3 (alpha = 1e-3,
+    k = 1/5, v0 = 2.4 on (0, 10 pi) x (-9, 9), paper level 5, 0.5 time units per
+    strip) on the device: once the growing mode dominates (t in [10, 20]) the
+    field amplitude grows at the rate of the linear dispersion relation of two
+    Maxwellian beams (gamma = 0.2258) to within 10%, and the mass is conserved."""
+    from paper_2204_05988_amd import sgdg
+    w = V.twostream_workload(d=1, paper_level=5)
+    P = Problem(w)
+    vp = sgdg.VlasovPoisson(w)
+    f = torch.tensor(ostrip.initial_coefficients(P), device=dev)
+    E, en0 = vp.field(vp.density(f, 1))
+    rec = [dict(t=0.0, energy=en0)]
+    m0 = V.mass(P, f.cpu().numpy())
+    opts = sgdg.default_solve_opts(rtol=1e-10, pc=sgdg.default_precond_opts(mass_sweeps=-2))
+    prev = 1
+    for j in range(1, 41):
+        f, _, st = vp.strip(f, prev, E, fp_tol=1e-6, solve=opts)
+        prev = P.R
+        E, en = vp.field(vp.density(f, P.R, 1.0))
+        rec.append(dict(t=0.5 * j, energy=en))
+    gamma = V.growth_rate(rec, 10.0, 20.0)
+    lin = V.twostream_growth_rate(0.2, 2.4)
+    m1 = V.mass(P, ostrip.trace_right(P, f.cpu().numpy(), P.R))
+    _say(f"  two-stream: growth rate {gamma:.4f} (linear theory {lin:.4f}), energy {rec[20]['energy']:.2e} -> "
+         f"{rec[40]['energy']:.2e}, mass drift {abs(m1 / m0 - 1):.2e}")
+    assert abs(gamma / lin - 1) < 0.1
+    assert rec[40]["energy"] > 10 * rec[20]["energy"]
+    assert abs(m1 / m0 - 1) < 1e-6
+    vp.close()
+

@@ -67,3 +67,31 @@ def test_landau_damping_rate():
     assert abs(omega - 1.4156) < 0.1 * 1.4156, omega
     assert drift < 1e-6, drift
     assert rec[-1]["energy"] < 0.01 * rec[0]["energy"]
+
+
+def test_landau_root_damps_at_the_papers_rate():
+    """The least-damped root of a unit Maxwellian's dielectric function at k = 1/2
+    damps at the rate the paper quotes from linear analysis (gamma ~ 0.153)."""
+    w = V.landau_mode(0.5)
+    assert abs(V.dielectric(w, 0.5, [(1.0, 0.0, 1.0)])) < 1e-12
+    assert abs(-w.imag - 0.153) < 0.0006
+    assert 1.40 < w.real < 1.43
+
+
+def test_twostream_rate_tends_to_cold_beams():
+    """As the thermal speed goes to zero the two-stream growth rate tends to the
+    closed form of two cold beams; at unit thermal speed it is smaller."""
+    cold = V.cold_twostream_growth_rate(0.2, 2.4)
+    a, om = 0.2 * 2.4, 1j * cold
+    assert abs(0.5 * (1 / (om - a) ** 2 + 1 / (om + a) ** 2) - 1) < 1e-12  # the cold beams' dispersion relation
+    for vth, tol in ((1e-2, 1e-4), (1e-3, 1e-6)):
+        assert abs(V.twostream_growth_rate(0.2, 2.4, vth) - cold) < tol
+    g = V.twostream_growth_rate(0.2, 2.4, 1.0)
+    assert 0.0 < g < cold
+    beams = [(0.5, 2.4, 1.0), (0.5, -2.4, 1.0)]
+    assert abs(V.dielectric(1j * g, 0.2, beams)) < 1e-10
+    for s in (0.1, 0.3, 1.0):
+        assert abs(V.dielectric(1j * s, 0.2, beams).imag) < 1e-12
+    # a single beam (no counter-stream) is stable
+    assert V.twostream_growth_rate(0.2, 0.0, 1.0) == 0.0
+

@@ -25,7 +25,7 @@ __all__ = [
     "Domain", "Workload", "lattice_shape", "lattice_coords", "nodal_fields",
     "grid_levels", "gauss_legendre_times", "random_vector", "sample_on_grids",
     "config_c1", "config_c2", "config_c3", "config_c4_member", "config_c4",
-    "config_c5", "config_table1", "config_tiny", "config_landau", "config_timedep_exact",
+    "config_c5", "config_table1", "config_tiny", "config_landau", "config_twostream", "config_timedep_exact",
     "with_time_fields", "h_min",
 ]
 
@@ -322,31 +322,50 @@ def config_table1(Lp: int, r: int = 1, d: int = 1) -> Workload:
         u0=lambda X, V: exact(0.0, X, V), f=None, g=None, exact=exact)
 
 
-def config_landau(d: int = 1, paper_level: int = 5, r: int = 1, dt: float = 0.5, alpha: float = 1e-2,
-                  k: float = 0.5, E=None, vmax: float = 6.0) -> Workload:
-    """Landau damping (Sect. 5.3): periodic (0, 4 pi)^d x (-vmax, vmax)^d, four cells per
-    axis on the coarsest level (lmin = 2, so the paper's level L is L + 1 here),
-    f0 = exp(-|v|^2/2) / (2 pi)^(d/2) * (1 + alpha sum_i cos(k x_i)), beta = (v, -E(x))
-    with E the nodal field on the finest x-lattice, [d][n] (zero when None)."""
+def _vp_workload(name, d, paper_level, r, dt, length, vmax, f0, E, tend):
+    """Periodic (0, length)^d x (-vmax, vmax)^d for the Vlasov-Poisson runs of Sect. 5.3,
+    four cells per axis on the coarsest level (lmin = 2, so the paper's level L is
+    L + 1 here), beta = (v, -E(x)) with E the nodal field on the finest x-lattice,
+    [d][n] (zero when None), delta = 0.5 h_min, strips up to time tend."""
     lmin = 2
     L = lmin + paper_level - 1
-    x = Domain(d, (0.0,) * d, (4 * np.pi,) * d, periodic=True)
+    x = Domain(d, (0.0,) * d, (length,) * d, periodic=True)
     v = Domain(d, (-vmax,) * d, (vmax,) * d)
     nfine = (2 ** L) ** d
     Ef = np.zeros((d, nfine)) if E is None else np.asarray(E, float).reshape(d, nfine)
     beta = [(1.0, (), (f"v{i}",)) for i in range(d)] + [(-1.0, (f"E{i}",), ()) for i in range(d)]
-    h = min(4 * np.pi, 2 * vmax) / 2 ** L
+    h = min(length, 2 * vmax) / 2 ** L
+    return Workload(
+        name=f"{name}_d{d}_L{paper_level}", x=x, v=v, lmin=lmin, L=L, r=r, dt=dt, delta=0.5 * h,
+        nstrips=int(round(tend / dt)), beta=beta, sigma=[],
+        xfields={f"E{i}": (lambda P, i=i: Ef[i].copy()) for i in range(d)},
+        vfields={f"v{i}": _coord(i) for i in range(d)},
+        u0=f0, f=None, g=None, exact=None)
+
+
+def config_landau(d: int = 1, paper_level: int = 5, r: int = 1, dt: float = 0.5, alpha: float = 1e-2,
+                  k: float = 0.5, E=None, vmax: float = 6.0) -> Workload:
+    """Landau damping (Sect. 5.3): periodic (0, 4 pi)^d x (-vmax, vmax)^d,
+    f0 = exp(-|v|^2/2) / (2 pi)^(d/2) * (1 + alpha sum_i cos(k x_i)), on [0, 50]."""
 
     def f0(X, V):
         return (np.exp(-0.5 * np.sum(V * V, axis=-1)) / (2 * np.pi) ** (d / 2)
                 * (1 + alpha * np.sum(np.cos(k * X), axis=-1)))
 
-    return Workload(
-        name=f"landau_d{d}_L{paper_level}", x=x, v=v, lmin=lmin, L=L, r=r, dt=dt, delta=0.5 * h,
-        nstrips=int(round(50 / dt)), beta=beta, sigma=[],
-        xfields={f"E{i}": (lambda P, i=i: Ef[i].copy()) for i in range(d)},
-        vfields={f"v{i}": _coord(i) for i in range(d)},
-        u0=f0, f=None, g=None, exact=None)
+    return _vp_workload("landau", d, paper_level, r, dt, 4 * np.pi, vmax, f0, E, 50.0)
+
+
+def config_twostream(d: int = 1, paper_level: int = 5, r: int = 1, dt: float = 0.5, alpha: float = 1e-3,
+                     k: float = 0.2, v0: float = 2.4, vmax: float = 9.0, E=None) -> Workload:
+    """Two-stream instability (Sect. 5.3): periodic (0, 10 pi)^d x (-9, 9)^d,
+    f0 = prod_i (exp(-(v_i - v0)^2/2) + exp(-(v_i + v0)^2/2)) / (2 sqrt(2 pi))^d
+         * (1 + alpha sum_i cos(k x_i)), on [0, 50] (the Landau runs' interval and strips)."""
+
+    def f0(X, V):
+        beams = np.prod(np.exp(-0.5 * (V - v0) ** 2) + np.exp(-0.5 * (V + v0) ** 2), axis=-1)
+        return beams / (2 * np.sqrt(2 * np.pi)) ** d * (1 + alpha * np.sum(np.cos(k * X), axis=-1))
+
+    return _vp_workload("twostream", d, paper_level, r, dt, 2 * np.pi / k, vmax, f0, E, 50.0)
 
 
 def with_time_fields(w: Workload, tfields, tquad: int = 0) -> Workload:
