@@ -36,8 +36,10 @@ Prints one JSON line.  Beside the headline number:
     vectors in FP64 and 1 in FP32;
   * apply_2d: the 2D phase-space problem (d=1, L=6) applied to a batch, and
     its 8-strip march with CT-preconditioned FGMRES to 1e-10;
-  * vlasov_poisson: Landau damping in 1+1 and 2+2 dimensions with the
-    per-strip fixed point of transport and field;
+  * vlasov_poisson: Landau damping in 1+1 and 2+2 dimensions and the 1+1
+    two-stream instability (with --twostream-2d also the 2+2 one over [0, 50],
+    the run whose wall time the paper reports), the per-strip fixed point of
+    transport and field, the electric energy and the two-stream growth rate;
   * table1: the periodic advection test of Sect. 5.1 (r = 1) for d = 1, 2, 3:
     every strip of one period solved on the device, the error in the SD norm
     and its observed order beside the paper's Table 1;
@@ -81,6 +83,8 @@ def parse():
                     help="learned leg reduced to the network's forward rate (freshly initialised weights)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-vp", action="store_true", help="skip the Vlasov-Poisson leg")
+    ap.add_argument("--twostream-2d", action="store_true",
+                    help="add the 2+2-dimensional two-stream run at the paper's level 5 over [0, 50] (about 4 minutes)")
     ap.add_argument("--table1", default="6,6,3",
                     help="highest paper levels of the Table-1 leg for d = 1,2,3 (0 skips a dimension; 0 alone skips the leg)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
@@ -394,7 +398,10 @@ def main():
     if a.batched > 0:
         out["batched"] = batched_leg(dev, a.batched)
     if not a.no_vp:
-        out["vlasov_poisson"] = vlasov_poisson_leg(dev)
+        runs = (("landau", 1, 5, 20), ("landau", 2, 5, 3), ("twostream", 1, 5, 100))
+        if a.twostream_2d:
+            runs = runs + (("twostream", 2, 5, 100),)
+        out["vlasov_poisson"] = vlasov_poisson_leg(dev, runs)
     if a.c3_level > 0:
         out["apply_6d"] = apply_6d_leg(dev, a.c3_level)
     t1 = tuple((d + 1, int(m)) for d, m in enumerate(a.table1.split(",")) if m and int(m) > 0)
@@ -662,16 +669,19 @@ def batched_learned_leg(dev, n=4, L=7, record_strips=8, train_steps=500):
     return out
 
 
-def vlasov_poisson_leg(dev, runs=((1, 5, 20), (2, 5, 3))):
-    """Landau damping (Sect. 5.3 setting: alpha = 0.01, k = 1/2, (0, 4 pi)^d x (-6, 6)^d,
-    0.5 time units per strip, r = 1): (d, paper level, strips) per run; the per-strip
-    fixed point of transport and field on the device, with its electric energy."""
+def vlasov_poisson_leg(dev, runs=(("landau", 1, 5, 20), ("landau", 2, 5, 3), ("twostream", 1, 5, 100))):
+    """Sect. 5.3 on the device, per run (problem, d, paper level, strips) with 0.5 time
+    units per strip and r = 1: Landau damping (alpha = 0.01, k = 1/2, (0, 4 pi)^d x
+    (-6, 6)^d) and the two-stream instability (alpha = 1e-3, k = 1/5, v0 = 2.4,
+    (0, 10 pi)^d x (-9, 9)^d); the per-strip fixed point of transport and field,
+    its electric energy, and for the two-stream runs the growth rate on [10, 20]
+    beside the linear theory's 0.2258 (two Maxwellian beams, k = 1/5, v0 = 2.4)."""
     import torch
     from paper_2204_05988_amd import sgdg
-    from workloads import config_landau
+    from workloads import config_landau, config_twostream
     out = {}
-    for d, pl, nst in runs:
-        w = config_landau(d, pl)
+    for prob, d, pl, nst in runs:
+        w = config_landau(d, pl) if prob == "landau" else config_twostream(d, pl)
         ops = sgdg.SparseGridOps(w)
         f = _interp_u0(ops, w, dev)
         ops.close()
@@ -691,12 +701,20 @@ def vlasov_poisson_leg(dev, runs=((1, 5, 20), (2, 5, 3))):
             secs.append(round(st.seconds, 4))
             asm.append(round(st.assemble_seconds, 4))
             outer.append(st.outer_iters)
+            if (j + 1) % 10 == 0:
+                _log(f"vlasov-poisson {prob} d={d}: strip {j + 1}/{nst}, energy {en:.3e}, "
+                     f"{time.perf_counter() - t0:.1f}s")
         total = time.perf_counter() - t0
-        key = f"landau_{d}d{d}v_paper_level{pl}"
-        out[key] = {"dofs": vp.ndof, "x_nodes": vp.n_fine, "strips": nst, "seconds": round(total, 3),
-                    "fixed_point_iters": fps, "fgmres_iters": outer, "strip_seconds": secs,
-                    "assemble_seconds": asm, "electric_energy": energies}
-        _log(f"vlasov-poisson {key}: {nst} strips in {total:.2f}s, fixed point {fps}")
+        key = f"{prob}_{d}d{d}v_paper_level{pl}"
+        out[key] = {"dofs": vp.ndof, "x_nodes": vp.n_fine, "strips": nst, "t_end": nst * w.dt,
+                    "seconds": round(total, 3), "fixed_point_iters": fps, "fgmres_iters": outer,
+                    "strip_seconds": secs, "assemble_seconds": asm, "electric_energy": energies}
+        if prob == "twostream" and nst * w.dt >= 20:
+            t = np.arange(nst + 1) * w.dt
+            keep = (t >= 10) & (t <= 20)
+            out[key]["growth_rate_10_20"] = 0.5 * float(np.polyfit(t[keep], np.log(np.array(energies)[keep]), 1)[0])
+            out[key]["growth_rate_linear_theory"] = 0.2258
+        _log(f"vlasov-poisson {key}: {nst} strips in {total:.2f}s, fixed point {fps[:5]}...")
         vp.close()
     return out
 
