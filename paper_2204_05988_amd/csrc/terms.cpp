@@ -249,7 +249,8 @@ bool proportional(const double* ti, const double* tj, int n, double* a) {
   return true;
 }
 
-// The factor c_i F_i + c_j F_j (F_i, F_j of one kind), registered as a combination.
+// The factor c_i F_i + c_j F_j (F_i, F_j of one kind), registered as a
+// combination; -1 if the parts cancel.
 int combine(DomainData& D, int fi, double ci, int fj, double cj) {
   std::map<int, double> acc;
   auto add = [&](int f, double c) {
@@ -266,6 +267,7 @@ int combine(DomainData& D, int fi, double ci, int fj, double cj) {
   key.kind = D.factors[size_t(fi)].kind;
   for (const auto& e : acc)
     if (e.second != 0.0) key.parts.push_back({e.second, e.first});
+  if (key.parts.empty()) return -1;
   if (key.parts.size() == 1 && key.parts[0].first == 1.0) return key.parts[0].second;
   return D.factor_id(key);
 }
@@ -296,6 +298,12 @@ void merge_terms(DomainData& X, DomainData& V, TermList& L) {
           continue;
         }
         L.terms.erase(L.terms.begin() + std::ptrdiff_t(j));
+        bool zero = a.xf < 0 || a.vf < 0;  // the pair cancels
+        if (!zero) {
+          zero = true;
+          for (int k = 0; k < n; ++k) zero = zero && a.tm[k] == 0.0;
+        }
+        if (zero) L.terms.erase(L.terms.begin() + std::ptrdiff_t(i));
         changed = true;
       }
   }
