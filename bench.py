@@ -83,6 +83,10 @@ def parse():
                     help="learned leg reduced to the network's forward rate (freshly initialised weights)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D phase-space (d=1) leg")
     ap.add_argument("--no-vp", action="store_true", help="skip the Vlasov-Poisson leg")
+    ap.add_argument("--vp-run", default="",
+                    help="PROBLEM,D,LEVEL,DT,J0,J1: only strips J0..J1 of one Vlasov-Poisson run (landau or "
+                         "twostream); J0 > 1 resumes from --vp-state, and the final state is written there")
+    ap.add_argument("--vp-state", default="", help="state file (.npz) of --vp-run")
     ap.add_argument("--twostream-2d", action="store_true",
                     help="add the 2+2-dimensional two-stream run at the paper's level 5 over [0, 50] (about 4 minutes)")
     ap.add_argument("--table1", default="6,6,3",
@@ -315,6 +319,9 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU; execution across several GPUs is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.vp_run:
+        print(json.dumps({"vp_run": vp_segment(a.vp_run, a.vp_state)}), flush=True)
+        return
     import torch
     from paper_2204_05988_amd import sgdg
     from workloads import config_c2
@@ -716,6 +723,64 @@ def vlasov_poisson_leg(dev, runs=(("landau", 1, 5, 20), ("landau", 2, 5, 3), ("t
             out[key]["growth_rate_linear_theory"] = 0.2258
         _log(f"vlasov-poisson {key}: {nst} strips in {total:.2f}s, fixed point {fps[:5]}...")
         vp.close()
+    return out
+
+
+def vp_segment(spec, state):
+    """Strips J0..J1 of one Vlasov-Poisson run (spec "PROBLEM,D,LEVEL,DT,J0,J1"), the
+    per-strip fixed point on the device; a run longer than one sitting is split into
+    segments that hand over f, E and the energy history through the state file."""
+    import torch
+    from paper_2204_05988_amd import sgdg
+    from workloads import config_landau, config_twostream
+    prob, d, pl, dt, j0, j1 = spec.split(",")
+    d, pl, dt, j0, j1 = int(d), int(pl), float(dt), int(j0), int(j1)
+    w = (config_landau if prob == "landau" else config_twostream)(d, pl, dt=dt)
+    dev = torch.device("cuda:0")
+    vp = sgdg.VlasovPoisson(w)
+    if j0 == 1:
+        ops = sgdg.SparseGridOps(w)
+        f = _interp_u0(ops, w, dev)
+        ops.close()
+        E, en = vp.field(vp.density(f, 1))
+        prev, energies, before = 1, [en], 0.0
+    else:
+        z = np.load(state)
+        f = torch.tensor(z["f"], device=dev)
+        E = torch.tensor(z["E"], device=dev)
+        prev, energies, before = int(z["prev"]), list(z["energies"]), float(z["seconds"])
+        if len(energies) != j0:
+            raise SystemExit(f"the state holds {len(energies) - 1} strips, not {j0 - 1}")
+    vopts = sgdg.default_solve_opts(rtol=1e-10, pc=sgdg.default_precond_opts(mass_sweeps=-2))
+    fps, outer, secs, asm = [], [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(j0, j1 + 1):
+        f, _, st = vp.strip(f, prev, E, fp_tol=1e-6, solve=vopts, raise_on_noconv=False)
+        prev = w.r + 1
+        E, en = vp.field(vp.density(f, prev, 1.0))
+        energies.append(en)
+        fps.append(st.fp_iters)
+        outer.append(st.outer_iters)
+        secs.append(round(st.seconds, 3))
+        asm.append(round(st.assemble_seconds, 3))
+        if (j - j0 + 1) % 10 == 0:
+            _log(f"{prob} d={d} level {pl}: strip {j}/{j1}, t = {j * dt:g}, energy {en:.3e}, "
+                 f"{time.perf_counter() - t0:.1f}s")
+    seconds = time.perf_counter() - t0
+    if state:
+        np.savez(state, f=f.cpu().numpy(), E=E.cpu().numpy(), prev=prev, energies=np.array(energies),
+                 seconds=before + seconds)
+    out = {"problem": prob, "d": d, "paper_level": pl, "dt": dt, "strips": [j0, j1], "dofs": vp.ndof,
+           "seconds": round(seconds, 2), "seconds_all_segments": round(before + seconds, 2),
+           "fixed_point_iters": fps, "fgmres_iters": outer, "strip_seconds": secs, "assemble_seconds": asm,
+           "electric_energy": energies}
+    if prob == "twostream":
+        t = np.arange(len(energies)) * dt
+        keep = (t >= 10) & (t <= 20)
+        if keep.sum() >= 3:
+            out["growth_rate_10_20"] = 0.5 * float(np.polyfit(t[keep], np.log(np.array(energies)[keep]), 1)[0])
+    vp.close()
     return out
 
 
