@@ -87,6 +87,8 @@ def parse():
                     help="PROBLEM,D,LEVEL,DT,J0,J1: only strips J0..J1 of one Vlasov-Poisson run (landau or "
                          "twostream); J0 > 1 resumes from --vp-state, and the final state is written there")
     ap.add_argument("--vp-state", default="", help="state file (.npz) of --vp-run")
+    ap.add_argument("--learned-run", type=int, default=0,
+                    help="only the learned leg, with pairs recorded from this many CT-preconditioned strips")
     ap.add_argument("--twostream-2d", action="store_true",
                     help="add the 2+2-dimensional two-stream run at the paper's level 5 over [0, 50] (about 4 minutes)")
     ap.add_argument("--table1", default="6,6,3",
@@ -323,6 +325,10 @@ def main():
         print(json.dumps({"vp_run": vp_segment(a.vp_run, a.vp_state)}), flush=True)
         return
     import torch
+    if a.learned_run:
+        leg = learned_leg(torch.device("cuda:0"), a.train_steps, record_strips=a.learned_run)
+        print(json.dumps({"learned_run": leg}), flush=True)
+        return
     from paper_2204_05988_amd import sgdg
     from workloads import config_c2
 
