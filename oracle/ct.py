@@ -16,8 +16,10 @@ the spanning coefficients of the sparse-grid interpolant (the combination
 technique is exact for interpolation, Sect. 4.3).
 
 Parity: pinned by the tests (one-grid sparse grid gives A^{-1}; linearity;
-reproduction of the sparse-grid interpolant).  Beyond these special cases the
-preconditioner is a heuristic with no closed form: parity unpinned.
+P_CT(A u) = u for u in V_lmin (x) V_lmin, the space every component grid
+contains, because each grid problem is A restricted to its component space;
+reproduction of the sparse-grid interpolant).  For general residuals the
+preconditioner has no closed form beyond these steps.
 """
 from __future__ import annotations
 

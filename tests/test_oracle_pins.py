@@ -307,6 +307,38 @@ def test_ct_linear_and_interpolation_exact():
     assert e @ P.apply_mass(e) < 1e-26
 
 
+@pytest.mark.parametrize("kind", ["d1", "d1p", "d2"])
+def test_ct_reproduces_functions_common_to_all_grids(kind):
+    """Algorithm 1's grid problems are the operator restricted to each component
+    space (the lower grids' residuals are x-restrictions of their upper
+    partners', i.e. the same dual values), so for u in the space every grid
+    contains, V_lmin (x) V_lmin, each grid solve returns u on that grid; the
+    combination (one more upper than lower grid) returns u itself:
+    P_CT(A u) = u.  A dropped or sign-flipped lower-grid term, a transposed
+    restriction or a wrong grid operator breaks it."""
+    P = Problem(config_tiny(kind))
+    lmin, R = P.w.lmin, P.R
+    g0 = next(g for g in P.upper if g[0] == lmin)
+    Ev = P.E("v", g0[1], lmin)
+    rng = np.random.default_rng(11)
+    u = np.zeros(P.ndof)
+    blocks = P.split(u)
+    i0 = P.upper.index(g0)
+    for s in range(R):
+        c = rng.standard_normal((P.nx(lmin), P.nv(lmin)))
+        blocks[i0][s] = (Ev @ c.T).T
+    z = CTPreconditioner(P)(P.apply(u))
+    e = z - u
+
+    def slice_of(vec, s):
+        return np.concatenate([b[s].ravel() for b in P.split(vec)])
+
+    for s in range(R):
+        es, us = slice_of(e, s), slice_of(u, s)
+        assert es @ P.apply_mass(es) <= 1e-22 * (us @ P.apply_mass(us))
+    assert np.abs(e).max() < 1e-10 * np.abs(u).max()
+
+
 def test_fgmres_solves_nonsingular_system():
     rng = np.random.default_rng(6)
     A = np.eye(40) * 3 + rng.standard_normal((40, 40)) * 0.3
