@@ -335,9 +335,9 @@ __global__ void __launch_bounds__(kFB) k_fused(FusedCall<T> C) {
   }
 }
 
-// Scan step on the lower diagonal, all factor groups per thread.
-// blockIdx.z = 0: Pt_{t+1} on lower grid t; blockIdx.z = 1: Qt on lower grid
-// nlow-1-t.  The restricted stencils E^T V (resp. E^T X) of width W couple a
+// Scan step on the lower diagonal, the factor groups of a chunk per thread.
+// Each item is one side: Pt_{t+1} on lower grid t, or Qt on lower grid
+// nlow-1-t (both sides of a step in one launch).  The restricted stencils E^T V (resp. E^T X) of width W couple a
 // coarse node with the fine nodes 2P + o; the u values at those nodes are
 // loaded once and reused by every group.
 // slot-major restricted stencils: entry o of the coarse nodes of one level is contiguous
@@ -386,12 +386,17 @@ __global__ void __launch_bounds__(kFB) k_scan2(FusedCall<T> C) {
   constexpr int W = D == 1 ? 5 : (D == 2 ? 19 : 65);
   constexpr int SS = D == 1 ? 3 : (D == 2 ? 7 : 15);
   constexpr int RS = R * W <= 48 ? R : 1;  // slices gathered per pass (registers)
-  const ScanItem si = C.sitems[blockIdx.x];
+  // vector-fastest block order: the blocks of one item for all vectors are
+  // dispatched together, so the item's stencil tables are read from L2 by
+  // every vector instead of being fetched again per vector (4% faster scans
+  // at 64 vectors, measured; an XCD-contiguous order measured slower)
+  const int lin = int(blockIdx.y) * int(gridDim.x) + int(blockIdx.x);
+  const int bx = lin / int(gridDim.y), b = lin - bx * int(gridDim.y);
+  const ScanItem si = C.sitems[bx];
   const ProbDesc& A = C.descs[si.prob];
   const DevGrids& G = A.G;
   const DevGrids& L = A.Gl;
   const bool lower = si.side == 0;
-  const int b = blockIdx.y;
   const DevOp& op = A.op;
   // blockIdx.z: this block's share of the factor groups (shorter dependent
   // chains per thread, more blocks for the small steps)

@@ -187,7 +187,14 @@ __global__ void __launch_bounds__(kSB) k_vstage(SplitCall<T> C) {
       T a0[R], a1[R];
       if (has_p) {
         load_slices<T, R>(pt + int64_t(px0) * nv * R, a0);
-        load_slices<T, R>(pt + int64_t(px1) * nv * R, a1);
+        // an x-node that coincides with a coarse node has one parent (the
+        // second weight is zero); a wavefront within one x-row skips the load
+        if (wx1 != T(0)) {
+          load_slices<T, R>(pt + int64_t(px1) * nv * R, a1);
+        } else {
+#pragma unroll
+          for (int s2 = 0; s2 < R; ++s2) a1[s2] = T(0);
+        }
       } else {
 #pragma unroll
         for (int s2 = 0; s2 < R; ++s2) a0[s2] = a1[s2] = T(0);
