@@ -21,6 +21,10 @@ struct KernelsT {
   // w += sign * sum_k coef[seg][k] V_k; optional partial norms of the result
   static void seg_axpy(const SegTable& S, const T* V, int64_t vstride, int nvec, const double* coef, int cstride,
                        T* w, double sign, double* partial_norm, hipStream_t s);
+  // w -= sum_k coef[seg][k] V_k, then partial as seg_dots of the new w (one
+  // Gram-Schmidt pass and the next pass's projections in one launch)
+  static void seg_axpy_dots(const SegTable& S, const T* V, int64_t vstride, int nvec, const double* coef,
+                            int cstride, T* w, double* partial, hipStream_t s);
   static void seg_scale(const SegTable& S, const T* w, const double* scal, T* out, hipStream_t s);
   static void seg_norm2(const SegTable& S, const T* w, double* partial, hipStream_t s);
   // combination technique on the CT segment table (upper grids then lower grids per problem)

@@ -42,25 +42,21 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 // ------------------------------------------------------------ segments ----
+constexpr int kDotWaves = kBlock / 64;
+constexpr int kDotMaxVec = 72;
+
+// partial[(chunk0 + chunk) * nvec + k] = sum over the block's chunk of V_k * wl
+// (wl: the thread's kPer elements of w, 0 past the segment): wave sums per
+// vector in LDS, one barrier, then thread k adds the waves of vector k
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
-                                                     const T* __restrict__ V, int64_t vstride, int nvec,
-                                                     const T* __restrict__ w, double* __restrict__ partial) {
-  // wave sums per vector in LDS, one barrier, then thread k adds the waves of vector k
-  constexpr int kWaves = kBlock / 64;
-  constexpr int kMaxVec = 72;
-  __shared__ double sh[kWaves][kMaxVec];
-  const BlockRef br = blk[blockIdx.x];
-  const SegInfo& S = segs[br.seg];
+__device__ __forceinline__ void chunk_dots(const SegInfo& S, const BlockRef& br, const T* __restrict__ V,
+                                           int64_t vstride, int nvec, const double (&wl)[kPer],
+                                           double* __restrict__ partial, double (*sh)[kDotMaxVec]) {
+  constexpr int kWaves = kDotWaves;
+  constexpr int kMaxVec = kDotMaxVec;
   const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
   const int64_t end = S.off + S.len;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double wl[kPer];
-#pragma unroll
-  for (int t = 0; t < kPer; ++t) {
-    const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
-    wl[t] = i < end ? double(w[i]) : 0.0;
-  }
   double* out = partial + int64_t(S.chunk0 + br.chunk) * nvec;
   for (int k0 = 0; k0 < nvec; k0 += kMaxVec) {
     const int nk = nvec - k0 < kMaxVec ? nvec - k0 : kMaxVec;
@@ -103,6 +99,64 @@ __global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__
     }
     __syncthreads();
   }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_seg_dots(const SegInfo* __restrict__ segs, const BlockRef* __restrict__ blk,
+                                                     const T* __restrict__ V, int64_t vstride, int nvec,
+                                                     const T* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sh[kDotWaves][kDotMaxVec];
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
+  const int64_t end = S.off + S.len;
+  double wl[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
+    wl[t] = i < end ? double(w[i]) : 0.0;
+  }
+  chunk_dots<T>(S, br, V, vstride, nvec, wl, partial, sh);
+}
+
+// One classical Gram-Schmidt pass followed by the next pass's projections:
+// w -= sum_k coef[seg][k] V_k (the arithmetic of k_seg_axpy with sign -1),
+// then partial = <V_k, w> as k_seg_dots computes it.  The block's chunk of
+// every V_k is read from memory once; the second read comes from the cache.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_seg_axpy_dots(const SegInfo* __restrict__ segs,
+                                                          const BlockRef* __restrict__ blk, const T* __restrict__ V,
+                                                          int64_t vstride, int nvec, const double* __restrict__ coef,
+                                                          int cstride, T* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sh[kDotWaves][kDotMaxVec];
+  const BlockRef br = blk[blockIdx.x];
+  const SegInfo& S = segs[br.seg];
+  const int64_t beg = S.off + int64_t(br.chunk) * kChunk;
+  const int64_t end = S.off + S.len;
+  const double* c = coef + int64_t(br.seg) * cstride;
+  const double sign = -1.0;
+  double wl[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int64_t i = beg + int64_t(t) * kBlock + threadIdx.x;
+    wl[t] = 0.0;
+    if (i < end) {
+      double a = double(w[i]);
+      int k = 0;
+      for (; k + 4 <= nvec; k += 4) {
+        double v4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v4[q] = double(V[int64_t(k + q) * vstride + i]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a += sign * c[k + q] * v4[q];
+      }
+      for (; k < nvec; ++k) a += sign * c[k] * double(V[int64_t(k) * vstride + i]);
+      const T r = T(a);
+      w[i] = r;
+      wl[t] = double(r);
+    }
+  }
+  chunk_dots<T>(S, br, V, vstride, nvec, wl, partial, sh);
 }
 
 template <class T>
@@ -601,6 +655,14 @@ void KernelsT<T>::seg_axpy(const SegTable& S, const T* V, int64_t vstride, int n
   if (S.nblk == 0) return;
   hipLaunchKernelGGL(k_seg_axpy<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, V, vstride, nvec, coef, cstride,
                      w, sign, partial_norm);
+  LAUNCH_CHECK();
+}
+template <class T>
+void KernelsT<T>::seg_axpy_dots(const SegTable& S, const T* V, int64_t vstride, int nvec, const double* coef,
+                                int cstride, T* w, double* partial, hipStream_t s) {
+  if (S.nblk == 0) return;
+  hipLaunchKernelGGL(k_seg_axpy_dots<T>, dim3(S.nblk), dim3(kBlock), 0, s, S.segs, S.blk, V, vstride, nvec, coef,
+                     cstride, w, partial);
   LAUNCH_CHECK();
 }
 template <class T>

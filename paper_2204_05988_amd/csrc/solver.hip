@@ -896,11 +896,13 @@ static int batched_gmres(Batch& B, const SegTab& ST, const std::function<void(co
   auto step = [&](int j, hipStream_t q) {
     M(V + int64_t(j) * total, tmp, q);
     A(tmp, w, q);
-    for (int pass = 0; pass < 2; ++pass) {
-      KernelsT<T>::seg_dots(S, V, total, j + 1, w, part, q);
-      gmres_add_proj(nseg, st, S.segs, part, j, q);
-      KernelsT<T>::seg_axpy(S, V, total, j + 1, st.hcol, m + 1, w, -1.0, pass == 1 ? part : nullptr, q);
-    }
+    // CGS2: two projection passes; the first pass's update and the second
+    // pass's projections share one read of the basis
+    KernelsT<T>::seg_dots(S, V, total, j + 1, w, part, q);
+    gmres_add_proj(nseg, st, S.segs, part, j, q);
+    KernelsT<T>::seg_axpy_dots(S, V, total, j + 1, st.hcol, m + 1, w, part, q);
+    gmres_add_proj(nseg, st, S.segs, part, j, q);
+    KernelsT<T>::seg_axpy(S, V, total, j + 1, st.hcol, m + 1, w, -1.0, part, q);
     gmres_givens(nseg, st, S.segs, part, j, tol, q);
     KernelsT<T>::seg_scale(S, w, st.inv, V + int64_t(j + 1) * total, q);
   };
@@ -1412,11 +1414,12 @@ static FgmresResult fgmres(Batch& B, const std::function<void(const double*, dou
       ran = j + 1;  // iterations queued (their directions Z_0..Z_j enter the update)
       P(V + int64_t(j) * n, Z + int64_t(j) * n);
       A(Z + int64_t(j) * n, w);
-      for (int pass = 0; pass < 2; ++pass) {
-        KernelsT<double>::seg_dots(S, V, n, j + 1, w, part, s);
-        gmres_add_proj(nseg, st, S.segs, part, j, s);
-        KernelsT<double>::seg_axpy(S, V, n, j + 1, st.hcol, m + 1, w, -1.0, pass == 1 ? part : nullptr, s);
-      }
+      // CGS2, the first update fused with the second projections
+      KernelsT<double>::seg_dots(S, V, n, j + 1, w, part, s);
+      gmres_add_proj(nseg, st, S.segs, part, j, s);
+      KernelsT<double>::seg_axpy_dots(S, V, n, j + 1, st.hcol, m + 1, w, part, s);
+      gmres_add_proj(nseg, st, S.segs, part, j, s);
+      KernelsT<double>::seg_axpy(S, V, n, j + 1, st.hcol, m + 1, w, -1.0, part, s);
       gmres_givens(nseg, st, S.segs, part, j, tol * 0.5, s);
       KernelsT<double>::seg_scale(S, w, st.inv, V + int64_t(j + 1) * n, s);
       SGDG_CHECK_HIP(hipMemcpyAsync(fr.act[j & 1], st.active, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
