@@ -756,7 +756,8 @@ def vp_segment(spec, state):
         f = torch.tensor(z["f"], device=dev)
         E = torch.tensor(z["E"], device=dev)
         prev, energies, before = int(z["prev"]), list(z["energies"]), float(z["seconds"])
-        masses = list(z["masses"])
+        # (a state written before the mass record existed resumes without it)
+        masses = list(z["masses"]) if "masses" in z.files else []
         if len(energies) != j0:
             raise SystemExit(f"the state holds {len(energies) - 1} strips, not {j0 - 1}")
     vopts = sgdg.default_solve_opts(rtol=1e-10, pc=sgdg.default_precond_opts(mass_sweeps=-2))
@@ -786,7 +787,8 @@ def vp_segment(spec, state):
            "seconds": round(seconds, 2), "seconds_all_segments": round(before + seconds, 2),
            "fixed_point_iters": fps, "fgmres_iters": outer, "strip_seconds": secs, "assemble_seconds": asm,
            "electric_energy": energies,
-           "mass_drift_max": float(np.max(np.abs(np.array(masses) / masses[0] - 1)))}
+           "mass_drift_max": (float(np.max(np.abs(np.array(masses) / masses[0] - 1)))
+                              if len(masses) == len(energies) else None)}
     if prob == "landau":
         # damping rate of the field amplitude from the local maxima of the electric
         # energy (energy ~ exp(-2 gamma t)) up to t = 25, where the paper's runs
