@@ -52,10 +52,15 @@ static inline T* ptr(const DevBuf& b) {
   return static_cast<T*>(b.p);
 }
 
+// While set (refresh_fields), an upload of the size a buffer already has
+// rewrites that allocation in place; otherwise every upload allocates anew.
+extern thread_local bool g_upload_inplace;
+
 template <class T>
 static inline T* upload(DevBuf& b, const std::vector<T>& h) {
-  b.alloc(h.size() * sizeof(T));
-  if (!h.empty()) SGDG_CHECK_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  const size_t nb = h.size() * sizeof(T);
+  if (!(g_upload_inplace && b.bytes == nb && (b.p != nullptr || nb == 0))) b.alloc(nb);
+  if (nb) SGDG_CHECK_HIP(hipMemcpy(b.p, h.data(), nb, hipMemcpyHostToDevice));
   return ptr<T>(b);
 }
 
@@ -133,6 +138,16 @@ struct sgdg_ops_s {
   sgdg_net recorder = nullptr;                 // network recording (r, P_CT r) pairs of this problem
   std::vector<sgdg_net> nets;                  // networks created for this problem
 };
+
+// Re-assembles the operator of o for new values of the coefficient fields the
+// problem registered (read again through the same pointers, which must still be
+// valid): the term lists are rebuilt from p, and if they and the factor
+// registries come out unchanged, the factor tables are recomputed and written
+// into the existing device buffers, so work buffers, launch tables and captured
+// graphs stay valid; cached batches are dropped only if a support mask
+// changed.  Returns false, with o unchanged, if the structure differs (the
+// caller then assembles a new handle).
+bool refresh_fields(sgdg_ops o, const sgdg_problem& p);
 
 // The learned preconditioner (net.hip) as seen by the strip solver.
 void net_apply_dev(sgdg_net n, const double* r, double* z, hipStream_t s);

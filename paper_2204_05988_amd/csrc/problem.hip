@@ -539,6 +539,74 @@ static sgdg_ops assemble_ops(sgdg_grid g, double dt, double delta, F&& terms) {
   return o.release();
 }
 
+thread_local bool g_upload_inplace = false;
+
+static bool same_terms(const TermList& a, const TermList& b) {
+  if (a.Rin != b.Rin || a.Rout != b.Rout || a.terms.size() != b.terms.size()) return false;
+  for (size_t i = 0; i < a.terms.size(); ++i) {
+    const Term &s = a.terms[i], &t = b.terms[i];
+    if (s.xf != t.xf || s.vf != t.vf) return false;
+    for (int k = 0; k < kMaxR * kMaxR; ++k)
+      if (s.tm[k] != t.tm[k]) return false;
+  }
+  return true;
+}
+
+bool refresh_fields(sgdg_ops o, const sgdg_problem& p) {
+  check_problem(o->grid, &p);
+  DomainData X = o->X, V = o->V;
+  bool vchanged = false;
+  for (size_t i = 0; i < X.fields.size(); ++i)
+    std::copy(X.field_src[i], X.field_src[i] + X.fields[i].size(), X.fields[i].begin());
+  for (size_t i = 0; i < V.fields.size(); ++i) {
+    const double* src = V.field_src[i];
+    vchanged = vchanged || !std::equal(V.fields[i].begin(), V.fields[i].end(), src);
+    std::copy(src, src + V.fields[i].size(), V.fields[i].begin());
+  }
+  TermList tl[4];
+  build_terms(X, V, p, o->grid->r, tl);
+  if (X.factors.size() != o->X.factors.size() || V.factors.size() != o->V.factors.size()) return false;
+  for (int k = 0; k < 4; ++k)
+    if (!same_terms(tl[k], o->ops[k].host)) return false;
+  assemble_all(X);
+  if (vchanged) assemble_all(V);
+  // the host-side masks that launch tables and cached batches are built from
+  const auto masks = [&]() {
+    std::vector<std::vector<uint64_t>> m;
+    std::vector<uint64_t> s(o->dx.hsup.begin(), o->dx.hsup.end());
+    s.insert(s.end(), o->dv.hsup.begin(), o->dv.hsup.end());
+    m.push_back(s);
+    for (int k = 0; k < 4; ++k) {
+      const OpDev& od = o->ops[k];
+      m.push_back(od.hxrowm);
+      m.push_back(od.hxreadm);
+      m.push_back(od.hxqtm);
+    }
+    return m;
+  };
+  const auto before = masks();
+  const uint64_t epoch = alloc_epoch();
+  o->X = std::move(X);
+  if (vchanged) o->V = std::move(V);
+  {
+    g_upload_inplace = true;
+    struct Reset {
+      ~Reset() { g_upload_inplace = false; }
+    } reset;
+    const int mfx = o->dx.d.mass_fac, mfv = o->dv.d.mass_fac;
+    upload_domain(o->X, o->dx);
+    if (vchanged) upload_domain(o->V, o->dv);
+    o->dx.d.mass_fac = mfx;
+    o->dv.d.mass_fac = mfv;
+    for (int k = 0; k < 4; ++k) upload_op(o->ops[k], o->X, o->dx);
+  }
+  if (alloc_epoch() != epoch || masks() != before) {
+    o->self.reset();
+    o->replicas.clear();
+  }
+  return true;
+}
+
 extern "C" sgdg_status sgdg_assemble_1d_factors(sgdg_grid g, const sgdg_problem* p, sgdg_ops* out) {
   API_BEGIN
   require(g && p && out, "null argument");

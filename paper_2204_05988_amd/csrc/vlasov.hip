@@ -366,6 +366,13 @@ void vp_assemble(sgdg_vp p) {
   pr.sigma = nullptr;
   pr.dt = p->dt;
   pr.delta = p->delta;
+  // the field changes only the values of the E-weighted x-factors: rewrite the
+  // existing operator's tables in place (its work buffers, launch tables and
+  // graphs stay); a new operator only if the term structure changed
+  if (p->ops && refresh_fields(p->ops, pr)) {
+    p->assemble_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return;
+  }
   sgdg_ops o = nullptr;
   const sgdg_status st = sgdg_assemble_1d_factors(p->g, &pr, &o);
   if (st != SGDG_OK) throw Error{st, std::string("assembling the transport operator: ") + sgdg_last_error()};

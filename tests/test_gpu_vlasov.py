@@ -100,6 +100,36 @@ def test_fixed_point_strip_matches_oracle(dev, d, pl):
     vp.close()
 
 
+@pytest.mark.parametrize("d,pl", CASES, ids=[f"d{d}_L{p}" for d, p in CASES])
+def test_strip_on_a_used_handle_equals_a_fresh_one(dev, d, pl):
+    """Every fixed-point iteration rewrites the operator's factor tables in place
+    for the new field.  A strip run on a handle whose operator has already been
+    rewritten for other fields (a strip from another initial state) gives, bit for
+    bit, what a new handle gives for the same inputs."""
+    from paper_2204_05988_amd import sgdg
+    w0 = V.landau_workload(d=d, paper_level=pl)
+    P0 = Problem(w0)
+    u0 = torch.tensor(ostrip.initial_coefficients(P0), device=dev)
+    opts = sgdg.default_solve_opts(rtol=1e-11, maxit=300)
+    fresh = sgdg.VlasovPoisson(w0)
+    E0, _ = fresh.field(fresh.density(u0, 1))
+    fa, Ea, sa = fresh.strip(u0, 1, E0, fp_tol=1e-10, solve=opts)
+    fresh.close()
+    used = sgdg.VlasovPoisson(w0)
+    # another state (twice the perturbation, so other fields) on the same grids
+    w1 = V.landau_workload(d=d, paper_level=pl, alpha=2e-2)
+    u1 = torch.tensor(ostrip.initial_coefficients(Problem(w1)), device=dev)
+    E1, _ = used.field(used.density(u1, 1))
+    _, _, s1 = used.strip(u1, 1, E1, fp_tol=1e-10, solve=opts)
+    fb, Eb, sb = used.strip(u0, 1, E0, fp_tol=1e-10, solve=opts)
+    used.close()
+    _say(f"  d={d}: fresh {sa.fp_iters} iterations ({sa.assemble_seconds:.3f}s assembly), "
+         f"used handle {s1.fp_iters} + {sb.fp_iters} ({sb.assemble_seconds:.3f}s)")
+    assert sa.fp_iters == sb.fp_iters
+    assert torch.equal(fa, fb)
+    assert torch.equal(Ea, Eb)
+
+
 def test_landau_damping_on_the_device(dev):
     """36 strips of the 1+1-dimensional Landau problem (paper level 5, 0.5 time
     units per strip) on the device: the field decays at gamma ~ 0.153 and the
