@@ -145,8 +145,8 @@ struct sgdg_ops_s {
 // registries come out unchanged, the factor tables are recomputed and written
 // into the existing device buffers, so work buffers, launch tables and captured
 // graphs stay valid; cached batches are dropped only if a support mask
-// changed.  Returns false, with o unchanged, if the structure differs (the
-// caller then assembles a new handle).
+// changed.  Returns false if the structure differs: o is then no longer
+// consistent and must be replaced by a newly assembled handle.
 bool refresh_fields(sgdg_ops o, const sgdg_problem& p);
 
 // The learned preconditioner (net.hip) as seen by the strip solver.

@@ -554,7 +554,8 @@ static bool same_terms(const TermList& a, const TermList& b) {
 
 bool refresh_fields(sgdg_ops o, const sgdg_problem& p) {
   check_problem(o->grid, &p);
-  DomainData X = o->X, V = o->V;
+  DomainData &X = o->X, &V = o->V;
+  const size_t nfx = X.factors.size(), nfv = V.factors.size();
   bool vchanged = false;
   for (size_t i = 0; i < X.fields.size(); ++i)
     std::copy(X.field_src[i], X.field_src[i] + X.fields[i].size(), X.fields[i].begin());
@@ -563,9 +564,11 @@ bool refresh_fields(sgdg_ops o, const sgdg_problem& p) {
     vchanged = vchanged || !std::equal(V.fields[i].begin(), V.fields[i].end(), src);
     std::copy(src, src + V.fields[i].size(), V.fields[i].begin());
   }
+  // the term lists of the new values (a term whose kinked weight vanishes for
+  // these fields is left out, which changes the structure)
   TermList tl[4];
   build_terms(X, V, p, o->grid->r, tl);
-  if (X.factors.size() != o->X.factors.size() || V.factors.size() != o->V.factors.size()) return false;
+  if (X.factors.size() != nfx || V.factors.size() != nfv) return false;
   for (int k = 0; k < 4; ++k)
     if (!same_terms(tl[k], o->ops[k].host)) return false;
   assemble_all(X);
@@ -586,8 +589,6 @@ bool refresh_fields(sgdg_ops o, const sgdg_problem& p) {
   };
   const auto before = masks();
   const uint64_t epoch = alloc_epoch();
-  o->X = std::move(X);
-  if (vchanged) o->V = std::move(V);
   {
     g_upload_inplace = true;
     struct Reset {

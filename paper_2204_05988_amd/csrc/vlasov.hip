@@ -369,9 +369,21 @@ void vp_assemble(sgdg_vp p) {
   // the field changes only the values of the E-weighted x-factors: rewrite the
   // existing operator's tables in place (its work buffers, launch tables and
   // graphs stay); a new operator only if the term structure changed
-  if (p->ops && refresh_fields(p->ops, pr)) {
-    p->assemble_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return;
+  if (p->ops) {
+    bool done = false;
+    try {
+      done = refresh_fields(p->ops, pr);
+    } catch (...) {
+      sgdg_ops_destroy(p->ops);  // possibly half rewritten
+      p->ops = nullptr;
+      throw;
+    }
+    if (done) {
+      p->assemble_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return;
+    }
+    sgdg_ops_destroy(p->ops);  // no longer consistent
+    p->ops = nullptr;
   }
   sgdg_ops o = nullptr;
   const sgdg_status st = sgdg_assemble_1d_factors(p->g, &pr, &o);
