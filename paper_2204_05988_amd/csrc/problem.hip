@@ -151,14 +151,23 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   d.nbr = upload(dd.nbr, nbr);
   // slot-major copies: entry e of consecutive nodes is contiguous.  off(l) is
   // the start of level l in a block of `stride` elements; K entries per node.
+  // (the host loops below run on all cores: a field refresh repeats them per
+  // fixed-point iteration)
   auto slot_major = [&](auto& dst, const auto& src, size_t nblocks, int64_t stride, int K, auto off) {
     dst.resize(src.size());
     for (size_t bk = 0; bk < nblocks; ++bk)
       for (int l = D.lmin; l <= D.lmax; ++l) {
         const int64_t n = D.L(l).n, base = int64_t(bk) * stride + off(l);
+#pragma omp parallel for if (n >= 4096)
         for (int64_t i = 0; i < n; ++i)
           for (int e = 0; e < K; ++e) dst[base + int64_t(e) * n + i] = src[base + i * K + e];
       }
+  };
+  auto to_f32 = [](const std::vector<double>& a, std::vector<float>& b) {
+    b.resize(a.size());
+    const int64_t n = int64_t(a.size());
+#pragma omp parallel for if (n >= 65536)
+    for (int64_t i = 0; i < n; ++i) b[size_t(i)] = float(a[size_t(i)]);
   };
   auto loff = [&](int l) { return d.lev_off[l - D.lmin]; };
   {
@@ -185,7 +194,7 @@ static void upload_domain(DomainData& D, DomDev& dd) {
       const auto& src = D.values[f][l - D.lmin];
       std::copy(src.begin(), src.end(), vals.begin() + f * o + d.lev_off[l - D.lmin]);
     }
-  for (size_t i = 0; i < vals.size(); ++i) v32[i] = float(vals[i]);
+  to_f32(vals, v32);
   d.vals = upload(dd.vals, vals);
   d.vals32 = upload(dd.vals32, v32);
   {
@@ -197,6 +206,7 @@ static void upload_domain(DomainData& D, DomDev& dd) {
     d.node_stride = no;
     dd.hsup.assign(nf * size_t(no), 0);
     dd.hpartial.assign(nf, 0);
+#pragma omp parallel for schedule(dynamic)
     for (size_t f = 0; f < nf; ++f) {
       uint8_t* sf = dd.hsup.data() + f * no;
       for (int l = D.lmin; l <= D.lmax; ++l) {
@@ -228,8 +238,8 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   {
     std::vector<double> t;
     slot_major(t, vals, nf, o, S, loff);
-    std::vector<float> t32(t.size());
-    for (size_t i = 0; i < t.size(); ++i) t32[i] = float(t[i]);
+    std::vector<float> t32;
+    to_f32(t, t32);
     d.tvals = upload(dd.tvals, t);
     d.tvals32 = upload(dd.tvals32, t32);
   }
@@ -253,8 +263,8 @@ static void upload_domain(DomainData& D, DomDev& dd) {
       const auto& src = D.rvalues[f][l - D.lmin];
       std::copy(src.begin(), src.end(), rv.begin() + f * wo + d.wlev_off[l - D.lmin]);
     }
-  std::vector<float> rv32(rv.size());
-  for (size_t i = 0; i < rv.size(); ++i) rv32[i] = float(rv[i]);
+  std::vector<float> rv32;
+  to_f32(rv, rv32);
   d.rvals = upload(dd.rvals, rv);
   d.rvals32 = upload(dd.rvals32, rv32);
   auto woff = [&](int l) { return d.wlev_off[l - D.lmin]; };
@@ -263,8 +273,8 @@ static void upload_domain(DomainData& D, DomDev& dd) {
   d.twide = upload(dd.twide, tw);
   std::vector<double> trv;
   slot_major(trv, rv, nf, wo, W, woff);
-  std::vector<float> trv32(trv.size());
-  for (size_t i = 0; i < trv.size(); ++i) trv32[i] = float(trv[i]);
+  std::vector<float> trv32;
+  to_f32(trv, trv32);
   d.trvals = upload(dd.trvals, trv);
   d.trvals32 = upload(dd.trvals32, trv32);
   // prolongated stencils (already slot-major per level)
@@ -288,8 +298,8 @@ static void upload_domain(DomainData& D, DomDev& dd) {
       const auto& src = D.pvalues[f][l - D.lmin];
       std::copy(src.begin(), src.end(), pv.begin() + f * pof + d.plev_off[l - D.lmin]);
     }
-  std::vector<float> pv32(pv.size());
-  for (size_t i = 0; i < pv.size(); ++i) pv32[i] = float(pv[i]);
+  std::vector<float> pv32;
+  to_f32(pv, pv32);
   d.pvals = upload(dd.pvals, pv);
   d.pvals32 = upload(dd.pvals32, pv32);
   // slot-pair copies of the slot-major factor tables: [K/2][n][2] per level
@@ -307,11 +317,11 @@ static void upload_domain(DomainData& D, DomDev& dd) {
       for (int l = D.lmin; l <= D.lmax; ++l) {
         const int64_t n = D.L(l).n, sb = int64_t(bk) * stride + off[l - D.lmin];
         const int64_t qb = int64_t(bk) * q + qoff[l - D.lmin];
-        for (int e = 0; e < K; ++e)
-          for (int64_t i = 0; i < n; ++i) dst[qb + ((e >> 1) * n + i) * 2 + (e & 1)] = src[sb + int64_t(e) * n + i];
+#pragma omp parallel for if (n >= 4096)
+        for (int64_t i = 0; i < n; ++i)
+          for (int e = 0; e < K; ++e) dst[qb + ((e >> 1) * n + i) * 2 + (e & 1)] = src[sb + int64_t(e) * n + i];
       }
-    dst32.resize(dst.size());
-    for (size_t i = 0; i < dst.size(); ++i) dst32[i] = float(dst[i]);
+    to_f32(dst, dst32);
   };
   {
     std::vector<double> tq;
