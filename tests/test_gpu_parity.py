@@ -184,7 +184,7 @@ def test_apply_batches_equal_single_vectors(dev, case, B):
 
 
 def test_apply_c2_full_size(dev):
-    """BASELINE workload c2 at its full size (L=7, 620 892 space-time DOFs)."""
+    """The 4D workload c2 at its full size (L=7, 620 892 space-time DOFs)."""
     w, P, ops = _problem("c2", config_c2)
     u = random_vector(P.ndof, 0)[0]
     _say(f"apply parity c2 full size n={P.ndof}")
